@@ -1,0 +1,329 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a library
+routine, a closed form, an invariant, an exact solution or a textbook value.
+Section numbers refer to arXiv:1212.0204.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.stats import norm
+
+import workloads as W
+from oracle import ENONPHYS, Oracle, OracleError
+from tests import exact_riemann as XR
+
+
+def moment_matrix(o):
+    """C of section 4.1: rows w*(1, v_k, |v_k|^2/2), built here from the node
+    list the oracle reports (the node list itself is pinned below)."""
+    v = o.velocities
+    w = o.dv ** o.d
+    rows = [np.ones(o.nv)] + [v[:, a] for a in range(o.d)] + [0.5 * (v ** 2).sum(1)]
+    return w * np.array(rows)
+
+
+def primitives(U, d):
+    rho = U[0]
+    u = U[1:1 + d] / rho
+    theta = (2.0 * U[d + 1] - rho * (u ** 2).sum(0)) / (d * rho)
+    return rho, u, theta
+
+
+# ------------------------------------------------------------- section 3, 4.1
+@pytest.mark.parametrize("d,nv", [(1, 8), (1, 7), (2, 6), (3, 4)])
+def test_velocity_lattice(d, nv):
+    dv = 0.375
+    o = Oracle(d, [4] * d, 0.1, nv, dv)
+    k1 = np.arange(nv) - nv // 2
+    if nv % 2:
+        assert k1[0] == -k1[-1]  # odd: symmetric set
+    else:
+        assert k1[0] == -nv // 2 and k1[-1] == nv // 2 - 1
+    grids = np.meshgrid(*([k1 * dv] * d), indexing="ij")
+    expect = np.stack([g.transpose(list(range(d))[::-1]).reshape(-1) for g in grids], 1)
+    assert np.array_equal(o.velocities, expect)
+    assert o.dt == 0.1 / dv  # dt v_k = k dx
+
+
+@pytest.mark.parametrize("d,nv,dv", [(1, 16, 0.5), (2, 8, 0.75), (3, 6, 1.0)])
+def test_projection_matrix_is_inverse_gram(d, nv, dv):
+    o = Oracle(d, [3] * d, 0.1, nv, dv)
+    C = moment_matrix(o)
+    np.testing.assert_allclose(o.A, np.linalg.inv(C @ C.T), rtol=1e-12, atol=0)
+
+
+def test_maxwellian_matches_normal_pdf():
+    o = Oracle(2, [2, 2], 0.1, 12, 0.5)
+    rho, u, th = 1.7, np.array([0.3, -0.6]), 0.8
+    U = np.array([rho, rho * u[0], rho * u[1], 0.5 * rho * (u @ u) + rho * th])
+    v = o.velocities
+    expect = rho * norm.pdf(v[:, 0], u[0], math.sqrt(th)) * norm.pdf(v[:, 1], u[1], math.sqrt(th))
+    np.testing.assert_allclose(o.maxwellian(U), expect, rtol=1e-13, atol=1e-300)
+
+
+@pytest.mark.parametrize("d,nv,dv", [(1, 12, 0.75), (2, 8, 0.9), (3, 6, 1.1)])
+def test_equilibrium_is_min_norm_correction(d, nv, dv):
+    """eq. (minimMax): E = M + C^T (C C^T)^{-1} (U - C M) is the minimum-norm
+    correction with C E = U; compare with numpy's min-norm least squares."""
+    o = Oracle(d, [2] * d, 0.1, nv, dv)
+    rng = np.random.default_rng(7)
+    for _ in range(3):
+        rho = rng.uniform(0.5, 2.0)
+        u = rng.uniform(-0.5, 0.5, d)
+        th = rng.uniform(0.5, 1.5)
+        U = np.concatenate([[rho], rho * u, [0.5 * rho * (u @ u) + 0.5 * d * rho * th]])
+        M = o.maxwellian(U)
+        E = o.equilibrium(U)
+        C = moment_matrix(o)
+        y = np.linalg.lstsq(C, U - C @ M, rcond=None)[0]  # min-norm solution
+        np.testing.assert_allclose(E, M + y, rtol=0, atol=1e-13 * np.abs(M).max())
+        np.testing.assert_allclose(C @ E, U, rtol=1e-13, atol=1e-14)
+        # the correction is not negligible on these coarse velocity grids
+        assert np.abs(C @ M - U).max() > 1e-8
+
+
+def test_equilibrium_correction_vanishes_with_resolution():
+    """|U - C M| -> 0 as dv -> 0 on a fixed box (the trapezoid rule of a
+    Gaussian), so E -> M (section 4.1 remark on truncation)."""
+    U = np.array([1.0, 0.2, 0.5 * 0.04 + 0.5 * 0.25])  # theta = 1/4
+    errs = []
+    for nv, dv in [(16, 1.0), (32, 0.5), (64, 0.25)]:
+        o = Oracle(1, [2], 0.1, nv, dv)
+        errs.append(np.abs(o.equilibrium(U) - o.maxwellian(U)).max())
+    assert errs[0] > 1e-4 and errs[2] < 1e-12 and errs[1] < errs[0]
+
+
+# ----------------------------------------------------- section 4.2: transport
+@pytest.mark.parametrize("d,n,nv", [(1, (37,), 9), (2, (11, 7), 6), (3, (5, 4, 6), 4)])
+def test_free_transport_is_exact_periodic_shift(d, n, nv):
+    """tau = +inf: lambda = 1, the scheme is the exact transport of the
+    piecewise-constant pieces (sections 4.2, 4.3.1): f^n(j,k) = f^0(j - k n, k)."""
+    o = Oracle(d, n, 0.05, nv, 0.5, tau=math.inf)
+    rng = np.random.default_rng(3)
+    f0 = rng.uniform(0.0, 1.0, (o.nv, o.nc))
+    o.set_f(f0)
+    steps = 3
+    o.step(steps)
+    kint = np.rint(o.velocities / 0.5).astype(int)
+    expect = np.empty_like(f0)
+    shape = tuple(n[::-1])
+    for k in range(o.nv):
+        plane = f0[k].reshape(shape)
+        shift = tuple(int(kint[k, a]) * steps for a in range(d))[::-1]
+        expect[k] = np.roll(plane, shift, axis=tuple(range(d))).reshape(-1)
+    assert np.array_equal(o.f, expect)
+
+
+def test_free_transport_outflow_replicates_boundary():
+    """outflow: pieces entering through a boundary copy the boundary cell's
+    piece of the same velocity (zero gradient); checked one step at a time."""
+    nx, nv = 23, 8
+    o = Oracle(1, (nx,), 0.05, nv, 0.5, bc=(1,), tau=math.inf)
+    rng = np.random.default_rng(5)
+    f = rng.uniform(0.0, 1.0, (nv, nx))
+    o.set_f(f)
+    for _ in range(3):
+        o.step(1)
+        nxt = np.empty_like(f)
+        for k in range(nv):
+            kk = k - nv // 2
+            src = np.clip(np.arange(nx) - kk, 0, nx - 1)
+            nxt[k] = f[k, src]
+        f = nxt
+        assert np.array_equal(o.f, f)
+
+
+# -------------------------------------------------- section 4.2: relaxation
+@pytest.mark.parametrize("tau", [0.05, 0.4, 3.0])
+def test_homogeneous_relaxation_closed_form(tau):
+    """Spatially uniform f: transport is the identity, U_E = U_M, and the
+    scheme reduces to f^n = E + lambda^n (f^0 - E) with U constant."""
+    d, nv, dv = 2, 10, 0.6
+    o = Oracle(d, (4, 3), 0.1, nv, dv, tau=tau)
+    v = o.velocities
+    bump = (np.exp(-((v[:, 0] - 1.0) ** 2 + v[:, 1] ** 2)) +
+            0.5 * np.exp(-((v[:, 0] + 0.7) ** 2 + (v[:, 1] - 0.4) ** 2) / 0.5))
+    f0 = np.repeat(bump[:, None], o.nc, axis=1)
+    o.set_f(f0)
+    C = moment_matrix(o)
+    U0 = C @ bump
+    rho, u, th = primitives(U0[:, None], d)
+    M = rho[0] * norm.pdf(v[:, 0], u[0, 0], math.sqrt(th[0])) * \
+        norm.pdf(v[:, 1], u[1, 0], math.sqrt(th[0]))
+    E = M + np.linalg.lstsq(C, U0 - C @ M, rcond=None)[0]
+    lam = math.exp(-o.dt / tau)
+    for n in range(1, 5):
+        o.step(1)
+        expect = E + lam ** n * (bump - E)
+        np.testing.assert_allclose(o.f, np.repeat(expect[:, None], o.nc, 1),
+                                   rtol=0, atol=1e-13)
+        np.testing.assert_allclose(o.U, np.repeat(U0[:, None], o.nc, 1),
+                                   rtol=1e-13, atol=1e-14)
+
+
+# --------------------------------------------------------- invariants (4.2)
+@pytest.mark.parametrize("tau", [0.0, 1e-3, 1e-2, 1.0, math.inf])
+@pytest.mark.parametrize("d", [1, 2])
+def test_periodic_conservation_and_moment_consistency(d, tau):
+    """Relaxation and exact transport conserve (section 4.2 remark); the HOFKS
+    correction gives P(f^{n+1}) = U^{n+1} (eq. mom with eq. minim_full)."""
+    if d == 1:
+        n, nv, dv = (48,), 24, 0.5
+        rho, u, th = W.sod_tube(48, left=(1.0, 0.2, 1.0), right=(0.5, -0.1, 0.6))
+    else:
+        n, nv, dv = (12, 10), 12, 0.75
+        rho, u, th = W.perturbed_gas(12, 2, 0.2, 0.1, 3, (11, 12))
+        rho, th, u = rho[:120], th[:120], u[:, :120]
+    o = Oracle(d, n, 1.0 / n[0], nv, dv, tau=tau)
+    o.init_macro(rho, u, th)
+    tot0 = o.U.sum(1)
+    o.step(6)
+    U = o.U
+    scale = np.abs(o.U).max(1)
+    np.testing.assert_allclose(U.sum(1), tot0, rtol=0, atol=1e-13 * scale.max() * o.nc)
+    np.testing.assert_allclose(moment_matrix(o) @ o.f, U, rtol=0, atol=1e-12 * scale.max())
+
+
+def test_fks_scheme_moments_are_transported_moments():
+    """scheme 1 (no Euler coupling): U_E := U_M, so the correction vanishes."""
+    rho, u, th = W.sod_tube(40)
+    o = Oracle(1, (40,), 1 / 40, 16, 0.5, bc=(1,), tau=1e-2, scheme=1)
+    o.init_macro(rho, u, th)
+    o.step(2)
+    assert np.abs(o.delta).max() == 0.0
+    np.testing.assert_allclose(moment_matrix(o) @ o.f, o.U, rtol=0, atol=1e-13)
+
+
+# --------------------------------------------------- section 4.3.2: MUSCL
+def test_muscl_uniform_state_is_steady():
+    o = Oracle(2, (6, 5), 0.1, 8, 0.5)
+    U = np.tile(np.array([[1.3], [0.2], [-0.4], [2.0]]), (1, 30))
+    Un, ns = o.muscl(U, 0.05)
+    np.testing.assert_allclose(Un, U, rtol=1e-15, atol=1e-15)
+
+
+def test_muscl_smooth_advection_second_order_in_space():
+    """uniform velocity and pressure: the Euler system advects rho.  Eq.
+    (discmom) is a forward-Euler step, first order in time; with dt ~ dx^2
+    (as for Table 1 of section 5.2) the MUSCL of section 4.3.2 shows its
+    second spatial order on smooth data (L1 rate ~2)."""
+    errs = []
+    for nx in (40, 80, 160):
+        x = (np.arange(nx) + 0.5) / nx
+        rho = 1.0 + 0.2 * np.sin(2 * np.pi * x)
+        uu, p = 1.0, 1.0
+        o = Oracle(1, (nx,), 1.0 / nx, 8, 0.5)
+        U = np.stack([rho, rho * uu, 0.5 * rho * uu ** 2 + p / (3.0 - 1.0)])  # gamma = 3
+        t = 0.1
+        nsteps = int(math.ceil(t / (0.5 / nx ** 2)))
+        for _ in range(nsteps):
+            U, ns = o.muscl(U, t / nsteps)
+            assert ns == 1
+        ex = 1.0 + 0.2 * np.sin(2 * np.pi * (x - uu * t))
+        errs.append(np.abs(U[0] - ex).mean())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates.min() > 1.7, (errs, rates)
+
+
+def test_muscl_forward_euler_is_first_order_at_fixed_cfl():
+    """the same problem at the scheme's own CFL 1/2 (eq. Time2): the time
+    error dominates and the rate drops to ~1."""
+    errs = []
+    for nx in (50, 100, 200):
+        x = (np.arange(nx) + 0.5) / nx
+        rho = 1.0 + 0.2 * np.sin(2 * np.pi * x)
+        o = Oracle(1, (nx,), 1.0 / nx, 8, 0.5)
+        U = np.stack([rho, rho, 0.5 * rho + 0.5])
+        Un, ns = o.muscl(U, 0.25)
+        errs.append(np.abs(Un[0] - (1.0 + 0.2 * np.sin(2 * np.pi * (x - 0.25)))).mean())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert 0.8 < rates.min() and rates.max() < 1.5, (errs, rates)
+
+
+def test_tau_zero_sod_converges_to_exact_riemann():
+    """tau = 0: HOFKS returns the MUSCL Euler solution (Theorem 1 discussion,
+    section 5.3 remark); the 1D-1V gas has gamma = (d+2)/d = 3 (eq. sys1).
+    The L1 density error against the exact Riemann solution decreases under
+    refinement at a first-order-like rate (shock-dominated)."""
+    left, right = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    errs = []
+    for nx in (100, 200, 400):
+        rho, u, th = W.sod_tube(nx)
+        o = Oracle(1, (nx,), 1.0 / nx, 16, 0.25 * 400 / nx, bc=(1,), tau=0.0)
+        o.init_macro(rho, u, th)
+        t_end = 0.16
+        steps = int(round(t_end / o.dt))
+        assert abs(steps * o.dt - t_end) < 1e-12
+        o.step(steps)
+        x = (np.arange(nx) + 0.5) / nx
+        rex, _, _ = XR.solution(left, right, 3.0, x, t_end)
+        errs.append(np.abs(o.U[0] - rex).mean())
+    assert errs[0] > errs[1] > errs[2]
+    assert math.log2(errs[0] / errs[2]) / 2 > 0.5, errs
+    assert errs[2] < 6e-3
+
+
+def test_exact_riemann_solver_textbook_sod():
+    """the exact solver itself: Sod's problem at gamma = 1.4 has the textbook
+    star state p* = 0.30313, u* = 0.92745 (5 digits)."""
+    ps, us = XR.star_state((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4)
+    assert abs(ps - 0.30313) < 5e-6 and abs(us - 0.92745) < 5e-6
+
+
+def test_mirror_symmetry_odd_velocity_set():
+    """odd n_v gives a symmetric velocity set; mirrored data stay mirrored
+    (pins the orientation of the shift, fluxes and slopes)."""
+    nx, nv = 60, 15
+    x = (np.arange(nx) + 0.5) / nx
+    rho = np.where(np.abs(x - 0.5) < 0.2, 1.0, 0.3) + 0.1 * x * (1 - x)
+    u = (0.3 * np.sin(2 * np.pi * x))[None, :]  # odd about the centre
+    th = np.where(np.abs(x - 0.5) < 0.2, 1.0, 0.7)
+    o = Oracle(1, (nx,), 1 / nx, nv, 8.0 / nv, bc=(1,), tau=3e-3)
+    o.init_macro(rho, u, th)
+    o.step(5)
+    U = o.U
+    np.testing.assert_allclose(U[0], U[0][::-1], rtol=1e-12)
+    np.testing.assert_allclose(U[1], -U[1][::-1], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(U[2], U[2][::-1], rtol=1e-12)
+
+
+# ------------------------------------------------------- Theorem 1 (4.3.1)
+def test_theorem1_delta_is_second_order_in_dt():
+    """From smooth equilibrium data, U_E - U_M = O(dt^2) (Theorem 1).  With
+    dv fixed, dt = dx/dv, so halving dx should divide max|delta| by ~4.  A
+    wrong gamma or a wrong flux would leave an O(dt) mismatch."""
+    res = []
+    for nx in (256, 512, 1024):
+        x = (np.arange(nx) + 0.5) / nx
+        rho = 1.0 + 0.2 * np.sin(2 * np.pi * x)
+        u = (0.1 + 0.1 * np.cos(2 * np.pi * x))[None, :]
+        th = 1.0 + 0.1 * np.sin(4 * np.pi * x)
+        o = Oracle(1, (nx,), 1 / nx, 48, 0.25, tau=0.0)
+        o.init_macro(rho, u, th)
+        o.step(1)
+        res.append(np.abs(o.delta).max())
+    rates = np.log2(np.array(res[:-1]) / np.array(res[1:]))
+    assert rates.min() > 1.85, (res, rates)
+
+
+# ------------------------------------------------------------ failure modes
+def test_nonphysical_state_is_reported():
+    o = Oracle(1, (4,), 0.25, 8, 0.5, tau=1e-2)
+    with pytest.raises(OracleError) as e:
+        o.init_macro(np.array([1.0, 0.0, 1.0, 1.0]), np.zeros((1, 4)), np.ones(4))
+    assert e.value.status == ENONPHYS
+    o.init_macro(np.ones(4), np.zeros((1, 4)), np.ones(4))
+    o.set_f(np.full((8, 4), np.nan))
+    with pytest.raises(OracleError):
+        o.step(1)
+
+
+def test_bad_descriptors_rejected():
+    with pytest.raises(OracleError):
+        Oracle(4, (2,), 0.1, 8, 0.5)
+    with pytest.raises(OracleError):
+        Oracle(1, (2,), 0.1, 1, 0.5)
+    with pytest.raises(OracleError):
+        Oracle(1, (2,), 0.1, 8, 0.5, tau=-1.0)

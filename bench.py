@@ -1,0 +1,156 @@
+"""Throughput of the HOFKS hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--forms a,b]
+
+Primary workload (``value``): the 2D-2V perturbed gas, 256^2 cells x 32^2
+velocities, plain FP64, tau = 1e-3, periodic; a step is one HOFKS time step
+(Euler sub-steps, relaxation + shift + moment sums, per-cell update).  The
+timed region starts with the state resident in HBM.  ``value`` counts cell-
+velocity updates per second.  The roofline object refers to the kinetic
+kernel, whose algorithmic traffic is one read and one write of every piece
+per step (16 B per cell-velocity in FP64, 8 B in FP32), timed with hipEvents
+on the library's stream.  Extra forms (FP32 precision form, ...) are reported
+under ``forms``.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "cell·velocity updates/s and % HBM peak, FP32/batched/MLP vs plain FP64"
+
+
+def run_solver(wl, steps, warmup, precision, scheme=0):
+    import torch
+    import workloads as W
+    from paper_1212_0204_amd import Solver
+
+    fields = W.initial_fields(wl)
+    s = Solver(wl.d, wl.n, wl.dx, wl.nv, wl.dv, bc=wl.bc, precision=precision, scheme=scheme,
+               tau=wl.tau)
+    if warmup:
+        s.set_state_macro(*fields)
+        s.step(warmup)
+        s.sync()
+    s.set_state_macro(*fields)
+    s.kernel_timing(enable=True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kms, cnt = s.kernel_timing(enable=False)
+    s.sync()  # raises on a non-physical state or sub-step overflow
+    substeps, _ = s.counters()
+    cv = wl.cv * steps
+    bpcv = 8 if precision else 16
+    kin_ms = kms[1] / max(cnt[1], 1)
+    achieved = bpcv * wl.cv / (kin_ms * 1e-3) / 1e9
+    out = {
+        "cv_per_s": cv / (ms * 1e-3),
+        "ms_per_step": ms / steps,
+        "kernel_ms_per_step": {"euler": kms[0] / max(cnt[0], 1), "kinetic": kin_ms,
+                               "cell_update": kms[2] / max(cnt[2], 1)},
+        "euler_substeps_last_step": substeps,
+        "kinetic_GBps": achieved,
+        "kinetic_hbm_frac": achieved / HBM_PEAK_GBPS,
+        "step_hbm_frac": bpcv * cv / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+    }
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(wl, budget_s=12.0):
+    """the oracle on the host cores, on the same workload: as many whole steps
+    of the full grid as fit in ~budget_s (at least one)."""
+    import workloads as W
+    from oracle import Oracle
+
+    o = Oracle(wl.d, wl.n, wl.dx, wl.nv, wl.dv, bc=wl.bc, tau=wl.tau)
+    o.init_macro(*W.initial_fields(wl))
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        o.step(1)
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": wl.cv * n / el, "unit": "cell-velocity updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{wl.name}: {n} full steps of the {wl.nc}-cell x {wl.nvel}-velocity grid "
+                      f"from the initial state ({el:.1f} s, OpenMP over cells, plain FP64 C)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp32_3d,fp64_3d")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    wl = W.GAS_2D
+    prim = run_solver(wl, args.steps, args.warmup, precision=0)
+    forms = {}
+    for name in [f for f in args.forms.split(",") if f]:
+        if name == "fp32_3d":
+            forms[name] = dict(workload=W.GAS_3D.name, **run_solver(W.GAS_3D, W.GAS_3D.steps, 2, 1))
+        elif name == "fp64_3d":
+            forms[name] = dict(workload=W.GAS_3D.name.replace("fp32", "fp64"),
+                               **run_solver(W.GAS_3D, W.GAS_3D.steps, 2, 0))
+    if "fp32_3d" in forms and "fp64_3d" in forms:
+        forms["fp32_3d"]["speedup_vs_fp64_same_workload"] = (
+            forms["fp32_3d"]["cv_per_s"] / forms["fp64_3d"]["cv_per_s"])
+    for f in forms.values():
+        f["speedup_vs_plain_fp64_2d"] = f["cv_per_s"] / prim["cv_per_s"]
+
+    line = {
+        "metric": METRIC,
+        "value": prim["cv_per_s"],
+        "unit": "cell-velocity updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": prim["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "cells": list(wl.n), "velocities_per_axis": wl.nv,
+                   "dv": wl.dv, "tau": wl.tau, "bc": "periodic", "hbm_step_frac": prim["step_hbm_frac"]},
+        "roofline": {"bound": "hbm", "achieved": prim["kinetic_GBps"], "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": prim["kinetic_hbm_frac"], "traffic": None,
+                     "kernel": "k_kinetic<2,double>",
+                     "algorithmic_bytes_per_launch": 16 * wl.cv},
+        "kernel_ms_per_step": prim["kernel_ms_per_step"],
+        "forms": forms,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

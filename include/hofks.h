@@ -1,0 +1,124 @@
+/*
+ * hofks.h -- C ABI of the MI355X (gfx950) library for the High Order Fast
+ * Kinetic Scheme (HOFKS) of Dimarco & Loubere, arXiv:1212.0204.
+ *
+ * One time step t^n -> t^{n+1} of the discrete-velocity BGK model (sections 3
+ * and 4.3.1 of the paper):
+ *   relaxation  f* = lambda f^n + (1 - lambda) E[U^n],  lambda = exp(-dt/tau)
+ *   transport   f_K(x_j, v_k) = f*(x_j - v_k dt), an exact shift of the pieces
+ *   moments     U_* = P(T(lambda f^n)),  U_M = P(T((1 - lambda) E[U^n]))  (eq. UK)
+ *   Euler       U_E = (1 - lambda) MUSCL_dt(U^n)             (section 4.3.2)
+ *   correction  f^{n+1} = f_K + C^T (C C^T)^{-1} (U_E - U_M)  (eq. minim_full)
+ *               U^{n+1} = U_* + U_E                           (eq. mom)
+ * E[U] is the conservative Maxwellian of eq. (minimMax).
+ *
+ * Lattice.  Velocity nodes v_k = k dv with k in {-n/2 .. n/2-1} per axis for
+ * even n and {-(n-1)/2 .. (n-1)/2} for odd n; the library sets dt = dx / dv, so
+ * v_k dt = k dx and transport moves every piece by exactly k cells.
+ *
+ * Layouts (host arrays).  Cells are x-fastest: j = (jz*Ny + jy)*Nx + jx.
+ * Moments U are component-major, U[r*Nc + j] with r = 0 (rho), 1..d (rho u),
+ * d+1 (E = |u|^2 rho/2 + d rho theta/2).  The distribution read by
+ * hofks_read_f is velocity-plane major, f[k*Nc + j], velocity nodes x-fastest:
+ * k = (iz*n + iy)*n + ix.
+ *
+ * Ownership.  The library never allocates device memory: the caller passes a
+ * device workspace of at least hofks_workspace_size() bytes (for example a
+ * torch uint8 tensor) and a HIP stream; both must outlive the context.  Host
+ * pointers belong to the caller and are only read/written during the call.
+ *
+ * Errors.  Every call returns a status; nothing crosses the ABI as an
+ * exception.  Kernels record non-physical states (rho <= 0, theta <= 0 or
+ * non-finite moments) and sub-step overflow in a device flag that is sticky:
+ * it is reported by the next synchronising call (hofks_read_*, hofks_sync).
+ * hofks_last_error() gives a message for the last failing call.  A context is
+ * not thread-safe.
+ */
+#ifndef HOFKS_H
+#define HOFKS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hofks_ctx hofks_ctx;
+
+typedef enum {
+  HOFKS_OK = 0,
+  HOFKS_EINVAL = -1,   /* bad argument or descriptor                          */
+  HOFKS_ESIZE = -2,    /* workspace or host buffer too small                  */
+  HOFKS_EDEVICE = -3,  /* a HIP runtime call failed                           */
+  HOFKS_ENONPHYS = -4, /* rho <= 0, theta <= 0 or non-finite moments were met */
+  HOFKS_ESTATE = -5    /* call out of order, or Euler sub-step cap exceeded   */
+} hofks_status;
+
+typedef struct {
+  int dim;          /* d in {1,2,3}: space and velocity dimension (section 2) */
+  int n_cells[3];   /* N_x, N_y, N_z; unused axes are ignored                  */
+  double dx;        /* cell size, the same on every axis (section 4)          */
+  int n_vel;        /* velocity nodes per axis, >= 2                          */
+  double dv;        /* velocity step; dt = dx / dv                            */
+  int bc[3];        /* per axis: 0 periodic, 1 outflow (zero gradient)        */
+  int precision;    /* 0: FP64 pieces; 1: FP32 pieces, FP64 compensated sums  */
+  int scheme;       /* 0 HOFKS; 1 FKS (U_E := U_M); 2 HOFKS with phi == 1     */
+} hofks_grid_desc;
+
+/* Bytes of device workspace a context with this descriptor needs. */
+hofks_status hofks_workspace_size(const hofks_grid_desc *desc, size_t *bytes);
+
+/* Create a context on the current HIP device.  dev_ws: device pointer to at
+ * least hofks_workspace_size() bytes, 256-byte aligned; hip_stream: the
+ * hipStream_t every kernel of this context is launched on (0 = null stream). */
+hofks_status hofks_create(const hofks_grid_desc *desc, void *dev_ws,
+                          size_t ws_bytes, void *hip_stream, hofks_ctx **out);
+
+/* Relaxation time tau of eq. (B): tau > 0, tau = +INF (free transport,
+ * lambda = 1) or tau = 0 (lambda = 0).  Takes effect at the next step. */
+hofks_status hofks_set_tau(hofks_ctx *ctx, double tau);
+
+/* Initial data (section 4.2): U^0 from host arrays rho[Nc], u[d*Nc]
+ * (component-major), theta[Nc]; f^0 = E[U^0].  Synchronous. */
+hofks_status hofks_set_state_macro(hofks_ctx *ctx, const double *rho,
+                                   const double *u, const double *theta);
+
+/* Arbitrary initial distribution f^0 (layout f[k*Nc + j], FP64 host array of
+ * Nv*Nc values); U^0 = P(f^0), eq. (DM).  Synchronous. */
+hofks_status hofks_set_state_f(hofks_ctx *ctx, const double *f, size_t bytes);
+
+/* Advance n_steps >= 0 time steps; asynchronous on the context's stream. */
+hofks_status hofks_step(hofks_ctx *ctx, int n_steps);
+
+/* Wait for the stream and report the sticky device flag. */
+hofks_status hofks_sync(hofks_ctx *ctx);
+
+/* Copy U^n to host U[(d+2)*Nc] (layout above).  Synchronous. */
+hofks_status hofks_read_moments(hofks_ctx *ctx, double *U);
+
+/* Copy f^n to host (layout above) as FP64 values; bytes >= 8*Nv*Nc.
+ * Synchronous.  Uses the idle half of the piece buffers as staging. */
+hofks_status hofks_read_f(hofks_ctx *ctx, double *f, size_t bytes);
+
+/* Number of Euler sub-steps of the last completed step (0 if none ran) and
+ * the steps taken so far.  Synchronous. */
+hofks_status hofks_read_counters(hofks_ctx *ctx, int *substeps, long *steps);
+
+/* Per-kernel timing with hipEvents recorded on the context's stream around
+ * each launch group of hofks_step: group 0 = the Euler sub-steps, 1 = the
+ * kinetic kernel (relaxation, shift, moment sums), 2 = the per-cell update.
+ * If ms/launches are non-null, synchronise and return the summed elapsed
+ * milliseconds and the launch counts of each group since the last call, then
+ * clear them; enable != 0 keeps recording for the following steps. */
+hofks_status hofks_kernel_timing(hofks_ctx *ctx, int enable, double ms[3],
+                                 int launches[3]);
+
+double hofks_dt(const hofks_ctx *ctx);
+const char *hofks_last_error(const hofks_ctx *ctx);
+void hofks_destroy(hofks_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOFKS_H */

@@ -1,0 +1,63 @@
+"""ctypes declarations of the C ABI in ``include/hofks.h``.
+
+Loading fails loudly when ``libhofks.so`` has not been built: there is no
+fallback implementation.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhofks.so")
+
+OK, EINVAL, ESIZE, EDEVICE, ENONPHYS, ESTATE = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "HOFKS_OK", -1: "HOFKS_EINVAL", -2: "HOFKS_ESIZE", -3: "HOFKS_EDEVICE",
+                -4: "HOFKS_ENONPHYS", -5: "HOFKS_ESTATE"}
+
+# every symbol include/hofks.h declares
+SYMBOLS = [
+    "hofks_workspace_size", "hofks_create", "hofks_set_tau", "hofks_set_state_macro",
+    "hofks_set_state_f", "hofks_step", "hofks_sync", "hofks_read_moments", "hofks_read_f",
+    "hofks_read_counters", "hofks_kernel_timing", "hofks_dt", "hofks_last_error", "hofks_destroy",
+]
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_cells", ctypes.c_int * 3), ("dx", ctypes.c_double),
+                ("n_vel", ctypes.c_int), ("dv", ctypes.c_double), ("bc", ctypes.c_int * 3),
+                ("precision", ctypes.c_int), ("scheme", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1212_0204_amd.build` "
+            "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    dp = P(ctypes.c_double)
+    L.hofks_workspace_size.argtypes = [P(GridDesc), P(sz)]
+    L.hofks_create.argtypes = [P(GridDesc), vp, sz, vp, P(vp)]
+    L.hofks_set_tau.argtypes = [vp, d]
+    L.hofks_set_state_macro.argtypes = [vp, dp, dp, dp]
+    L.hofks_set_state_f.argtypes = [vp, dp, sz]
+    L.hofks_step.argtypes = [vp, i]
+    L.hofks_sync.argtypes = [vp]
+    L.hofks_read_moments.argtypes = [vp, dp]
+    L.hofks_read_f.argtypes = [vp, dp, sz]
+    L.hofks_read_counters.argtypes = [vp, P(i), P(ctypes.c_long)]
+    L.hofks_kernel_timing.argtypes = [vp, i, dp, P(i)]
+    L.hofks_dt.argtypes = [vp]
+    L.hofks_dt.restype = d
+    L.hofks_last_error.argtypes = [vp]
+    L.hofks_last_error.restype = ctypes.c_char_p
+    L.hofks_destroy.argtypes = [vp]
+    L.hofks_destroy.restype = None
+    _lib = L
+    return L

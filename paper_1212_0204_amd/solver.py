@@ -1,0 +1,127 @@
+"""``Solver``: one grid + velocity set on one GPU, through the C ABI.
+
+Argument marshalling only: arrays are handed to the library as host pointers,
+the workspace is a torch uint8 tensor on the current device and kernels run on
+torch's current HIP stream.
+"""
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+class HofksError(RuntimeError):
+    def __init__(self, status, what, msg=""):
+        name = _lib.STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{what}: {name} {msg}".strip())
+        self.status = status
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Solver:
+    """HOFKS on a Cartesian grid of ``n_cells`` (x first) with ``n_vel`` velocity
+    nodes per axis spaced ``dv``; the time step is ``dx / dv``.
+
+    precision: 0 FP64 pieces; 1 FP32 pieces with FP64 compensated moment sums.
+    scheme: 0 HOFKS; 1 FKS (no Euler coupling); 2 HOFKS with phi == 1.
+    bc per axis: 0 periodic, 1 outflow.
+    """
+
+    def __init__(self, dim, n_cells, dx, n_vel, dv, bc=None, precision=0, scheme=0,
+                 tau=math.inf, stream=None):
+        L = _lib.lib()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HOFKS library needs a ROCm GPU")
+        n = (list(n_cells) + [1, 1, 1])[:3]
+        b = (list(bc if bc is not None else [0, 0, 0]) + [0, 0, 0])[:3]
+        self.desc = _lib.GridDesc(dim, (ctypes.c_int * 3)(*n), float(dx), int(n_vel), float(dv),
+                                  (ctypes.c_int * 3)(*b), int(precision), int(scheme))
+        self.d, self.nm = dim, dim + 2
+        self.nc = int(np.prod(n[:dim]))
+        self.nv = int(n_vel) ** dim
+        size = ctypes.c_size_t(0)
+        self._check(L.hofks_workspace_size(ctypes.byref(self.desc), ctypes.byref(size)),
+                    "workspace_size", None)
+        self.workspace_bytes = size.value
+        self.workspace = torch.empty(size.value, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p(0)
+        self._check(L.hofks_create(ctypes.byref(self.desc), ctypes.c_void_p(self.workspace.data_ptr()),
+                                   size.value, ctypes.c_void_p(self.stream.cuda_stream),
+                                   ctypes.byref(h)), "create", None)
+        self._h = h
+        self.set_tau(tau)
+
+    # ------------------------------------------------------------ plumbing
+    def _check(self, st, what, h=-1):
+        if st != 0:
+            msg = ""
+            hh = self._h if h == -1 else h
+            if hh:
+                msg = _lib.lib().hofks_last_error(hh).decode()
+            raise HofksError(st, what, msg)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.lib().hofks_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    # ------------------------------------------------------------ the ABI
+    def set_tau(self, tau):
+        self._check(_lib.lib().hofks_set_tau(self._h, float(tau)), "set_tau")
+
+    def set_state_macro(self, rho, u, theta):
+        rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(self.nc)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(self.d, self.nc)
+        theta = np.ascontiguousarray(theta, dtype=np.float64).reshape(self.nc)
+        self._check(_lib.lib().hofks_set_state_macro(self._h, _dp(rho), _dp(u), _dp(theta)),
+                    "set_state_macro")
+
+    def set_state_f(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.nv, self.nc)
+        self._check(_lib.lib().hofks_set_state_f(self._h, _dp(f), f.nbytes), "set_state_f")
+
+    def step(self, n=1):
+        self._check(_lib.lib().hofks_step(self._h, int(n)), "step")
+
+    def sync(self):
+        self._check(_lib.lib().hofks_sync(self._h), "sync")
+
+    def read_moments(self):
+        U = np.empty((self.nm, self.nc), dtype=np.float64)
+        self._check(_lib.lib().hofks_read_moments(self._h, _dp(U)), "read_moments")
+        return U
+
+    def read_f(self):
+        f = np.empty((self.nv, self.nc), dtype=np.float64)
+        self._check(_lib.lib().hofks_read_f(self._h, _dp(f), f.nbytes), "read_f")
+        return f
+
+    def counters(self):
+        s, n = ctypes.c_int(0), ctypes.c_long(0)
+        self._check(_lib.lib().hofks_read_counters(self._h, ctypes.byref(s), ctypes.byref(n)),
+                    "read_counters")
+        return s.value, n.value
+
+    def kernel_timing(self, enable=True):
+        """(ms[3], launches[3]) of the Euler, kinetic and cell-update groups
+        since the previous call; keeps recording while ``enable``."""
+        ms = np.zeros(3)
+        cnt = (ctypes.c_int * 3)()
+        self._check(_lib.lib().hofks_kernel_timing(self._h, int(enable), _dp(ms), cnt),
+                    "kernel_timing")
+        return ms, list(cnt)
+
+    @property
+    def dt(self):
+        return _lib.lib().hofks_dt(self._h)

@@ -1,0 +1,205 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+The plain FP64 form must match the oracle to 1e-12 normwise per moment (and
+on f); the FP32 precision form to 1e-5 on moments.  Free transport must be
+bit-exact.  Every case prints its name, sizes and seed before running.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Oracle
+from tests.helpers import moment_errors, rel_inf
+
+gpu = pytest.mark.gpu
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def _solver(**kw):
+    from paper_1212_0204_amd import Solver
+    return Solver(**kw)
+
+
+def announce(*a):
+    print("CASE", *a, flush=True)
+
+
+def run_pair(d, n, dx, nv, dv, bc, tau, steps, fields=None, f0=None, precision=0, scheme=0):
+    o = Oracle(d, n, dx, nv, dv, bc=bc, tau=tau, scheme=scheme)
+    s = _solver(dim=d, n_cells=n, dx=dx, n_vel=nv, dv=dv, bc=bc, precision=precision,
+                scheme=scheme, tau=tau)
+    if f0 is not None:
+        o.set_f(f0)
+        s.set_state_f(f0)
+    else:
+        o.init_macro(*fields)
+        s.set_state_macro(*fields)
+    o.step(steps)
+    s.step(steps)
+    return o, s
+
+
+# ------------------------------------------------------------------- FP64
+@gpu
+def test_sod_tube_fp64_full_config():
+    """1D-1V Sod: 200 cells x 64 velocities, tau = 1e-2, 100 steps, outflow."""
+    wl = W.SOD_1D
+    announce("sod1d", wl)
+    o, s = run_pair(1, wl.n, wl.dx, wl.nv, wl.dv, wl.bc, wl.tau, wl.steps, W.initial_fields(wl))
+    err = moment_errors(s.read_moments(), o.U, 1)
+    assert err.max() < TOL64, err
+    assert rel_inf(s.read_f(), o.f) < TOL64
+    assert s.counters()[0] == o.substeps
+
+
+@gpu
+@pytest.mark.parametrize("tau", [0.0, 1e-4, 1e-2, 1.0])
+def test_sod_tube_fp64_tau_sweep(tau):
+    announce("sod1d tau", tau)
+    rho, u, th = W.sod_tube(130)
+    o, s = run_pair(1, (130,), 1 / 130, 24, 0.5, (1,), tau, 12, (rho, u, th))
+    assert moment_errors(s.read_moments(), o.U, 1).max() < TOL64
+    assert rel_inf(s.read_f(), o.f) < TOL64
+
+
+@gpu
+@pytest.mark.parametrize("d,n,nv", [(1, (97,), 16), (2, (70, 37), 10), (3, (23, 9, 11), 6)])
+def test_free_transport_bit_exact(d, n, nv):
+    """tau = +inf: pieces move by exactly k cells per step; bit-exact."""
+    announce("free transport", d, n, nv)
+    rng = np.random.default_rng(100 + d)
+    f0 = rng.uniform(0.0, 1.0, (nv ** d, int(np.prod(n))))
+    o, s = run_pair(d, n, 1.0 / n[0], nv, 0.5, (0,) * d, math.inf, 5, f0=f0)
+    assert np.array_equal(s.read_f(), o.f)
+
+
+@gpu
+@pytest.mark.parametrize("n,bc,tau,scheme", [
+    ((70, 37), (0, 0), 1e-3, 0),     # ragged x tile, several rows
+    ((300, 20), (0, 0), 1e-2, 0),    # two x segments, ragged tail
+    ((48, 40), (1, 1), 5e-3, 0),     # outflow on both axes
+    ((64, 32), (0, 1), 0.0, 0),      # tau = 0: Euler only
+    ((64, 32), (0, 0), 1e-2, 1),     # FKS
+    ((64, 32), (0, 0), 1e-2, 2),     # unlimited
+])
+def test_2d_fp64(n, bc, tau, scheme):
+    announce("2d fp64", n, bc, tau, scheme)
+    rho, u, th = W.perturbed_gas(max(n), 2, 0.2, 0.1, 4, (21, 22))
+    nn = max(n)
+    rho = rho.reshape(nn, nn)[:n[1], :n[0]].reshape(-1)
+    th = th.reshape(nn, nn)[:n[1], :n[0]].reshape(-1)
+    u = 0.1 * np.stack([np.sin(np.linspace(0, 6, n[0] * n[1])), np.cos(np.linspace(0, 5, n[0] * n[1]))])
+    o, s = run_pair(2, n, 1.0 / n[0], 16, 0.5, bc, tau, 8, (rho, u, th), scheme=scheme)
+    assert moment_errors(s.read_moments(), o.U, 2).max() < TOL64
+    assert rel_inf(s.read_f(), o.f) < TOL64
+    if scheme != 1 and tau != math.inf:
+        assert s.counters()[0] == o.substeps
+
+
+@gpu
+def test_3d_fp64():
+    announce("3d fp64 (23, 9, 11) x 8^3")
+    n = (23, 9, 11)
+    rng = np.random.default_rng(31)
+    nc = int(np.prod(n))
+    rho = 1.0 + 0.2 * rng.uniform(-1, 1, nc)
+    th = 1.0 + 0.2 * rng.uniform(-1, 1, nc)
+    u = 0.2 * rng.uniform(-1, 1, (3, nc))
+    o, s = run_pair(3, n, 1.0 / 23, 8, 0.75, (0, 1, 0), 1e-2, 4, (rho, u, th))
+    assert moment_errors(s.read_moments(), o.U, 3).max() < TOL64
+    assert rel_inf(s.read_f(), o.f) < TOL64
+
+
+@gpu
+def test_gas2d_full_size_three_steps():
+    """the 256^2 x 32^2 perturbed-gas workload at full size, 3 steps"""
+    wl = W.GAS_2D
+    announce("gas2d full", wl)
+    o, s = run_pair(2, wl.n, wl.dx, wl.nv, wl.dv, wl.bc, wl.tau, 3, W.initial_fields(wl))
+    assert moment_errors(s.read_moments(), o.U, 2).max() < TOL64
+    f = s.read_f()
+    fo = o.f
+    assert rel_inf(f, fo) < TOL64
+
+
+@gpu
+def test_gas2d_full_size_conservation_200_steps():
+    """periodic conservation of mass, momentum and energy over the whole run"""
+    wl = W.GAS_2D
+    announce("gas2d conservation", wl)
+    s = _solver(dim=2, n_cells=wl.n, dx=wl.dx, n_vel=wl.nv, dv=wl.dv, bc=wl.bc, tau=wl.tau)
+    s.set_state_macro(*W.initial_fields(wl))
+    U0 = s.read_moments()
+    s.step(wl.steps)
+    U = s.read_moments()
+    tot0, tot = U0.sum(1), U.sum(1)
+    scale = np.abs(U0).max(1) * U0.shape[1]
+    assert (np.abs(tot - tot0) / scale).max() < 1e-13
+
+
+# ------------------------------------------------------------------- FP32
+@gpu
+@pytest.mark.parametrize("d,n,nv,dv,tau", [(2, (70, 37), 16, 0.5, 1e-3), (3, (20, 12, 10), 12, 0.5, 1e-3),
+                                           (1, (200,), 64, 0.25, 1e-2)])
+def test_precision_form_moments(d, n, nv, dv, tau):
+    announce("fp32", d, n, nv, tau)
+    nc = int(np.prod(n))
+    if d == 1:
+        fields = W.sod_tube(n[0])
+        bc = (1,)
+    else:
+        rng = np.random.default_rng(41)
+        fields = (1.0 + 0.1 * rng.uniform(-1, 1, nc), 0.05 * rng.uniform(-1, 1, (d, nc)),
+                  1.0 + 0.1 * rng.uniform(-1, 1, nc))
+        bc = (0,) * d
+    o, s = run_pair(d, n, 1.0 / n[0], nv, dv, bc, tau, 10, fields, precision=1)
+    err = moment_errors(s.read_moments(), o.U, d)
+    print("fp32 moment errors", err)
+    assert err.max() < TOL32, err
+
+
+# ----------------------------------------------------------- error paths
+@gpu
+def test_nonphysical_state_is_reported():
+    from paper_1212_0204_amd import HofksError
+    announce("nonphysical")
+    s = _solver(dim=1, n_cells=(64,), dx=1 / 64, n_vel=8, dv=0.5, bc=(0,), tau=1e-2)
+    with pytest.raises(HofksError) as e:
+        s.set_state_macro(np.r_[np.ones(63), -1.0], np.zeros((1, 64)), np.ones(64))
+    assert e.value.status == -4
+    f = np.full((8, 64), 0.1)
+    f[3, 5] = np.nan
+    s.set_state_f(f)
+    s.step(1)
+    with pytest.raises(HofksError) as e:
+        s.read_moments()
+    assert e.value.status == -4
+
+
+@gpu
+def test_step_before_state_is_rejected():
+    from paper_1212_0204_amd import HofksError
+    s = _solver(dim=1, n_cells=(64,), dx=1 / 64, n_vel=8, dv=0.5, bc=(0,), tau=1e-2)
+    with pytest.raises(HofksError) as e:
+        s.step(1)
+    assert e.value.status == -5
+
+
+@gpu
+def test_tau_change_mid_run_matches_oracle():
+    announce("tau change")
+    rho, u, th = W.sod_tube(96)
+    o = Oracle(1, (96,), 1 / 96, 16, 0.5, bc=(1,), tau=1e-2)
+    s = _solver(dim=1, n_cells=(96,), dx=1 / 96, n_vel=16, dv=0.5, bc=(1,), tau=1e-2)
+    o.init_macro(rho, u, th)
+    s.set_state_macro(rho, u, th)
+    for tau in (1e-2, 1e-3, math.inf, 0.0, 1e-1):
+        o.set_tau(tau)
+        s.set_tau(tau)
+        o.step(3)
+        s.step(3)
+    assert moment_errors(s.read_moments(), o.U, 1).max() < TOL64
+    assert rel_inf(s.read_f(), o.f) < TOL64

@@ -29,10 +29,12 @@ struct Plan {
   Mat A;
   int prec;
   size_t tsize;  // bytes per stored piece
-  int TX, TR, nseg, nrowgrp, nchunk, nvr;
+  int TX, TR, nseg, nrowgrp, nchunk, nvr, GE;
   size_t lds;
+  int RS;  // record stride (values)
   // workspace offsets (bytes)
-  size_t off_g[2], off_U, off_UE[2], off_rec, off_recT, off_cf, off_part, off_slots, off_flag;
+  size_t off_g[2], off_U[2], off_UE[2], off_rec[2], off_vt, off_cf, off_part, off_slots,
+      off_tiles, off_flag;
   size_t total;
 };
 
@@ -70,6 +72,11 @@ int fmt_err(char* buf, const char* f, ...) {
   vsnprintf(buf, 512, f, ap);
   va_end(ap);
   return 0;
+}
+
+int rec_stride_rt(int d, int prec) {
+  if (prec) return d == 1 ? rec_stride<1, float>() : d == 2 ? rec_stride<2, float>() : rec_stride<3, float>();
+  return d == 1 ? rec_stride<1, double>() : d == 2 ? rec_stride<2, double>() : rec_stride<3, double>();
 }
 
 hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
@@ -148,7 +155,16 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
   const long base = (long)P->nseg * P->nrowgrp;
   long nch = (2048 + base - 1) / base;
   P->nchunk = (int)std::max(1L, std::min<long>(nch, P->nvr));
-  P->lds = (size_t)P->TR * P->R * (P->TX + G.nv1 - 1) * P->tsize;
+  // Euler group: at most one block per compute unit (so that the group is
+  // co-resident whatever else is running), grid-strided over cells
+  int ncu = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      ncu < 1)
+    ncu = 256;
+  P->GE = (int)std::min<long>(std::min(256, ncu), ((long)G.nc + 255) / 256);
+  P->RS = rec_stride_rt(d, P->prec);
+  P->lds = (size_t)P->TR * P->RS * (P->TX + G.nv1 - 1) * P->tsize;
   if (P->lds > 65536) return fmt_err(err, "velocity grid too wide for the LDS tile"), HOFKS_EINVAL;
 
   size_t off = 0;
@@ -158,22 +174,28 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
   off = align256(off + gbytes);
   P->off_g[1] = off;
   off = align256(off + gbytes);
-  P->off_U = off;
+  P->off_U[0] = off;
+  off = align256(off + ubytes);
+  P->off_U[1] = off;
   off = align256(off + ubytes);
   P->off_UE[0] = off;
   off = align256(off + ubytes);
   P->off_UE[1] = off;
   off = align256(off + ubytes);
-  P->off_rec = off;
-  off = align256(off + (size_t)P->R * G.nc * sizeof(double));
-  P->off_recT = off;
-  if (P->prec) off = align256(off + (size_t)P->R * G.nc * sizeof(float));
+  P->off_rec[0] = off;
+  off = align256(off + (size_t)P->RS * G.nc * P->tsize);
+  P->off_rec[1] = off;
+  off = align256(off + (size_t)P->RS * G.nc * P->tsize);
+  P->off_vt = off;
+  off = align256(off + (size_t)G.nv1 * sizeof(VelNode));
   P->off_cf = off;
   off = align256(off + ubytes);
   P->off_part = off;
   off = align256(off + (size_t)P->nchunk * 2 * nm * G.nc * sizeof(double));
   P->off_slots = off;
-  off = align256(off + 2 * (SMAX + 1) * SLOT_STRIDE * sizeof(double));
+  off = align256(off + 3 * (size_t)SET_D * sizeof(double));
+  P->off_tiles = off;
+  off = align256(off + (size_t)P->nseg * P->nrowgrp * sizeof(int));
   P->off_flag = off;
   off = align256(off + 64);
   P->total = off;
@@ -188,9 +210,11 @@ struct hofks_ctx {
   hipStream_t stream;
   unsigned char* ws;
   void* g[2];
-  int cur;
-  double *U, *UE[2], *rec, *cf, *part, *slots;
-  void* recT;
+  int cur;                 // piece buffer holding f^n
+  double *U[2], *UE[2], *cf, *part, *slots;
+  void* rec[2];
+  VelNode* vt;
+  int* tiles;
   int* flag;
   double tau;
   int s_cap;
@@ -211,19 +235,20 @@ hofks_status hip_fail(hofks_ctx* c, hipError_t e, const char* what) {
   return HOFKS_EDEVICE;
 }
 
-#define HIPCHK(c, call)                                   \
-  do {                                                    \
-    hipError_t e_ = (call);                               \
+#define HIPCHK(c, call)                                    \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
     if (e_ != hipSuccess) return hip_fail((c), e_, #call); \
   } while (0)
 
 unsigned nblk(size_t n, unsigned b = 256) { return (unsigned)((n + b - 1) / b); }
 
-double* slot_set(hofks_ctx* c, int set) {
-  return c->slots + (size_t)set * (SMAX + 1) * SLOT_STRIDE;
-}
+double* slot_set(hofks_ctx* c, int set) { return c->slots + (size_t)set * SET_D; }
+int rpar(const hofks_ctx* c) { return (int)(c->steps & 1); }   // buffer holding U^n, rec^n
+int rset(const hofks_ctx* c) { return (int)(c->steps % 3); }   // speeds of U^n
 
-// timing groups: 0 Euler sub-steps, 1 kinetic, 2 cell update
+// timing groups: 0 Euler sub-steps (not separable in the fused step), 1 the
+// fused step kernel, 2 unused
 hipEvent_t next_event(hofks_ctx* c) {
   if (c->ev_next == c->ev_pool.size()) {
     hipEvent_t e;
@@ -256,34 +281,71 @@ struct Mark {
 
 // ---------------------------------------------------------------- launchers
 template <int D, typename T>
-hofks_status launch_cell_update(hofks_ctx* c, int mode, int set, int aset) {
+hofks_status launch_cell_init(hofks_ctx* c, int mode) {
   const Plan& P = c->P;
-  hipLaunchKernelGGL((k_cell_update<D, T>), dim3(nblk(P.G.nc)), dim3(256), 0, c->stream, c->U,
-                     c->cf, c->rec, (T*)(P.prec ? c->recT : nullptr), c->part, P.nchunk, c->UE[0],
-                     c->UE[1], c->slots, set, aset, c->s_cap, c->flag, P.G, P.A, mode,
-                     (int)(c->desc.scheme == 1));
+  const int rp = rpar(c);
+  hipLaunchKernelGGL((k_cell_init<D, T>), dim3(nblk(P.G.nc)), dim3(256), 0, c->stream, c->U[rp],
+                     c->cf, (T*)c->rec[rp], c->vt, c->part, slot_set(c, rset(c)), c->flag, P.G,
+                     P.A, mode);
   HIPCHK(c, hipGetLastError());
   return HOFKS_OK;
 }
 
 template <int D, typename T>
-hofks_status launch_kinetic(hofks_ctx* c, int set) {
+hofks_status launch_step(hofks_ctx* c) {
   const Plan& P = c->P;
-  const T* gin = (const T*)c->g[c->cur];
-  T* gout = (T*)c->g[c->cur ^ 1];
-  const T* rec = P.prec ? (const T*)c->recT : (const T*)c->rec;
-  const dim3 grid((unsigned)((long)P.nseg * P.nrowgrp * P.nchunk));
+  const int rp = rpar(c);
+  const long n = c->steps;
+  StepArgs<T> a;
+  a.g_in = (const T*)c->g[c->cur];
+  a.g_out = (T*)c->g[c->cur ^ 1];
+  a.rec_in = (const T*)c->rec[rp];
+  a.rec_out = (T*)c->rec[rp ^ 1];
+  a.vt = c->vt;
+  a.U_in = c->U[rp];
+  a.U_out = c->U[rp ^ 1];
+  a.UE0 = c->UE[0];
+  a.UE1 = c->UE[1];
+  a.cf = c->cf;
+  a.part = c->part;
+  a.tile_cnt = c->tiles;
+  a.set_r = slot_set(c, (int)(n % 3));
+  a.set_w = slot_set(c, (int)((n + 1) % 3));
+  a.set_z = slot_set(c, (int)((n + 2) % 3));
+  a.flag = c->flag;
+  a.TX = P.TX;
+  a.TR = P.TR;
+  a.nseg = P.nseg;
+  a.nrowgrp = P.nrowgrp;
+  a.nchunk = P.nchunk;
+  a.nvr = P.nvr;
+  a.s_cap = c->s_cap;
+  a.unlimited = (int)(c->desc.scheme == 2);
+  a.fks = (int)(c->desc.scheme == 1);
   const bool ft = (P.G.mu == 0.0);
-  const bool comp = (P.prec == 1);
-  double* zs = slot_set(c, set ^ 1);
-#define KLAUNCH(FT, CP)                                                                       \
-  hipLaunchKernelGGL((k_kinetic<D, T, FT, CP>), grid, dim3(256), P.lds, c->stream, gin, gout, \
-                     rec, c->part, zs, P.G, P.TX, P.TR, P.nseg, P.nrowgrp, P.nchunk, P.nvr)
-  if (ft) {
-    if (comp) KLAUNCH(true, true); else KLAUNCH(true, false);
-  } else {
-    if (comp) KLAUNCH(false, true); else KLAUNCH(false, false);
+  const bool eul = !ft && c->desc.scheme != 1;
+  a.GE = eul ? P.GE : 0;
+  constexpr bool CP = sizeof(T) == 4;  // compensated sums in the FP32 form
+  const int bcx = P.G.bc[0];
+  const bool unr = (P.G.nv1 % 8) == 0;
+  const dim3 grid((unsigned)(a.GE + (long)P.nseg * P.nrowgrp * P.nchunk));
+#define KLAUNCH(FT, BCX, UNR, EUL)                                                              \
+  hipLaunchKernelGGL((k_step<D, T, FT, CP, BCX, UNR, EUL>), grid, dim3(256), P.lds, c->stream, \
+                     a, P.G, P.A)
+#define KL2(FT, EUL)                                        \
+  if (bcx == 0) {                                           \
+    if (unr) KLAUNCH(FT, 0, 8, EUL); else KLAUNCH(FT, 0, 1, EUL); \
+  } else {                                                  \
+    if (unr) KLAUNCH(FT, 1, 8, EUL); else KLAUNCH(FT, 1, 1, EUL); \
   }
+  if (ft) {
+    KL2(true, false)
+  } else if (eul) {
+    KL2(false, true)
+  } else {
+    KL2(false, false)
+  }
+#undef KL2
 #undef KLAUNCH
   HIPCHK(c, hipGetLastError());
   return HOFKS_OK;
@@ -291,28 +353,11 @@ hofks_status launch_kinetic(hofks_ctx* c, int set) {
 
 template <int D, typename T>
 hofks_status step_impl(hofks_ctx* c, int nsteps) {
-  const Plan& P = c->P;
-  const bool need_euler = (P.G.mu != 0.0) && (c->desc.scheme != 1);
   for (int it = 0; it < nsteps; ++it) {
-    const int set = (int)(c->steps & 1);
-    if (need_euler) {
-      Mark m(c, 0);
-      for (int i = 0; i < c->s_cap; ++i) {
-        hipLaunchKernelGGL((k_muscl<D>), dim3(nblk(P.G.nc)), dim3(256), 0, c->stream, c->U,
-                           c->UE[0], c->UE[1], c->slots, set, i, c->s_cap, c->flag, P.G,
-                           (int)(c->desc.scheme == 2));
-      }
-      HIPCHK(c, hipGetLastError());
-    }
     hofks_status st;
     {
       Mark m(c, 1);
-      st = launch_kinetic<D, T>(c, set);
-    }
-    if (st) return st;
-    {
-      Mark m(c, 2);
-      st = launch_cell_update<D, T>(c, MODE_STEP, set, set ^ 1);
+      st = launch_step<D, T>(c);
     }
     if (st) return st;
     c->cur ^= 1;
@@ -340,10 +385,20 @@ hofks_status zero_doubles(hofks_ctx* c, double* p, size_t n) {
   return HOFKS_OK;
 }
 
+hofks_status zero_ints(hofks_ctx* c, int* p, int n) {
+  hipLaunchKernelGGL(k_zero_int, dim3(nblk((size_t)n)), dim3(256), 0, c->stream, p, n);
+  HIPCHK(c, hipGetLastError());
+  return HOFKS_OK;
+}
+
 hofks_status read_flag(hofks_ctx* c) {
   int h[2] = {0, 0};
   HIPCHK(c, hipMemcpyAsync(h, c->flag, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (h[0] & FLAG_SPIN) {
+    fmt_err(c->err, "a bounded wait of the step kernel gave up; results are invalid");
+    return HOFKS_EDEVICE;
+  }
   if (h[0] & FLAG_NONPHYS) {
     fmt_err(c->err, "non-physical moments (rho <= 0, theta <= 0 or non-finite) were met");
     return HOFKS_ENONPHYS;
@@ -355,30 +410,39 @@ hofks_status read_flag(hofks_ctx* c) {
   return HOFKS_OK;
 }
 
-// after the records and the speeds of slot set `set` row 0 are final: size
-// the number of sub-step launches per step
-hofks_status plan_substeps(hofks_ctx* c, int set) {
-  double a[SLOT_STRIDE];
-  HIPCHK(c, hipMemcpyAsync(a, slot_set(c, set), sizeof(a), hipMemcpyDeviceToHost, c->stream));
+// sub-step cap from the speeds of U^n (row 0 of the read set)
+hofks_status plan_substeps(hofks_ctx* c) {
+  double a[ASTR];
+  HIPCHK(c, hipMemcpyAsync(a, slot_set(c, rset(c)), sizeof(a), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   double sum = 0.0;
   for (int k = 0; k < c->P.d; ++k) sum += a[k];
-  double sv = std::ceil(2.0 * c->P.G.dt * sum / c->P.G.dx);
-  int s0 = (sv >= 1.0 && sv < SMAX) ? (int)sv : (sv >= SMAX ? SMAX : 1);
+  const double sv = std::ceil(2.0 * c->P.G.dt * sum / c->P.G.dx);
+  const int s0 = (sv >= 1.0 && sv < SMAX) ? (int)sv : (sv >= SMAX ? SMAX : 1);
   c->s_cap = std::min(SMAX, std::max(2 * s0, s0 + 8));
   return HOFKS_OK;
 }
 
-// records of the current U and cf with the current lambda (after set_tau)
+// records and speeds of the current U and cf with the current lambda
 hofks_status refresh(hofks_ctx* c) {
-  const int set = (int)(c->steps & 1);
-  hofks_status st = zero_doubles(c, slot_set(c, set), SLOT_STRIDE);
+  hofks_status st = zero_doubles(c, c->slots, 3 * (size_t)SET_D);
   if (st) return st;
   st = dispatch(c, [&](auto D, auto t) {
-    return launch_cell_update<decltype(D)::value, decltype(t)>(c, MODE_REFRESH, set, set);
+    return launch_cell_init<decltype(D)::value, decltype(t)>(c, MODE_REFRESH);
   });
   if (st) return st;
-  return plan_substeps(c, set);
+  return plan_substeps(c);
+}
+
+// common start of both state set-ups
+hofks_status reset_counters(hofks_ctx* c) {
+  c->cur = 0;
+  c->steps = 0;
+  hofks_status st = zero_ints(c, c->flag, 16);
+  if (st) return st;
+  st = zero_ints(c, c->tiles, c->P.nseg * c->P.nrowgrp);
+  if (st) return st;
+  return zero_doubles(c, c->slots, 3 * (size_t)SET_D);
 }
 
 }  // namespace
@@ -414,22 +478,31 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
   c->stream = (hipStream_t)hip_stream;
   c->ws = (unsigned char*)dev_ws;
   const Plan& P = c->P;
-  c->g[0] = c->ws + P.off_g[0];
-  c->g[1] = c->ws + P.off_g[1];
+  for (int i = 0; i < 2; ++i) {
+    c->g[i] = c->ws + P.off_g[i];
+    c->U[i] = (double*)(c->ws + P.off_U[i]);
+    c->UE[i] = (double*)(c->ws + P.off_UE[i]);
+    c->rec[i] = (void*)(c->ws + P.off_rec[i]);
+  }
   c->cur = 0;
-  c->U = (double*)(c->ws + P.off_U);
-  c->UE[0] = (double*)(c->ws + P.off_UE[0]);
-  c->UE[1] = (double*)(c->ws + P.off_UE[1]);
-  c->rec = (double*)(c->ws + P.off_rec);
-  c->recT = P.prec ? (void*)(c->ws + P.off_recT) : nullptr;
+  c->vt = (VelNode*)(c->ws + P.off_vt);
   c->cf = (double*)(c->ws + P.off_cf);
   c->part = (double*)(c->ws + P.off_part);
   c->slots = (double*)(c->ws + P.off_slots);
+  c->tiles = (int*)(c->ws + P.off_tiles);
   c->flag = (int*)(c->ws + P.off_flag);
   c->tau = INFINITY;
   c->s_cap = 1;
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, c->stream, c->flag, 16);
-  if (hipGetLastError() != hipSuccess) {
+  // velocity node table of one axis (the lattice, used by every kernel)
+  std::vector<VelNode> tab(P.G.nv1);
+  for (int i = 0; i < P.G.nv1; ++i) {
+    const double v = (i - P.G.kofs) * P.G.dv;
+    tab[i] = VelNode{v, v * v, (float)v, (float)(0.5 * v * v), 0.0f, 0.0f};
+  }
+  if (reset_counters(c) != HOFKS_OK ||
+      hipMemcpyAsync(c->vt, tab.data(), tab.size() * sizeof(VelNode), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
     delete c;
     return HOFKS_EDEVICE;
   }
@@ -461,43 +534,36 @@ hofks_status hofks_set_state_macro(hofks_ctx* c, const double* rho, const double
   if (!c || !rho || !theta || !u) return HOFKS_EINVAL;
   const Plan& P = c->P;
   const size_t nc = P.G.nc;
+  hofks_status st = reset_counters(c);
+  if (st) return st;
   double* prim = c->UE[0];  // (d+2) x nc staging: rho | u | theta
   HIPCHK(c, hipMemcpyAsync(prim, rho, nc * 8, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(prim + nc, u, nc * 8 * P.d, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(prim + nc * (P.d + 1), theta, nc * 8, hipMemcpyHostToDevice, c->stream));
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, c->stream, c->flag, 16);
-  hofks_status st = zero_doubles(c, c->slots, 2 * (SMAX + 1) * SLOT_STRIDE);
-  if (st) return st;
   st = zero_doubles(c, c->cf, (size_t)P.nm * nc);
   if (st) return st;
-  c->cur = 0;
-  c->steps = 0;
   st = dispatch(c, [&](auto D, auto t) -> hofks_status {
     constexpr int DD = decltype(D)::value;
     using T = decltype(t);
     hipLaunchKernelGGL((k_prim_to_moments<DD>), dim3(nblk(nc)), dim3(256), 0, c->stream, prim,
-                       c->U, (int)nc);
+                       c->U[0], (int)nc);
     // Maxwellian parameters of U^0, then sample M into the pieces, sum the
     // stored pieces and project onto U^0 (f^0 = E[U^0], section 4.2)
-    hofks_status s2 = launch_cell_update<DD, T>(c, MODE_REFRESH, 0, 0);
+    hofks_status s2 = launch_cell_init<DD, T>(c, MODE_REFRESH);
     if (s2) return s2;
     const size_t tot = (size_t)P.G.nv * nc;
     hipLaunchKernelGGL((k_fill_maxwellian<DD, T>), dim3(nblk(tot)), dim3(256), 0, c->stream,
-                       (T*)c->g[0], c->rec, P.G);
+                       (T*)c->g[0], (const T*)c->rec[0], P.G);
     hipLaunchKernelGGL((k_piece_sums<DD, T>), dim3(nblk(nc)), dim3(256), 0, c->stream,
                        (const T*)c->g[0], c->part, P.G);
     HIPCHK(c, hipGetLastError());
-    return HOFKS_OK;
-  });
-  if (st) return st;
-  st = zero_doubles(c, c->slots, 2 * (SMAX + 1) * SLOT_STRIDE);
-  if (st) return st;
-  st = dispatch(c, [&](auto D, auto t) {
-    return launch_cell_update<decltype(D)::value, decltype(t)>(c, MODE_INIT, 0, 0);
+    s2 = zero_doubles(c, c->slots, 3 * (size_t)SET_D);
+    if (s2) return s2;
+    return launch_cell_init<DD, T>(c, MODE_INIT);
   });
   if (st) return st;
   c->ready = true;
-  st = plan_substeps(c, 0);
+  st = plan_substeps(c);
   if (st) return st;
   return read_flag(c);
 }
@@ -507,16 +573,15 @@ hofks_status hofks_set_state_f(hofks_ctx* c, const double* f, size_t bytes) {
   const Plan& P = c->P;
   const size_t nc = P.G.nc, tot = (size_t)P.G.nv * nc;
   if (bytes < tot * 8) return HOFKS_ESIZE;
+  hofks_status st = reset_counters(c);
+  if (st) return st;
   // stage FP64 planes through the idle piece buffer, store in piece precision
   const size_t per = std::max<size_t>(1, (tot * P.tsize) / (nc * 8));
   double* stage = (double*)c->g[1];
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, c->stream, c->flag, 16);
-  c->cur = 0;
-  c->steps = 0;
   for (size_t k0 = 0; k0 < (size_t)P.G.nv; k0 += per) {
     const size_t nk = std::min(per, (size_t)P.G.nv - k0);
     HIPCHK(c, hipMemcpyAsync(stage, f + k0 * nc, nk * nc * 8, hipMemcpyHostToDevice, c->stream));
-    hofks_status st = dispatch(c, [&](auto, auto t) -> hofks_status {
+    st = dispatch(c, [&](auto, auto t) -> hofks_status {
       using T = decltype(t);
       hipLaunchKernelGGL((k_store_planes<T>), dim3(nblk(nk * nc)), dim3(256), 0, c->stream,
                          (T*)c->g[0] + k0 * nc, stage, nk * nc);
@@ -525,19 +590,17 @@ hofks_status hofks_set_state_f(hofks_ctx* c, const double* f, size_t bytes) {
     });
     if (st) return st;
   }
-  hofks_status st = zero_doubles(c, c->slots, 2 * (SMAX + 1) * SLOT_STRIDE);
-  if (st) return st;
   st = dispatch(c, [&](auto D, auto t) -> hofks_status {
     constexpr int DD = decltype(D)::value;
     using T = decltype(t);
     hipLaunchKernelGGL((k_piece_sums<DD, T>), dim3(nblk(nc)), dim3(256), 0, c->stream,
                        (const T*)c->g[0], c->part, P.G);
     HIPCHK(c, hipGetLastError());
-    return launch_cell_update<DD, T>(c, MODE_INIT_FROM_SUMS, 0, 0);
+    return launch_cell_init<DD, T>(c, MODE_INIT_FROM_SUMS);
   });
   if (st) return st;
   c->ready = true;
-  st = plan_substeps(c, 0);
+  st = plan_substeps(c);
   if (st) return st;
   return read_flag(c);
 }
@@ -557,8 +620,8 @@ hofks_status hofks_sync(hofks_ctx* c) {
 
 hofks_status hofks_read_moments(hofks_ctx* c, double* U) {
   if (!c || !U) return HOFKS_EINVAL;
-  HIPCHK(c, hipMemcpyAsync(U, c->U, (size_t)c->P.nm * c->P.G.nc * 8, hipMemcpyDeviceToHost,
-                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(U, c->U[rpar(c)], (size_t)c->P.nm * c->P.G.nc * 8,
+                           hipMemcpyDeviceToHost, c->stream));
   return read_flag(c);
 }
 

@@ -1,36 +1,41 @@
 // kernels.hpp -- gfx950 kernels of one HOFKS time step (arXiv:1212.0204).
 //
-// Data kept resident in HBM between steps (all component-major, cells
-// x-fastest):
-//   g[k][j]   pieces of the distribution, one plane per velocity node k
-//             (FP64, or FP32 in the precision form).  The true distribution is
-//             f(j,k) = g(j,k) + w m_k . cf(j): the consistency correction of
-//             eq. (minim_full) is kept as d+2 coefficients per cell and applied
-//             when the piece is next read, so every step reads and writes each
-//             piece exactly once.
-//   U[r][j]   moments U^n (FP64).
-//   cf[r][j]  pending correction coefficients (C C^T)^{-1}(U_E - U_M).
-//   rec[q][j] per-cell record read by the pieces that leave cell j:
-//             q = 0 .. d+1         log prefactor, u_1..u_d, beta = 1/(2 theta)
-//             q = d+2 .. 2d+3      p = w (lambda cf + (1-lambda) cE)
-//             q = 2d+4 .. 3d+5     e = w cE
-//             with cE = (C C^T)^{-1}(U - C M) the conservative correction of
-//             eq. (minimMax); a piece of velocity v leaving cell j' relaxes to
-//               f* = lambda g + (1-lambda) M + p.m(v),
-//               E  = M + e.m(v),  M = exp(lp - beta |v - u|^2).
-// Per step: k_muscl (s sub-steps of eq. discmom on U^n), k_kinetic (relax +
-// shift + moment sums over all velocities of every cell), k_cell_update
-// (delta, U^{n+1}, cf, the next records and the next Lax-Friedrichs speeds).
+// Data kept resident in HBM between steps (cells x-fastest):
+//   g[k][j]    pieces of the distribution, one plane per velocity node k
+//              (FP64, or FP32 in the precision form).  The distribution is
+//              f(j,k) = g(j,k) + w m_k . cf(j): the consistency correction of
+//              eq. (minim_full) is kept as d+2 coefficients per cell and
+//              applied when the piece is next read, so every step reads and
+//              writes each piece exactly once.
+//   U[r][j]    moments U^n (FP64), two buffers (read / written by a step).
+//   cf[r][j]   pending correction coefficients (C C^T)^{-1}(U_E - U_M).
+//   rec[j][q]  per-cell record read by the pieces that leave cell j, in the
+//              piece precision, two buffers:
+//              q = 0 .. d+1      log prefactor, u_1..u_d, beta = 1/(2 theta)
+//              q = d+2 .. 2d+3   p = w (lambda cf + (1-lambda) cE)
+//              q = 2d+4 .. 3d+5  e = w cE
+//              with cE = (C C^T)^{-1}(U - C M) the conservative correction of
+//              eq. (minimMax); a piece of velocity v leaving cell j' relaxes to
+//                f* = lambda g + (1-lambda) M + p.m(v),
+//                E  = M + e.m(v),   M = exp(lp - beta |v - u|^2).
+// One launch of k_step advances one time step: its first blocks run the s
+// Euler sub-steps of eq. (discmom) on U^n (grid barrier between sub-steps),
+// the other blocks relax, shift and sum the pieces tile by tile, and the last
+// velocity chunk to finish a tile forms delta, U^{n+1}, cf and the next
+// records of the tile's cells once the Euler group is done.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace hofks {
 
-constexpr int SMAX = 512;  // largest Euler sub-step count a plan may use
-constexpr int SLOT_STRIDE = 4;
+constexpr int SMAX = 512;         // largest Euler sub-step count a plan may use
+constexpr int ASTR = 4;           // doubles per row of Lax-Friedrichs speeds
+constexpr int SET_D = (SMAX + 1) * ASTR + 8;  // doubles per slot set (+ 16 control ints)
 constexpr int FLAG_NONPHYS = 1;
 constexpr int FLAG_SUBSTEP = 2;
+constexpr int FLAG_SPIN = 4;      // a bounded wait gave up: results are invalid
+constexpr unsigned SPIN_CAP = 1u << 20;  // ~1-2 s of polling
 
 struct Geom {
   int n[3];
@@ -55,10 +60,14 @@ __device__ __forceinline__ int map_axis(int i, int N, int bc) {
   return i < 0 ? 0 : (i >= N ? N - 1 : i);
 }
 
-// |i - in-range| <= N guaranteed by the plan
-__device__ __forceinline__ int map_near(int i, int N, int bc) {
-  if (bc == 0) return i < 0 ? i + N : (i >= N ? i - N : i);
-  return i < 0 ? 0 : (i >= N ? N - 1 : i);
+template <int BCX>
+__device__ __forceinline__ int map_x(int xN, int kx, int N) {
+  if (BCX == 0) {  // periodic: t = x + N - k in [0, 2N)
+    const unsigned t = (unsigned)(xN - kx);
+    return (int)min(t, t - (unsigned)N);
+  }
+  const int t = xN - N - kx;  // outflow: clamp to the boundary cell
+  return min(max(t, 0), N - 1);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -70,6 +79,10 @@ __device__ __forceinline__ void atomic_max_pos(double* addr, double v) {
   // non-negative doubles order like their bit patterns
   atomicMax(reinterpret_cast<unsigned long long*>(addr),
             static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+
+__device__ __forceinline__ unsigned load_acquire(unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Euler sub-step count of a step, from the speeds of U^n (same rule as the
@@ -103,13 +116,76 @@ __device__ __forceinline__ float fast_exp<float>(float x) {
   return __expf(x);
 }
 
+// Record of a cell, array-of-structures: R = 3(d+2) values padded to RS so
+// that a record is an odd number of 16-byte chunks.  Lanes of a wavefront
+// read consecutive records with ds_read_b128; an odd chunk stride spreads
+// eight consecutive lanes over all LDS banks.
+template <int D, typename T>
+__host__ __device__ constexpr int rec_values() {
+  return 3 * (D + 2);
+}
+template <int D, typename T>
+__host__ __device__ constexpr int rec_stride() {
+  constexpr int per16 = 16 / (int)sizeof(T);
+  constexpr int n16 = (rec_values<D, T>() + per16 - 1) / per16;
+  return (n16 % 2 ? n16 : n16 + 1) * per16;
+}
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  using type = double2;
+};
+template <>
+struct Vec16<float> {
+  using type = float4;
+};
+
+// velocity node table of one axis: v, v^2, and FP32 copies (scalar loads)
+struct VelNode {
+  double v, v2;
+  float vf, v2hf;  // (float)v, (float)(v^2 / 2)
+  float pad0, pad1;
+};
+
+// bounded wait: gives up (and flags) after SPIN_CAP sleeps, or at once when
+// another wait of the launch has already given up
+__device__ __forceinline__ void spin_until_geq(unsigned* p, unsigned target, int* flag) {
+  unsigned it = 0;
+  while (load_acquire(p) < target) {
+    __builtin_amdgcn_s_sleep(2);
+    ++it;
+    if (it > SPIN_CAP ||
+        ((it & 255u) == 0 &&
+         (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SPIN))) {
+      atomicOr(flag, FLAG_SPIN);
+      break;
+    }
+  }
+}
+
+// barrier of the nb blocks of the Euler group (monotonic arrival counter)
+__device__ __forceinline__ void group_barrier(unsigned* cnt, unsigned target, int* flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(cnt, 1u);
+    spin_until_geq(cnt, target, flag);
+  }
+  __syncthreads();
+  __threadfence();  // acquire for every wave: the next sub-step reads other blocks' cells
+}
+
 // ===================================================================== MUSCL
 // Section 4.3.2: flux-split Lax-Friedrichs with Van Leer limited slopes of
 // W+- = F +- alpha U, unsplit over the d directions, forward Euler in time.
+// The face flux psi = (F_l + F_r)/2 - alpha (U_r - U_l)/2 + (s+_l - s-_r)/4
+// is written as (W+_l + W-_r)/2 + (s+_l - s-_r)/4.
 
+// W+- of one cell along axis a; false if the state is not physical
 template <int D>
-__device__ __forceinline__ bool euler_flux(const double* U, int a, double gam, double* F,
-                                           double* speed) {
+__device__ __forceinline__ bool split_flux(const double* U, int a, double alpha, double gam,
+                                           double* Wp, double* Wm) {
   constexpr int NM = D + 2;
   double rho = U[0], usq = 0.0, u[3];
 #pragma unroll
@@ -117,150 +193,304 @@ __device__ __forceinline__ bool euler_flux(const double* U, int a, double gam, d
     u[b] = U[1 + b] / rho;
     usq += u[b] * u[b];
   }
-  double th = (2.0 * U[NM - 1] - rho * usq) / (D * rho);
-  double p = rho * th;
+  const double th = (2.0 * U[NM - 1] - rho * usq) / (D * rho);
+  const double p = rho * th;
+  double F[NM];
   F[0] = U[1 + a];
 #pragma unroll
   for (int b = 0; b < D; ++b) F[1 + b] = U[1 + b] * u[a] + (a == b ? p : 0.0);
   F[NM - 1] = (U[NM - 1] + p) * u[a];
-  if (speed) *speed = fabs(u[a]) + sqrt(gam * p / rho);
+#pragma unroll
+  for (int r = 0; r < NM; ++r) {
+    Wp[r] = F[r] + alpha * U[r];
+    Wm[r] = F[r] - alpha * U[r];
+  }
   return (rho > 0.0) && (th > 0.0) && isfinite(rho) && isfinite(th) && isfinite(usq);
+}
+
+// |u_a| + c for every axis; false if the state is not physical
+template <int D>
+__device__ __forceinline__ bool lf_speeds(const double* U, double gam, double* sp) {
+  constexpr int NM = D + 2;
+  const double rho = U[0];
+  double usq = 0.0, u[3];
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    u[b] = U[1 + b] / rho;
+    usq += u[b] * u[b];
+  }
+  const double th = (2.0 * U[NM - 1] - rho * usq) / (D * rho);
+  const bool ok = (rho > 0.0) && (th > 0.0) && isfinite(rho) && isfinite(th) && isfinite(usq);
+  const double c = ok ? sqrt(gam * (rho * th) / rho) : 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) sp[a] = ok ? fabs(u[a]) + c : 0.0;
+  return ok;
 }
 
 __device__ __forceinline__ double vl_slope(double a, double b, int unlimited) {
   if (unlimited) return b;
-  double ab = a * b;
+  const double ab = a * b;
   return ab > 0.0 ? 2.0 * ab / (a + b) : 0.0;
 }
 
-// flux through a face from the four cells around it (indices 0..3 of Uq/Fq)
-template <int NM>
-__device__ __forceinline__ void face_flux(const double (*Uq)[NM], const double (*Fq)[NM],
-                                          double alpha, int unl, double* psi) {
+// new value of cell j after one sub-step: in - dt_s/dx sum_a (psi_a+ - psi_a-).
+// Each face is formed from its own four cells (both neighbours of a face get
+// bit-identical fluxes, so the update conserves exactly up to the final sum).
+template <int D>
+__device__ __forceinline__ bool euler_cell(const double* __restrict__ in, int j,
+                                           const double* alpha, double dts_dx, const Geom& G,
+                                           int unl, double* Un) {
+  constexpr int NM = D + 2;
+  const int c[3] = {j % G.n[0], (j / G.n[0]) % G.n[1], j / (G.n[0] * G.n[1])};
+  double div[NM];
 #pragma unroll
-  for (int r = 0; r < NM; ++r) {
-    double wp0 = Fq[0][r] + alpha * Uq[0][r], wp1 = Fq[1][r] + alpha * Uq[1][r],
-           wp2 = Fq[2][r] + alpha * Uq[2][r];
-    double wm1 = Fq[1][r] - alpha * Uq[1][r], wm2 = Fq[2][r] - alpha * Uq[2][r],
-           wm3 = Fq[3][r] - alpha * Uq[3][r];
-    double sp = vl_slope(wp1 - wp0, wp2 - wp1, unl);
-    double sm = vl_slope(wm2 - wm1, wm3 - wm2, unl);
-    psi[r] = 0.5 * (Fq[1][r] + Fq[2][r]) - 0.5 * alpha * (Uq[2][r] - Uq[1][r]) +
-             0.25 * (sp - sm);
+  for (int r = 0; r < NM; ++r) div[r] = 0.0;
+  bool phys = true;
+#pragma unroll 1
+  for (int a = 0; a < D; ++a) {
+#pragma unroll 1
+    for (int side = -1; side <= 0; ++side) {
+      // face between cells j+side and j+side+1: stencil j+side-1 .. j+side+2
+      double Wp[3][NM], Wm[3][NM];  // W+ of cells 0..2, W- of cells 1..3
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int cc[3] = {c[0], c[1], c[2]};
+        cc[a] = map_axis(c[a] + side - 1 + q, G.n[a], G.bc[a]);
+        const int jj = (cc[2] * G.n[1] + cc[1]) * G.n[0] + cc[0];
+        double Uq[NM], wp[NM], wm[NM];
+#pragma unroll
+        for (int r = 0; r < NM; ++r) Uq[r] = in[(size_t)r * G.nc + jj];
+        phys &= split_flux<D>(Uq, a, alpha[a], G.gam, wp, wm);
+#pragma unroll
+        for (int r = 0; r < NM; ++r) {
+          if (q < 3) Wp[q][r] = wp[r];
+          if (q > 0) Wm[q - 1][r] = wm[r];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < NM; ++r) {
+        const double sp = vl_slope(Wp[1][r] - Wp[0][r], Wp[2][r] - Wp[1][r], unl);
+        const double sm = vl_slope(Wm[1][r] - Wm[0][r], Wm[2][r] - Wm[1][r], unl);
+        const double psi = 0.5 * (Wp[1][r] + Wm[1][r]) + 0.25 * (sp - sm);
+        div[r] += side == 0 ? psi : -psi;
+      }
+    }
   }
+#pragma unroll
+  for (int r = 0; r < NM; ++r) Un[r] = in[(size_t)r * G.nc + j] - dts_dx * div[r];
+  return phys;
 }
 
-// one Euler sub-step i of the current step (slot set `set`)
-template <int D>
-__global__ __launch_bounds__(256) void k_muscl(const double* __restrict__ U,
-                                               double* __restrict__ UE0,
-                                               double* __restrict__ UE1,
-                                               double* __restrict__ slots, int set, int i,
-                                               int s_cap, int* __restrict__ flag, Geom G,
-                                               int unlimited) {
+// ============================================================ cell record
+// Maxwellian parameters of U (eq. M, theta from eq. E), separable discrete
+// moments C M (sums along each velocity axis), cE = A (U - C M), and the
+// record; speeds |u_a| + c for the next Euler solve.  Returns physicality.
+template <int D, typename T>
+__device__ __forceinline__ bool cell_record(const double* Un, const double* cfv, const Geom& G,
+                                            const Mat& A, const VelNode* __restrict__ vt,
+                                            T* __restrict__ rec_j, double* speed) {
   constexpr int NM = D + 2;
-  double* srow = slots + (size_t)set * (SMAX + 1) * SLOT_STRIDE;
-  bool over;
-  const int s = substeps<D>(srow, G, s_cap, &over);
-  if (i >= s) return;
-  const double* in = (i == 0) ? U : ((i & 1) ? UE1 : UE0);
-  double* out = ((i + 1) & 1) ? UE1 : UE0;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const double dts = G.dt / s;
-  bool phys = true;
-  double speed_out[3] = {0.0, 0.0, 0.0};
-  if (j < G.nc) {
-    int c[3] = {j % G.n[0], (j / G.n[0]) % G.n[1], j / (G.n[0] * G.n[1])};
-    double div[NM];
+  const double rho = Un[0];
+  double u[3] = {0.0, 0.0, 0.0}, usq = 0.0;
 #pragma unroll
-    for (int r = 0; r < NM; ++r) div[r] = 0.0;
+  for (int a = 0; a < D; ++a) {
+    u[a] = Un[1 + a] / rho;
+    usq += u[a] * u[a];
+  }
+  const double th = (2.0 * Un[NM - 1] - rho * usq) / (D * rho);
+  const bool phys = (rho > 0.0) && (th > 0.0) && isfinite(rho) && isfinite(th) && isfinite(usq);
+  double lp = 0.0, beta = 0.0, cE[NM];
+#pragma unroll
+  for (int r = 0; r < NM; ++r) cE[r] = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) speed[a] = 0.0;
+  if (phys) {
+    beta = 0.5 / th;
+    const double pref = rho * pow(2.0 * M_PI * th, -0.5 * D);
+    lp = log(rho) - 0.5 * D * log(2.0 * M_PI * th);
+    double G0[3], G1[3], G2[3];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const double alpha = srow[i * SLOT_STRIDE + a];
-      double Uq[5][NM], Fq[5][NM];
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        int cc[3] = {c[0], c[1], c[2]};
-        cc[a] = map_axis(c[a] + q - 2, G.n[a], G.bc[a]);
-        int jj = (cc[2] * G.n[1] + cc[1]) * G.n[0] + cc[0];
-#pragma unroll
-        for (int r = 0; r < NM; ++r) Uq[q][r] = in[(size_t)r * G.nc + jj];
-        phys &= euler_flux<D>(Uq[q], a, G.gam, Fq[q], nullptr);
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      for (int i = 0; i < G.nv1; ++i) {
+        const double v = vt[i].v;
+        const double e = exp(-beta * (v - u[a]) * (v - u[a]));
+        s0 += e;
+        s1 += v * e;
+        s2 += vt[i].v2 * e;
       }
-      double pl[NM], pr[NM];
-      face_flux<NM>(Uq, Fq, alpha, unlimited, pl);          // face j-1/2
-      face_flux<NM>(Uq + 1, Fq + 1, alpha, unlimited, pr);  // face j+1/2
-#pragma unroll
-      for (int r = 0; r < NM; ++r) div[r] += pr[r] - pl[r];
+      G0[a] = s0;
+      G1[a] = s1;
+      G2[a] = s2;
     }
-    double Un[NM];
+    double CM[NM];
+    double all0 = 1.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) all0 *= G0[a];
+    CM[0] = G.w * pref * all0;
+    double en = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      double oth = 1.0;
+#pragma unroll
+      for (int b2 = 0; b2 < D; ++b2)
+        if (b2 != a) oth *= G0[b2];
+      CM[1 + a] = G.w * pref * G1[a] * oth;
+      en += G2[a] * oth;
+    }
+    CM[NM - 1] = G.w * pref * 0.5 * en;
 #pragma unroll
     for (int r = 0; r < NM; ++r) {
-      Un[r] = in[(size_t)r * G.nc + j] - dts / G.dx * div[r];
-      out[(size_t)r * G.nc + j] = Un[r];
-    }
-    if (i + 1 < s) {
-      double F[NM];
+      double acc = 0.0;
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        double sp;
-        phys &= euler_flux<D>(Un, a, G.gam, F, &sp);
-        speed_out[a] = phys ? sp : 0.0;
-      }
+      for (int s2 = 0; s2 < NM; ++s2) acc += A.a[r * NM + s2] * (Un[s2] - CM[s2]);
+      cE[r] = acc;
+    }
+    const double c = sqrt(G.gam * (rho * th) / rho);
+#pragma unroll
+    for (int a = 0; a < D; ++a) speed[a] = fabs(u[a]) + c;
+  }
+  const bool need_eq = G.mu != 0.0;
+  constexpr int RS = rec_stride<D, T>();
+  T rv[RS];
+#pragma unroll
+  for (int q = 0; q < RS; ++q) rv[q] = (T)0;
+  rv[0] = (T)lp;
+#pragma unroll
+  for (int a = 0; a < D; ++a) rv[1 + a] = (T)u[a];
+  rv[D + 1] = (T)beta;
+#pragma unroll
+  for (int r = 0; r < NM; ++r) {
+    rv[NM + r] = (T)(need_eq ? G.w * (G.lam * cfv[r] + G.mu * cE[r]) : G.w * (G.lam * cfv[r]));
+    rv[2 * NM + r] = (T)(G.w * cE[r]);
+  }
+#pragma unroll
+  for (int q = 0; q < RS; ++q) rec_j[q] = rv[q];
+  return phys;
+}
+
+// ================================================================ step
+template <typename T>
+struct StepArgs {
+  const T* g_in;
+  T* g_out;
+  const T* rec_in;
+  T* rec_out;
+  const VelNode* vt;
+  const double* U_in;
+  double* U_out;
+  double* UE0;
+  double* UE1;
+  double* cf;
+  double* part;       // nchunk x 2(d+2) x nc velocity-chunk sums
+  int* tile_cnt;      // chunks finished per tile
+  double* set_r;      // speeds of U^n (row 0) and of the sub-steps; control
+  double* set_w;      // speeds of U^{n+1} (row 0), written by the epilogues
+  double* set_z;      // the set of the step after next, cleared here
+  int* flag;
+  int TX, TR, nseg, nrowgrp, nchunk, nvr, GE, s_cap, unlimited, fks;
+};
+
+// Euler group: blocks 0 .. GE-1 advance U^n over dt with s sub-steps; the
+// speeds of sub-step i+1 are reduced with atomics into row i+1 of set_r.
+template <int D, typename T>
+__device__ void euler_group(const StepArgs<T>& a, const Geom& G) {
+  constexpr int NM = D + 2;
+  double* S = a.set_r;
+  unsigned* ctrl = reinterpret_cast<unsigned*>(S + (SMAX + 1) * ASTR);
+  bool over;
+  const int s = substeps<D>(S, G, a.s_cap, &over);
+  if (blockIdx.x == 0) {
+    for (int q = threadIdx.x; q < SET_D; q += blockDim.x) a.set_z[q] = 0.0;
+    if (threadIdx.x == 0) {
+      if (over) atomicOr(a.flag, FLAG_SUBSTEP);
+      a.flag[1] = s;
     }
   }
-  if (!phys) atomicOr(flag, FLAG_NONPHYS);
-  if (i + 1 < s) {
+  const double dts_dx = (G.dt / s) / G.dx;
+  for (int i = 0; i < s; ++i) {
+    const double* in = (i == 0) ? a.U_in : ((i & 1) ? a.UE1 : a.UE0);
+    double* out = ((i + 1) & 1) ? a.UE1 : a.UE0;
+    double alpha[3];
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      double m = wave_max(speed_out[a]);
-      if ((threadIdx.x & 63) == 0) atomic_max_pos(srow + (i + 1) * SLOT_STRIDE + a, m);
+    for (int d2 = 0; d2 < D; ++d2)
+      alpha[d2] = __hip_atomic_load(S + i * ASTR + d2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool phys = true;
+    double mx[3] = {0.0, 0.0, 0.0};
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < G.nc; j += a.GE * blockDim.x) {
+      double Un[NM];
+      phys &= euler_cell<D>(in, j, alpha, dts_dx, G, a.unlimited, Un);
+#pragma unroll
+      for (int r = 0; r < NM; ++r) out[(size_t)r * G.nc + j] = Un[r];
+      if (i + 1 < s) {
+        double sp[3];
+        phys &= lf_speeds<D>(Un, G.gam, sp);
+#pragma unroll
+        for (int d2 = 0; d2 < D; ++d2) mx[d2] = fmax(mx[d2], sp[d2]);
+      }
     }
+    if (!phys) atomicOr(a.flag, FLAG_NONPHYS);
+    if (i + 1 < s) {
+#pragma unroll
+      for (int d2 = 0; d2 < D; ++d2) {
+        const double m = wave_max(mx[d2]);
+        if ((threadIdx.x & 63) == 0) atomic_max_pos(S + (i + 1) * ASTR + d2, m);
+      }
+    }
+    group_barrier(ctrl, (unsigned)((i + 1) * a.GE), a.flag);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_store(ctrl + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// =================================================================== kinetic
-// One block = TX x TR destination cells (TX consecutive x, TR rows), one
-// chunk of velocity rows.  For every velocity row (k_y, k_z) the records of
-// the upstream row segment are staged in LDS; the inner loop over k_x reads
-// the piece g(j - k, k) (coalesced along x), relaxes it, writes it to cell j
-// of the new buffer and accumulates the moment sums of f* and of E.
-template <int D, typename T, bool FT, bool COMP>
-__global__ __launch_bounds__(256) void k_kinetic(const T* __restrict__ g_in,
-                                                 T* __restrict__ g_out,
-                                                 const T* __restrict__ rec,
-                                                 double* __restrict__ part,
-                                                 double* __restrict__ zero_slots, Geom G,
-                                                 int TX, int TR, int nseg, int nrowgrp,
-                                                 int nchunk, int nvr) {
+// One kinetic block = TX x TR destination cells (TX consecutive x, TR rows)
+// and one chunk of velocity rows.  For every velocity row (k_y, k_z) the
+// records of the upstream row segment are staged in LDS; the loop over k_x
+// issues the loads of UNR pieces g(j - k, k) (coalesced along x) before using
+// them, relaxes each piece, writes it to cell j of the new buffer and sums
+// the moments of f* and of E.  The last chunk to finish a tile then forms the
+// new state of the tile's cells.
+template <int D, typename T, bool FT, bool COMP, int BCX, int UNR, bool EUL>
+__global__ __launch_bounds__(256) void k_step(StepArgs<T> a, Geom G, Mat A) {
+  if (EUL && (int)blockIdx.x < a.GE) {
+    euler_group<D, T>(a, G);
+    return;
+  }
   constexpr int NM = D + 2;
-  constexpr int R = 3 * NM;
-  extern __shared__ unsigned char lds_raw[];
+  constexpr int RS = rec_stride<D, T>();
+  constexpr int PER16 = 16 / (int)sizeof(T);
+  constexpr int NCH = (rec_values<D, T>() + PER16 - 1) / PER16;  // chunks read per piece
+  using V = typename Vec16<T>::type;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  __shared__ int s_last;
   T* lds = reinterpret_cast<T*>(lds_raw);
+  const int TX = a.TX, TR = a.TR;
   const int SW = TX + G.nv1 - 1;
 
-  if (zero_slots != nullptr && blockIdx.x == 0) {
-    for (int q = threadIdx.x; q < (SMAX + 1) * SLOT_STRIDE; q += blockDim.x) zero_slots[q] = 0.0;
-  }
-
-  int b = blockIdx.x;
-  const int seg = b % nseg;
-  b /= nseg;
-  const int rg = b % nrowgrp;
-  const int chunk = b / nrowgrp;
+  int b = (int)blockIdx.x - (EUL ? a.GE : 0);
+  const int tile = b % (a.nseg * a.nrowgrp);
+  const int seg = b % a.nseg;
+  b /= a.nseg;
+  const int rg = b % a.nrowgrp;
+  const int chunk = b / a.nrowgrp;
   const int tx = threadIdx.x % TX, tr = threadIdx.x / TX;
   const int x0 = seg * TX;
   const int x = x0 + tx;
+  const int Nx = G.n[0];
+  const int xN = x + Nx;
   const int nrows = G.n[1] * G.n[2];
   const int row = rg * TR + tr;
-  const bool active = (x < G.n[0]) && (row < nrows) && (tr < TR);
+  const bool active = (x < Nx) && (row < nrows) && (tr < TR);
   const int jy = active ? row % G.n[1] : 0;
   const int jz = active ? row / G.n[1] : 0;
-  const int dest = row * G.n[0] + x;
-  const int vr0 = (int)((long)chunk * nvr / nchunk);
-  const int vr1 = (int)((long)(chunk + 1) * nvr / nchunk);
+  const int dest = row * Nx + x;
+  const int vr0 = (int)((long)chunk * a.nvr / a.nchunk);
+  const int vr1 = (int)((long)(chunk + 1) * a.nvr / a.nchunk);
   const int xlo = x0 - (G.nv1 - 1 - G.kofs);
   const int lofs = G.nv1 - 1 - G.kofs;
+  const T lam = (T)G.lam, mu = (T)G.mu;
 
   double SK[NM], SE[NM], CK[NM], CE[NM];
 #pragma unroll
@@ -270,22 +500,30 @@ __global__ __launch_bounds__(256) void k_kinetic(const T* __restrict__ g_in,
     const int iy = (D >= 2) ? vr % G.nv1 : 0;
     const int iz = (D >= 3) ? vr / G.nv1 : 0;
     const int ky = iy - G.kofs, kz = iz - G.kofs;
-    const double vy = (D >= 2) ? ky * G.dv : 0.0;
-    const double vz = (D >= 3) ? kz * G.dv : 0.0;
-    const double hrow = 0.5 * (vy * vy + vz * vz);
+    const double vy = (D >= 2) ? a.vt[iy].v : 0.0;
+    const double vz = (D >= 3) ? a.vt[iz].v : 0.0;
+    const double hrow = (D >= 2 ? 0.5 * a.vt[iy].v2 : 0.0) + (D >= 3 ? 0.5 * a.vt[iz].v2 : 0.0);
 
+    // stage the records of the upstream row segments (16-byte chunks)
     __syncthreads();
-    for (int idx = threadIdx.x; idx < TR * SW; idx += blockDim.x) {
-      const int r_ = idx / SW, i = idx - r_ * SW;
-      const int rw = rg * TR + r_;
-      if (rw < nrows) {
-        const int ry = rw % G.n[1], rz = rw / G.n[1];
-        const int uy = (D >= 2) ? map_axis(ry - ky, G.n[1], G.bc[1]) : 0;
-        const int uz = (D >= 3) ? map_axis(rz - kz, G.n[2], G.bc[2]) : 0;
-        const int ux = map_axis(xlo + i, G.n[0], G.bc[0]);
-        const int cell = (uz * G.n[1] + uy) * G.n[0] + ux;
-#pragma unroll
-        for (int q = 0; q < R; ++q) lds[(r_ * R + q) * SW + i] = rec[(size_t)q * G.nc + cell];
+    {
+      constexpr int C16 = RS / PER16;
+      const int total = TR * SW * C16;
+      V* ldsv = reinterpret_cast<V*>(lds);
+      const V* recv = reinterpret_cast<const V*>(a.rec_in);
+      for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int c = idx % C16;
+        const int cellslot = idx / C16;
+        const int r_ = cellslot / SW, i = cellslot - r_ * SW;
+        const int rw = rg * TR + r_;
+        if (rw < nrows) {
+          const int ry = rw % G.n[1], rz = rw / G.n[1];
+          const int uy = (D >= 2) ? map_axis(ry - ky, G.n[1], G.bc[1]) : 0;
+          const int uz = (D >= 3) ? map_axis(rz - kz, G.n[2], G.bc[2]) : 0;
+          const int ux = map_axis(xlo + i, Nx, G.bc[0]);
+          const int cell = (uz * G.n[1] + uy) * Nx + ux;
+          ldsv[idx] = recv[(size_t)cell * C16 + c];
+        }
       }
     }
     __syncthreads();
@@ -293,54 +531,87 @@ __global__ __launch_bounds__(256) void k_kinetic(const T* __restrict__ g_in,
 
     const int uy = (D >= 2) ? map_axis(jy - ky, G.n[1], G.bc[1]) : 0;
     const int uz = (D >= 3) ? map_axis(jz - kz, G.n[2], G.bc[2]) : 0;
-    const int ubase = (uz * G.n[1] + uy) * G.n[0];
-    const T* L = lds + tr * R * SW;
+    const int ubase = (uz * G.n[1] + uy) * Nx;
+    const T* Lrow = lds + (size_t)tr * SW * RS;
     const size_t kbase = (size_t)vr * G.nv1;
-    const T lam = (T)G.lam, mu = (T)G.mu;
     const T vyT = (T)vy, vzT = (T)vz;
+    const T hrowT = (T)hrow;
     double aK0 = 0.0, aK1 = 0.0, aK2 = 0.0, aE0 = 0.0, aE1 = 0.0, aE2 = 0.0;
 
-    for (int ix = 0; ix < G.nv1; ++ix) {
-      const int kx = ix - G.kofs;
-      const double vx = kx * G.dv;
-      const int li = tx - kx + lofs;
-      const int xs = map_near(x - kx, G.n[0], G.bc[0]);
-      const size_t plane = (kbase + ix) * (size_t)G.nc;
-      const T g = g_in[plane + ubase + xs];
-      const T vxT = (T)vx;
-      const T vhT = (T)(hrow + 0.5 * vx * vx);
-      // pending correction + relaxation poly p.m(v)
-      T pp = L[(NM + 0) * SW + li] + L[(NM + 1) * SW + li] * vxT;
-      if (D >= 2) pp += L[(NM + 2) * SW + li] * vyT;
-      if (D >= 3) pp += L[(NM + 3) * SW + li] * vzT;
-      pp += L[(2 * NM - 1) * SW + li] * vhT;
-      T fs;
-      if (FT) {
-        fs = g + pp;
-      } else {
-        T q = (vxT - L[1 * SW + li]) * (vxT - L[1 * SW + li]);
-        if (D >= 2) q += (vyT - L[2 * SW + li]) * (vyT - L[2 * SW + li]);
-        if (D >= 3) q += (vzT - L[3 * SW + li]) * (vzT - L[3 * SW + li]);
-        const T M = fast_exp<T>(L[0 * SW + li] - L[(D + 1) * SW + li] * q);
-        T pe = L[(2 * NM + 0) * SW + li] + L[(2 * NM + 1) * SW + li] * vxT;
-        if (D >= 2) pe += L[(2 * NM + 2) * SW + li] * vyT;
-        if (D >= 3) pe += L[(2 * NM + 3) * SW + li] * vzT;
-        pe += L[(3 * NM - 1) * SW + li] * vhT;
-        const T E = M + pe;
-        fs = lam * g + (mu * M + pp);
-        const double Ed = (double)E;
-        aE0 += Ed;
-        aE1 += vx * Ed;
-        aE2 += (vx * vx) * Ed;
+    for (int ix0 = 0; ix0 < G.nv1; ix0 += UNR) {
+      T gv[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int ix = ix0 + u;
+        const int kx = ix - G.kofs;
+        const T* gp = a.g_in + (kbase + ix) * (size_t)G.nc;
+        gv[u] = gp[ubase + map_x<BCX>(xN, kx, Nx)];
       }
-      g_out[plane + dest] = fs;
-      const double fd = (double)fs;
-      aK0 += fd;
-      aK1 += vx * fd;
-      aK2 += (vx * vx) * fd;
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int ix = ix0 + u;
+        const int kx = ix - G.kofs;
+        const VelNode vn = a.vt[ix];
+        const double vx = vn.v;
+        const T vxT = (sizeof(T) == 4) ? (T)vn.vf : (T)vn.v;
+        const T vhT = (sizeof(T) == 4) ? (T)(hrowT + (T)vn.v2hf) : (T)(hrow + 0.5 * vn.v2);
+        const V* rp = reinterpret_cast<const V*>(Lrow + (tx - kx + lofs) * RS);
+        T rv[NCH * PER16];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          const V t = rp[c];
+          if constexpr (sizeof(T) == 8) {
+            rv[2 * c] = t.x;
+            rv[2 * c + 1] = t.y;
+          } else {
+            rv[4 * c] = t.x;
+            rv[4 * c + 1] = t.y;
+            rv[4 * c + 2] = t.z;
+            rv[4 * c + 3] = t.w;
+          }
+        }
+        // record: [lp, u_1..u_D, beta | p_0..p_{D+1} | e_0..e_{D+1}]
+        T pp = rv[NM + 0] + rv[NM + 1] * vxT;
+        if (D >= 2) pp += rv[NM + 2] * vyT;
+        if (D >= 3) pp += rv[NM + 3] * vzT;
+        pp += rv[2 * NM - 1] * vhT;
+        const T g = gv[u];
+        T fs;
+        if (FT) {
+          fs = g + pp;
+        } else {
+          const T dx_ = vxT - rv[1];
+          T q = dx_ * dx_;
+          if (D >= 2) {
+            const T dy_ = vyT - rv[2];
+            q += dy_ * dy_;
+          }
+          if (D >= 3) {
+            const T dz_ = vzT - rv[3];
+            q += dz_ * dz_;
+          }
+          const T M = fast_exp<T>(rv[0] - rv[D + 1] * q);
+          T pe = rv[2 * NM + 0] + rv[2 * NM + 1] * vxT;
+          if (D >= 2) pe += rv[2 * NM + 2] * vyT;
+          if (D >= 3) pe += rv[2 * NM + 3] * vzT;
+          pe += rv[3 * NM - 1] * vhT;
+          const T E = M + pe;
+          fs = lam * g + (mu * M + pp);
+          const double Ed = (double)E;
+          aE0 += Ed;
+          aE1 += vx * Ed;
+          aE2 += vn.v2 * Ed;
+        }
+        T* op = a.g_out + (kbase + ix) * (size_t)G.nc;
+        op[dest] = fs;
+        const double fd = (double)fs;
+        aK0 += fd;
+        aK1 += vx * fd;
+        aK2 += vn.v2 * fd;
+      }
     }
     // fold the row into the totals: m = (1, v_x, v_y, v_z, |v|^2/2)
-    double rk[NM], re[NM];
+    double rk[NM + 2], re[NM + 2];  // padded: the D >= 3 branch indexes [3]
     rk[0] = aK0;
     rk[1] = aK1;
     re[0] = aE0;
@@ -366,85 +637,118 @@ __global__ __launch_bounds__(256) void k_kinetic(const T* __restrict__ g_in,
       }
     }
   }
-  if (!active) return;
-  double* P = part + (size_t)chunk * 2 * NM * G.nc;
+  if (active) {
+    double* P = a.part + (size_t)chunk * 2 * NM * G.nc;
 #pragma unroll
-  for (int r = 0; r < NM; ++r) {
-    P[(size_t)r * G.nc + dest] = COMP ? SK[r] + CK[r] : SK[r];
-    if (!FT) P[(size_t)(NM + r) * G.nc + dest] = COMP ? SE[r] + CE[r] : SE[r];
+    for (int r = 0; r < NM; ++r) {
+      P[(size_t)r * G.nc + dest] = COMP ? SK[r] + CK[r] : SK[r];
+      if (!FT) P[(size_t)(NM + r) * G.nc + dest] = COMP ? SE[r] + CE[r] : SE[r];
+    }
+  }
+
+  // ------------------------------------------------ last chunk of the tile
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int old = atomicAdd(a.tile_cnt + tile, 1);
+    s_last = (old == a.nchunk - 1);
+    if (s_last) atomicExch(a.tile_cnt + tile, 0);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+
+  const bool need_eq = G.mu != 0.0;
+  int s = 0;
+  if (EUL) {
+    unsigned* ctrl = reinterpret_cast<unsigned*>(a.set_r + (SMAX + 1) * ASTR);
+    if (threadIdx.x == 0) spin_until_geq(ctrl + 1, 1u, a.flag);
+    __syncthreads();
+    __threadfence();
+    bool over;
+    s = substeps<D>(a.set_r, G, a.s_cap, &over);
+  }
+  bool phys = true;
+  double speed[3] = {0.0, 0.0, 0.0};
+  if (active) {
+    double SKt[NM], SEt[NM];
+#pragma unroll
+    for (int r = 0; r < NM; ++r) SKt[r] = SEt[r] = 0.0;
+    for (int c = 0; c < a.nchunk; ++c) {
+      const double* P = a.part + (size_t)c * 2 * NM * G.nc;
+#pragma unroll
+      for (int r = 0; r < NM; ++r) {
+        SKt[r] += P[(size_t)r * G.nc + dest];
+        if (!FT) SEt[r] += P[(size_t)(NM + r) * G.nc + dest];
+      }
+    }
+    double delta[NM];
+#pragma unroll
+    for (int r = 0; r < NM; ++r) delta[r] = 0.0;
+    if (EUL) {
+      const double* UEs = (s & 1) ? a.UE1 : a.UE0;
+#pragma unroll
+      for (int r = 0; r < NM; ++r) {
+        const double UM = G.mu * (G.w * SEt[r]);
+        const double UEv = G.mu * UEs[(size_t)r * G.nc + dest];
+        delta[r] = UEv - UM;
+      }
+    }
+    double Un[NM], cfv[NM];
+#pragma unroll
+    for (int r = 0; r < NM; ++r) Un[r] = G.w * SKt[r] + delta[r];
+#pragma unroll
+    for (int r = 0; r < NM; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int s2 = 0; s2 < NM; ++s2) acc += A.a[r * NM + s2] * delta[s2];
+      cfv[r] = acc;
+    }
+    phys = cell_record<D, T>(Un, cfv, G, A, a.vt, a.rec_out + (size_t)dest * RS, speed);
+#pragma unroll
+    for (int r = 0; r < NM; ++r) {
+      a.U_out[(size_t)r * G.nc + dest] = Un[r];
+      a.cf[(size_t)r * G.nc + dest] = cfv[r];
+    }
+  }
+  if (active && need_eq && !phys) atomicOr(a.flag, FLAG_NONPHYS);
+  if (EUL) {
+#pragma unroll
+    for (int d2 = 0; d2 < D; ++d2) {
+      const double m = wave_max(phys ? speed[d2] : 0.0);
+      if ((threadIdx.x & 63) == 0) atomic_max_pos(a.set_w + d2, m);
+    }
   }
 }
 
-// =============================================================== cell update
-// Per cell: sums of the velocity chunks -> U_K, U_M; delta = U_E - U_M;
-// U^{n+1} = U_K + delta (= U_* + U_E); cf = A delta; then the record of the
-// new state (Maxwellian parameters, separable discrete moments C M, cE) and
-// the Lax-Friedrichs speeds of U^{n+1} for the next Euler solve.
+// ======================================================= set-up / refresh
+// MODE_INIT: U given, the pieces g hold sampled values with sums S (chunk 0
+// of part): project onto U as in eq. (minim1), cf = A (U - w S).
+// MODE_INIT_FROM_SUMS: U = w S (cf = 0).  MODE_REFRESH: U and cf given
+// (after a change of tau).  Writes the record and the speeds of U (row 0 of
+// `set`).
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_cell_update(
-    double* __restrict__ U, double* __restrict__ cf, double* __restrict__ rec,
-    T* __restrict__ recT, const double* __restrict__ part, int nchunk,
-    const double* __restrict__ UE0, const double* __restrict__ UE1, double* __restrict__ slots,
-    int set, int aset, int s_cap, int* __restrict__ flag, Geom G, Mat A, int mode, int fks) {
+__global__ __launch_bounds__(256) void k_cell_init(double* __restrict__ U, double* __restrict__ cf,
+                                                   T* __restrict__ rec,
+                                                   const VelNode* __restrict__ vt,
+                                                   const double* __restrict__ part,
+                                                   double* __restrict__ set, int* __restrict__ flag,
+                                                   Geom G, Mat A, int mode) {
   constexpr int NM = D + 2;
+  constexpr int RS = rec_stride<D, T>();
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = j < G.nc;
-  const bool need_eq = G.mu != 0.0;
   bool phys = true;
   double speed[3] = {0.0, 0.0, 0.0};
   if (act) {
     double Un[NM], cfv[NM];
-    if (mode == MODE_STEP) {
-      double SK[NM], SE[NM];
-#pragma unroll
-      for (int r = 0; r < NM; ++r) SK[r] = SE[r] = 0.0;
-      for (int c = 0; c < nchunk; ++c) {
-        const double* P = part + (size_t)c * 2 * NM * G.nc;
-#pragma unroll
-        for (int r = 0; r < NM; ++r) {
-          SK[r] += P[(size_t)r * G.nc + j];
-          if (need_eq) SE[r] += P[(size_t)(NM + r) * G.nc + j];
-        }
-      }
-      double delta[NM];
-      if (!need_eq) {
-#pragma unroll
-        for (int r = 0; r < NM; ++r) delta[r] = 0.0;
-      } else if (fks) {
-#pragma unroll
-        for (int r = 0; r < NM; ++r) delta[r] = 0.0;
-      } else {
-        bool over;
-        const int s = substeps<D>(slots + (size_t)set * (SMAX + 1) * SLOT_STRIDE, G, s_cap, &over);
-        if (over && j == 0) atomicOr(flag, FLAG_SUBSTEP);
-        if (j == 0) flag[1] = s;
-        const double* UEs = (s & 1) ? UE1 : UE0;
-#pragma unroll
-        for (int r = 0; r < NM; ++r) {
-          double UM = G.mu * (G.w * SE[r]);
-          double UEv = G.mu * UEs[(size_t)r * G.nc + j];
-          delta[r] = UEv - UM;
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < NM; ++r) Un[r] = G.w * SK[r] + delta[r];
-#pragma unroll
-      for (int r = 0; r < NM; ++r) {
-        double acc = 0.0;
-#pragma unroll
-        for (int s2 = 0; s2 < NM; ++s2) acc += A.a[r * NM + s2] * delta[s2];
-        cfv[r] = acc;
-      }
-    } else if (mode == MODE_REFRESH) {
+    if (mode == MODE_REFRESH) {
 #pragma unroll
       for (int r = 0; r < NM; ++r) {
         Un[r] = U[(size_t)r * G.nc + j];
         cfv[r] = cf[(size_t)r * G.nc + j];
       }
     } else {
-      // MODE_INIT: U given; MODE_INIT_FROM_SUMS: U = w S.  The pieces g hold
-      // sampled values whose sums S are in chunk 0 of part; project them onto
-      // U as in eq. (minim1): cf = A (U - w S).
       double S[NM];
 #pragma unroll
       for (int r = 0; r < NM; ++r) {
@@ -459,97 +763,18 @@ __global__ __launch_bounds__(256) void k_cell_update(
         cfv[r] = acc;
       }
     }
-
-    // Maxwellian parameters of U^{n+1} (eq. M with theta from eq. E)
-    const double rho = Un[0];
-    double u[3] = {0.0, 0.0, 0.0}, usq = 0.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      u[a] = Un[1 + a] / rho;
-      usq += u[a] * u[a];
-    }
-    const double th = (2.0 * Un[NM - 1] - rho * usq) / (D * rho);
-    phys = (rho > 0.0) && (th > 0.0) && isfinite(rho) && isfinite(th) && isfinite(usq);
-    double lp = 0.0, beta = 0.0, cE[NM];
-#pragma unroll
-    for (int r = 0; r < NM; ++r) cE[r] = 0.0;
-    if (phys) {
-      beta = 0.5 / th;
-      const double pref = rho * pow(2.0 * M_PI * th, -0.5 * D);
-      lp = log(rho) - 0.5 * D * log(2.0 * M_PI * th);
-      // separable discrete moments of the Maxwellian: sums along each axis
-      double G0[3], G1[3], G2[3];
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int i = 0; i < G.nv1; ++i) {
-          const double v = (i - G.kofs) * G.dv;
-          const double e = exp(-beta * (v - u[a]) * (v - u[a]));
-          s0 += e;
-          s1 += v * e;
-          s2 += v * v * e;
-        }
-        G0[a] = s0;
-        G1[a] = s1;
-        G2[a] = s2;
-      }
-      double CM[NM];
-      double all0 = 1.0;
-#pragma unroll
-      for (int a = 0; a < D; ++a) all0 *= G0[a];
-      CM[0] = G.w * pref * all0;
-      double en = 0.0;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        double oth = 1.0;
-#pragma unroll
-        for (int b2 = 0; b2 < D; ++b2)
-          if (b2 != a) oth *= G0[b2];
-        CM[1 + a] = G.w * pref * G1[a] * oth;
-        en += G2[a] * oth;
-      }
-      CM[NM - 1] = G.w * pref * 0.5 * en;
-#pragma unroll
-      for (int r = 0; r < NM; ++r) {
-        double acc = 0.0;
-#pragma unroll
-        for (int s2 = 0; s2 < NM; ++s2) acc += A.a[r * NM + s2] * (Un[s2] - CM[s2]);
-        cE[r] = acc;
-      }
-      const double p = rho * th;
-#pragma unroll
-      for (int a = 0; a < D; ++a) speed[a] = fabs(u[a]) + sqrt(G.gam * p / rho);
-    }
-    // record
-    double rv[3 * NM];
-    rv[0] = lp;
-#pragma unroll
-    for (int a = 0; a < D; ++a) rv[1 + a] = u[a];
-    rv[D + 1] = beta;
-#pragma unroll
-    for (int r = 0; r < NM; ++r) {
-      rv[NM + r] = need_eq ? G.w * (G.lam * cfv[r] + G.mu * cE[r]) : G.w * (G.lam * cfv[r]);
-      rv[2 * NM + r] = G.w * cE[r];
-    }
+    phys = cell_record<D, T>(Un, cfv, G, A, vt, rec + (size_t)j * RS, speed);
 #pragma unroll
     for (int r = 0; r < NM; ++r) {
       U[(size_t)r * G.nc + j] = Un[r];
       cf[(size_t)r * G.nc + j] = cfv[r];
     }
-#pragma unroll
-    for (int q = 0; q < 3 * NM; ++q) {
-      rec[(size_t)q * G.nc + j] = rv[q];
-      if (recT != nullptr) recT[(size_t)q * G.nc + j] = (T)rv[q];
-    }
   }
-  if (act && (need_eq || mode == MODE_INIT) && !phys) atomicOr(flag, FLAG_NONPHYS);
-  if (need_eq && !fks) {
+  if (act && (G.mu != 0.0 || mode == MODE_INIT) && !phys) atomicOr(flag, FLAG_NONPHYS);
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      double m = wave_max(phys ? speed[a] : 0.0);
-      if ((threadIdx.x & 63) == 0)
-        atomic_max_pos(slots + (size_t)aset * (SMAX + 1) * SLOT_STRIDE + a, m);
-    }
+  for (int d2 = 0; d2 < D; ++d2) {
+    const double m = wave_max(phys ? speed[d2] : 0.0);
+    if ((threadIdx.x & 63) == 0) atomic_max_pos(set + d2, m);
   }
 }
 
@@ -574,7 +799,8 @@ __global__ void k_prim_to_moments(const double* __restrict__ prim, double* __res
 
 // g(j,k) = M_k of cell j (the pointwise Maxwellian of the record)
 template <int D, typename T>
-__global__ void k_fill_maxwellian(T* __restrict__ g, const double* __restrict__ rec, Geom G) {
+__global__ void k_fill_maxwellian(T* __restrict__ g, const T* __restrict__ rec, Geom G) {
+  constexpr int RS = rec_stride<D, T>();
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)G.nv * G.nc) return;
   const int j = (int)(idx % G.nc);
@@ -584,10 +810,10 @@ __global__ void k_fill_maxwellian(T* __restrict__ g, const double* __restrict__ 
   for (int a = 0; a < D; ++a) {
     const double v = (k % G.nv1 - G.kofs) * G.dv;
     k /= G.nv1;
-    const double d = v - rec[(size_t)(1 + a) * G.nc + j];
+    const double d = v - (double)rec[(size_t)j * RS + 1 + a];
     q += d * d;
   }
-  g[idx] = (T)exp(rec[j] - rec[(size_t)(D + 1) * G.nc + j] * q);
+  g[idx] = (T)exp((double)rec[(size_t)j * RS] - (double)rec[(size_t)j * RS + D + 1] * q);
 }
 
 // S_r(j) = sum_k m_k[r] g(j,k) into part chunk 0

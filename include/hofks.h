@@ -117,6 +117,36 @@ double hofks_dt(const hofks_ctx *ctx);
 const char *hofks_last_error(const hofks_ctx *ctx);
 void hofks_destroy(hofks_ctx *ctx);
 
+/* ------------------------------------------------------------- batches
+ * Many independent 1D-1V tubes (dim 1, outflow, precision 1, scheme 0; n_vel
+ * a multiple of 8), each with its own cells, dx, velocity grid, dt = dx/dv
+ * and relaxation time, advanced together: one persistent launch per step
+ * pulls per-tube Euler solves and per-segment kinetic work from a queue, and
+ * hofks_step replays a captured graph of consecutive launches.  The same
+ * calls as above apply to a batch context with concatenated host arrays:
+ *   hofks_set_state_macro  rho, u, theta of tube 0 cells, then tube 1, ...
+ *   hofks_read_moments     per tube 3 x Nx_i (component-major), concatenated
+ *   hofks_read_f           per tube n_vel_i x Nx_i, concatenated
+ * hofks_set_tau and hofks_set_state_f return HOFKS_EINVAL for a batch.  A
+ * tube that meets a non-physical state is flagged and keeps running; its
+ * flag is read with hofks_batch_tube_flags and the synchronising calls still
+ * succeed, so the other tubes stay readable. */
+hofks_status hofks_batch_workspace_size(const hofks_grid_desc *descs, int n,
+                                        size_t *bytes);
+/* taus[n]: per-tube tau (> 0, +INF or 0); other arguments as hofks_create. */
+hofks_status hofks_batch_create(const hofks_grid_desc *descs, const double *taus,
+                                int n, void *dev_ws, size_t ws_bytes,
+                                void *hip_stream, hofks_ctx **out);
+/* Per-tube error bits (1 non-physical, 2 sub-step cap) to host flags[n]. */
+hofks_status hofks_batch_tube_flags(hofks_ctx *ctx, int *flags);
+/* Choose the kinetic item width and the persistent grid of a batch by timing
+ * `steps` steps per candidate on the current state, which is advanced (set
+ * the state again afterwards).  cache_path (may be NULL) is a JSON-lines file
+ * of earlier choices keyed by the batch shape; a match skips the timing, a
+ * new choice is appended.  choice[2] (may be NULL) gets (cells, grid). */
+hofks_status hofks_autotune(hofks_ctx *ctx, int steps, const char *cache_path,
+                            int choice[2]);
+
 #ifdef __cplusplus
 }
 #endif

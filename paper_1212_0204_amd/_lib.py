@@ -17,7 +17,8 @@ STATUS_NAMES = {0: "HOFKS_OK", -1: "HOFKS_EINVAL", -2: "HOFKS_ESIZE", -3: "HOFKS
 SYMBOLS = [
     "hofks_workspace_size", "hofks_create", "hofks_set_tau", "hofks_set_state_macro",
     "hofks_set_state_f", "hofks_step", "hofks_sync", "hofks_read_moments", "hofks_read_f",
-    "hofks_read_counters", "hofks_kernel_timing", "hofks_dt", "hofks_last_error", "hofks_destroy",
+    "hofks_read_counters", "hofks_kernel_timing", "hofks_dt", "hofks_batch_workspace_size",
+    "hofks_batch_create", "hofks_batch_tube_flags", "hofks_autotune", "hofks_last_error", "hofks_destroy",
 ]
 
 
@@ -53,6 +54,10 @@ def lib():
     L.hofks_read_f.argtypes = [vp, dp, sz]
     L.hofks_read_counters.argtypes = [vp, P(i), P(ctypes.c_long)]
     L.hofks_kernel_timing.argtypes = [vp, i, dp, P(i)]
+    L.hofks_batch_workspace_size.argtypes = [P(GridDesc), i, P(sz)]
+    L.hofks_batch_create.argtypes = [P(GridDesc), dp, i, vp, sz, vp, P(vp)]
+    L.hofks_batch_tube_flags.argtypes = [vp, P(i)]
+    L.hofks_autotune.argtypes = [vp, i, ctypes.c_char_p, P(i)]
     L.hofks_dt.argtypes = [vp]
     L.hofks_dt.restype = d
     L.hofks_last_error.argtypes = [vp]

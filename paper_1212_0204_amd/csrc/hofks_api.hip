@@ -11,12 +11,17 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <numeric>
+#include <sstream>
+#include <string>
 #include <new>
 #include <type_traits>
 #include <utility>
 #include <vector>
 
 #include "hofks.h"
+#include "batch.hpp"
 #include "kernels.hpp"
 
 using namespace hofks;
@@ -223,8 +228,13 @@ struct hofks_ctx {
   // optional per-kernel timing: hipEvents around each launch group
   bool timing;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;  // (group, start, stop)
+  struct MarkRec {
+    int group, count;
+    hipEvent_t a, b;
+  };
+  std::vector<MarkRec> ev_marks;
   size_t ev_next;
+  struct Batch* batch;  // non-null for a batch of independent tubes
   char err[512];
 };
 
@@ -260,9 +270,9 @@ hipEvent_t next_event(hofks_ctx* c) {
 
 struct Mark {
   hofks_ctx* c;
-  int group;
+  int group, count;
   hipEvent_t a = nullptr;
-  Mark(hofks_ctx* c_, int g) : c(c_), group(g) {
+  Mark(hofks_ctx* c_, int g, int n = 1) : c(c_), group(g), count(n) {
     if (c->timing) {
       a = next_event(c);
       if (a) (void)hipEventRecord(a, c->stream);
@@ -273,7 +283,7 @@ struct Mark {
       hipEvent_t b = next_event(c);
       if (b) {
         (void)hipEventRecord(b, c->stream);
-        c->ev_marks.push_back({group, {a, b}});
+        c->ev_marks.push_back({group, count, a, b});
       }
     }
   }
@@ -445,6 +455,14 @@ hofks_status reset_counters(hofks_ctx* c) {
   return zero_doubles(c, c->slots, 3 * (size_t)SET_D);
 }
 
+// batch helpers (defined with the batch code below)
+hofks_status batch_set_state(hofks_ctx*, const double*, const double*, const double*);
+hofks_status batch_step(hofks_ctx*, int, bool);
+hofks_status batch_read_flag(hofks_ctx*);
+hofks_status batch_read_moments(hofks_ctx*, double*);
+hofks_status batch_read_f(hofks_ctx*, double*, size_t);
+hofks_status batch_max_substeps(hofks_ctx*, int*);
+double batch_dt(const hofks_ctx*);
 }  // namespace
 
 // ====================================================================== ABI
@@ -512,6 +530,7 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
 
 hofks_status hofks_set_tau(hofks_ctx* c, double tau) {
   if (!c) return HOFKS_EINVAL;
+  if (c->batch) return fmt_err(c->err, "tube relaxation times are fixed at creation"), HOFKS_EINVAL;
   if (!(tau >= 0.0)) return fmt_err(c->err, "tau must be >= 0 or +inf"), HOFKS_EINVAL;
   c->tau = tau;
   Geom& G = c->P.G;
@@ -532,6 +551,7 @@ hofks_status hofks_set_tau(hofks_ctx* c, double tau) {
 hofks_status hofks_set_state_macro(hofks_ctx* c, const double* rho, const double* u,
                                    const double* theta) {
   if (!c || !rho || !theta || !u) return HOFKS_EINVAL;
+  if (c->batch) return batch_set_state(c, rho, u, theta);
   const Plan& P = c->P;
   const size_t nc = P.G.nc;
   hofks_status st = reset_counters(c);
@@ -570,6 +590,7 @@ hofks_status hofks_set_state_macro(hofks_ctx* c, const double* rho, const double
 
 hofks_status hofks_set_state_f(hofks_ctx* c, const double* f, size_t bytes) {
   if (!c || !f) return HOFKS_EINVAL;
+  if (c->batch) return fmt_err(c->err, "not available for batches"), HOFKS_EINVAL;
   const Plan& P = c->P;
   const size_t nc = P.G.nc, tot = (size_t)P.G.nv * nc;
   if (bytes < tot * 8) return HOFKS_ESIZE;
@@ -608,6 +629,7 @@ hofks_status hofks_set_state_f(hofks_ctx* c, const double* f, size_t bytes) {
 hofks_status hofks_step(hofks_ctx* c, int n) {
   if (!c || n < 0) return HOFKS_EINVAL;
   if (!c->ready) return fmt_err(c->err, "set the state before stepping"), HOFKS_ESTATE;
+  if (c->batch) return batch_step(c, n, true);
   return dispatch(c, [&](auto D, auto t) {
     return step_impl<decltype(D)::value, decltype(t)>(c, n);
   });
@@ -615,11 +637,13 @@ hofks_status hofks_step(hofks_ctx* c, int n) {
 
 hofks_status hofks_sync(hofks_ctx* c) {
   if (!c) return HOFKS_EINVAL;
+  if (c->batch) return batch_read_flag(c);
   return read_flag(c);
 }
 
 hofks_status hofks_read_moments(hofks_ctx* c, double* U) {
   if (!c || !U) return HOFKS_EINVAL;
+  if (c->batch) return batch_read_moments(c, U);
   HIPCHK(c, hipMemcpyAsync(U, c->U[rpar(c)], (size_t)c->P.nm * c->P.G.nc * 8,
                            hipMemcpyDeviceToHost, c->stream));
   return read_flag(c);
@@ -627,6 +651,7 @@ hofks_status hofks_read_moments(hofks_ctx* c, double* U) {
 
 hofks_status hofks_read_f(hofks_ctx* c, double* f, size_t bytes) {
   if (!c || !f) return HOFKS_EINVAL;
+  if (c->batch) return batch_read_f(c, f, bytes);
   const Plan& P = c->P;
   const size_t nc = P.G.nc, tot = (size_t)P.G.nv * nc;
   if (bytes < tot * 8) return HOFKS_ESIZE;
@@ -652,8 +677,13 @@ hofks_status hofks_read_f(hofks_ctx* c, double* f, size_t bytes) {
 hofks_status hofks_read_counters(hofks_ctx* c, int* substeps, long* steps) {
   if (!c) return HOFKS_EINVAL;
   int h[2] = {0, 0};
-  HIPCHK(c, hipMemcpyAsync(h, c->flag, sizeof(h), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->batch) {
+    hofks_status st = batch_max_substeps(c, h + 1);
+    if (st) return st;
+  } else {
+    HIPCHK(c, hipMemcpyAsync(h, c->flag, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
   if (substeps) *substeps = h[1];
   if (steps) *steps = c->steps;
   return HOFKS_OK;
@@ -667,9 +697,9 @@ hofks_status hofks_kernel_timing(hofks_ctx* c, int enable, double* ms, int* laun
     int cnt[3] = {0, 0, 0};
     for (auto& m : c->ev_marks) {
       float t = 0.0f;
-      HIPCHK(c, hipEventElapsedTime(&t, m.second.first, m.second.second));
-      acc[m.first] += t;
-      cnt[m.first] += 1;
+      HIPCHK(c, hipEventElapsedTime(&t, m.a, m.b));
+      acc[m.group] += t;
+      cnt[m.group] += m.count;
     }
     for (int g = 0; g < 3; ++g) {
       if (ms) ms[g] = acc[g];
@@ -682,14 +712,633 @@ hofks_status hofks_kernel_timing(hofks_ctx* c, int enable, double* ms, int* laun
   return HOFKS_OK;
 }
 
-double hofks_dt(const hofks_ctx* c) { return c ? c->P.G.dt : 0.0; }
+double hofks_dt(const hofks_ctx* c) {
+  if (!c) return 0.0;
+  return c->batch ? batch_dt(c) : c->P.G.dt;
+}
 
 const char* hofks_last_error(const hofks_ctx* c) { return c ? c->err : "null context"; }
 
-void hofks_destroy(hofks_ctx* c) {
-  if (!c) return;
-  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-  delete c;
+}  // extern "C"
+
+// ================================================================== batches
+// A batch of independent 1D-1V outflow tubes in FP32 pieces.  Host-side plan:
+// per-tube offsets into four arenas (pieces, records, FP64 moments, velocity
+// nodes), the Euler/kinetic work order, the tuned item width and grid, and a
+// captured graph of consecutive step launches.
+struct Batch {
+  int n = 0;
+  std::vector<hofks_grid_desc> descs;
+  std::vector<double> taus;
+  std::vector<TubeDev> tubes;
+  long long g_floats = 0, r_floats = 0, d_doubles = 0;
+  int nvt = 0, items_max = 0;
+  long long total_cells = 0, total_cv = 0;
+  size_t off_gar = 0, off_rar = 0, off_dar = 0, off_vt = 0, off_tubes = 0, off_order = 0,
+         off_items = 0, off_queue = 0, off_alpha = 0, off_done = 0, off_s = 0, off_tflag = 0,
+         off_flag = 0, total = 0;
+  // device pointers
+  float *gar = nullptr, *rar = nullptr;
+  double *dar = nullptr, *alpha = nullptr;
+  VelNode* vtar = nullptr;
+  TubeDev* tubes_d = nullptr;
+  int *order = nullptr, *queue = nullptr, *done = nullptr, *tube_s = nullptr, *tflag = nullptr,
+      *flag = nullptr;
+  int2* items = nullptr;
+  // launch configuration
+  int cells = 256, grid = 0, unr = 8, nitems = 0, ncu = 256;
+  size_t lds = 0;
+  // graph of GRAPH_STEPS launches starting at parity 0
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_cells = 0, graph_grid = 0;
+};
+
+namespace {
+
+constexpr int GRAPH_STEPS = 16;
+
+hofks_status batch_plan(const hofks_grid_desc* descs, const double* taus, int n, Batch* B,
+                        char* err) {
+  if (!descs || n < 1 || n > (1 << 20)) return fmt_err(err, "bad tube count"), HOFKS_EINVAL;
+  B->n = n;
+  B->descs.assign(descs, descs + n);
+  B->taus.assign(n, INFINITY);
+  if (taus) B->taus.assign(taus, taus + n);
+  B->tubes.resize(n);
+  long long go = 0, ro = 0, dof = 0;
+  int vto = 0, nitems = 0;
+  constexpr int RS = rec_stride<1, float>();
+  for (int i = 0; i < n; ++i) {
+    const hofks_grid_desc& d = descs[i];
+    if (d.dim != 1 || d.precision != 1 || d.bc[0] != 1 || d.scheme != 0)
+      return fmt_err(err, "tube %d: batches hold 1D outflow HOFKS tubes in FP32", i), HOFKS_EINVAL;
+    Plan P;
+    hofks_status st = make_plan(&d, &P, err);
+    if (st) return st;
+    if (d.n_vel % 8 != 0 || d.n_vel > 256)
+      return fmt_err(err, "tube %d: n_vel must be a multiple of 8", i), HOFKS_EINVAL;
+    const double tau = B->taus[i];
+    if (!(tau >= 0.0)) return fmt_err(err, "tube %d: tau must be >= 0 or +inf", i), HOFKS_EINVAL;
+    TubeDev& T = B->tubes[i];
+    const long long Nx = P.G.n[0], nv = P.G.nv1;
+    T.g[0] = go;
+    T.g[1] = go + nv * Nx;
+    go += 2 * nv * Nx;
+    T.rec[0] = ro;
+    T.rec[1] = ro + RS * Nx;
+    ro += 2 * RS * Nx;
+    T.U[0] = dof;
+    T.U[1] = dof + 3 * Nx;
+    T.UE[0] = dof + 6 * Nx;
+    T.UE[1] = dof + 9 * Nx;
+    T.cf = dof + 12 * Nx;
+    dof += 15 * Nx;
+    T.vt = vto;
+    vto += (int)nv;
+    T.Nx = (int)Nx;
+    T.nv1 = (int)nv;
+    T.kofs = P.G.kofs;
+    T.dx = P.G.dx;
+    T.dv = P.G.dv;
+    T.dt = P.G.dt;
+    T.w = P.G.w;
+    T.gam = P.G.gam;
+    if (std::isinf(tau)) {
+      T.lam = 1.0;
+      T.mu = 0.0;
+    } else if (tau == 0.0) {
+      T.lam = 0.0;
+      T.mu = 1.0;
+    } else {
+      T.lam = std::exp(-T.dt / tau);
+      T.mu = -std::expm1(-T.dt / tau);
+    }
+    for (int q = 0; q < 9; ++q) T.A[q] = P.A.a[q];
+    nitems += (int)((Nx + 127) / 128);
+    B->total_cells += Nx;
+    B->total_cv += Nx * nv;
+  }
+  B->g_floats = go;
+  B->r_floats = ro;
+  B->d_doubles = dof;
+  B->nvt = vto;
+  B->items_max = nitems;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  B->off_gar = take(sizeof(float) * go);
+  B->off_rar = take(sizeof(float) * ro);
+  B->off_dar = take(sizeof(double) * dof);
+  B->off_vt = take(sizeof(VelNode) * vto);
+  B->off_tubes = take(sizeof(TubeDev) * n);
+  B->off_order = take(sizeof(int) * n);
+  B->off_items = take(sizeof(int2) * nitems);
+  B->off_queue = take(64);
+  B->off_alpha = take(sizeof(double) * n * 2 * ASTR);
+  B->off_done = take(sizeof(int) * n * 2);
+  B->off_s = take(sizeof(int) * n);
+  B->off_tflag = take(sizeof(int) * n);
+  B->off_flag = take(64);
+  B->total = off;
+  return HOFKS_OK;
+}
+
+Geom host_tube_geom(const TubeDev& T) {
+  Geom G{};
+  G.n[0] = T.Nx;
+  G.n[1] = G.n[2] = 1;
+  G.nc = T.Nx;
+  G.nv1 = T.nv1;
+  G.kofs = T.kofs;
+  G.nv = T.nv1;
+  G.bc[0] = 1;
+  G.dx = T.dx;
+  G.dv = T.dv;
+  G.dt = T.dt;
+  G.w = T.w;
+  G.lam = T.lam;
+  G.mu = T.mu;
+  G.gam = T.gam;
+  return G;
+}
+
+int unroll_for(const Batch* B, int cells) {
+  const int vg = 1024 / cells;
+  int u = 8;
+  for (const TubeDev& T : B->tubes) {
+    const int per = T.nv1 / vg;
+    while (u > 1 && per % u) u /= 2;
+  }
+  return u;
+}
+
+size_t lds_for(const Batch* B, int cells) {
+  int nvmax = 0;
+  for (const TubeDev& T : B->tubes) nvmax = std::max(nvmax, T.nv1);
+  const size_t recb = (size_t)(cells + nvmax - 1) * rec_stride<1, float>() * sizeof(float);
+  const size_t redb = (size_t)(1024 / cells - 1) * cells * 6 * sizeof(double);
+  return std::max(recb, redb);
+}
+
+// work order: Euler items by decreasing Nx * s, kinetic items by decreasing
+// per-item work (n_v), both on the host from the speeds of U^n
+hofks_status batch_order(hofks_ctx* c) {
+  Batch* B = c->batch;
+  std::vector<double> al((size_t)B->n * 2 * ASTR);
+  HIPCHK(c, hipMemcpyAsync(al.data(), B->alpha, al.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int p = (int)(c->steps & 1);
+  std::vector<double> work(B->n);
+  for (int i = 0; i < B->n; ++i) {
+    const TubeDev& T = B->tubes[i];
+    const double s = std::max(1.0, std::ceil(2.0 * T.dt * al[((size_t)i * 2 + p) * ASTR] / T.dx));
+    work[i] = (double)T.Nx * s;
+  }
+  std::vector<int> order(B->n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  std::vector<int2> items;
+  for (int i : order) {
+    const TubeDev& T = B->tubes[i];
+    for (int sg = 0; sg * B->cells < T.Nx; ++sg) items.push_back(make_int2(i, sg));
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [&](const int2& a, const int2& b) { return B->tubes[a.x].nv1 > B->tubes[b.x].nv1; });
+  B->nitems = (int)items.size();
+  HIPCHK(c, hipMemcpyAsync(B->order, order.data(), sizeof(int) * B->n, hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(B->items, items.data(), sizeof(int2) * items.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return HOFKS_OK;
+}
+
+BatchArgs batch_args(hofks_ctx* c, int parity) {
+  Batch* B = c->batch;
+  BatchArgs a;
+  a.gar = B->gar;
+  a.rar = B->rar;
+  a.dar = B->dar;
+  a.vtar = B->vtar;
+  a.tubes = B->tubes_d;
+  a.euler_order = B->order;
+  a.items = B->items;
+  a.ntubes = B->n;
+  a.nitems = B->nitems;
+  a.queue = B->queue;
+  a.alpha = B->alpha;
+  a.done = B->done;
+  a.tube_s = B->tube_s;
+  a.tflag = B->tflag;
+  a.flag = B->flag;
+  a.parity = parity;
+  a.s_cap = SMAX;
+  return a;
+}
+
+hofks_status batch_launch(hofks_ctx* c, hipStream_t stream, int parity) {
+  Batch* B = c->batch;
+  const BatchArgs a = batch_args(c, parity);
+  const dim3 grid(B->grid), block(1024);
+#define BL(CELLS, UNR) \
+  hipLaunchKernelGGL((k_batch_step<CELLS, UNR>), grid, block, B->lds, stream, a)
+  const int u = B->unr;
+  switch (B->cells) {
+    case 128:
+      if (u == 8) BL(128, 8); else if (u == 4) BL(128, 4); else if (u == 2) BL(128, 2); else BL(128, 1);
+      break;
+    case 512:
+      if (u == 8) BL(512, 8); else if (u == 4) BL(512, 4); else if (u == 2) BL(512, 2); else BL(512, 1);
+      break;
+    default:
+      if (u == 8) BL(256, 8); else if (u == 4) BL(256, 4); else if (u == 2) BL(256, 2); else BL(256, 1);
+  }
+#undef BL
+  HIPCHK(c, hipGetLastError());
+  return HOFKS_OK;
+}
+
+hofks_status batch_configure(hofks_ctx* c, int cells, int grid) {
+  Batch* B = c->batch;
+  B->cells = cells;
+  B->unr = unroll_for(B, cells);
+  B->lds = lds_for(B, cells);
+  B->grid = grid > 0 ? grid : B->ncu;
+  return batch_order(c);
+}
+
+hofks_status batch_capture(hofks_ctx* c) {
+  Batch* B = c->batch;
+  if (B->gexec && B->graph_cells == B->cells && B->graph_grid == B->grid) return HOFKS_OK;
+  if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->gexec = nullptr;
+  B->graph = nullptr;
+  if (!B->cap) HIPCHK(c, hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+  HIPCHK(c, hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < GRAPH_STEPS; ++i) {
+    hofks_status st = batch_launch(c, B->cap, i & 1);
+    if (st) {
+      hipGraph_t g;
+      (void)hipStreamEndCapture(B->cap, &g);
+      return st;
+    }
+  }
+  HIPCHK(c, hipStreamEndCapture(B->cap, &B->graph));
+  HIPCHK(c, hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
+  B->graph_cells = B->cells;
+  B->graph_grid = B->grid;
+  return HOFKS_OK;
+}
+
+hofks_status batch_step(hofks_ctx* c, int n, bool use_graph) {
+  Batch* B = c->batch;
+  if (use_graph) {
+    hofks_status st = batch_capture(c);
+    if (st) return st;
+  }
+  while (n > 0) {
+    const int p = (int)(c->steps & 1);
+    if (use_graph && p == 0 && n >= GRAPH_STEPS) {
+      {
+        Mark m(c, 1, GRAPH_STEPS);
+        HIPCHK(c, hipGraphLaunch(B->gexec, c->stream));
+      }
+      c->steps += GRAPH_STEPS;
+      n -= GRAPH_STEPS;
+      continue;
+    }
+    hofks_status st;
+    {
+      Mark m(c, 1);
+      st = batch_launch(c, c->stream, p);
+    }
+    if (st) return st;
+    c->steps += 1;
+    n -= 1;
+  }
+  return HOFKS_OK;
+}
+
+hofks_status batch_read_flag(hofks_ctx* c) {
+  Batch* B = c->batch;
+  int h = 0;
+  std::vector<int> tf(B->n);
+  HIPCHK(c, hipMemcpyAsync(&h, B->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(tf.data(), B->tflag, sizeof(int) * B->n, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (h & FLAG_SPIN) {
+    fmt_err(c->err, "a bounded wait of the batch kernel gave up; results are invalid");
+    return HOFKS_EDEVICE;
+  }
+  int bad = 0, first = -1, bits = 0;
+  for (int i = 0; i < B->n; ++i)
+    if (tf[i]) {
+      ++bad;
+      bits |= tf[i];
+      if (first < 0) first = i;
+    }
+  // flagged tubes are reported through hofks_batch_tube_flags and excluded
+  // by the caller; the other tubes stay readable
+  if (bad)
+    fmt_err(c->err, "%d tube(s) flagged (first: %d, bits %d); see hofks_batch_tube_flags", bad,
+            first, bits);
+  return HOFKS_OK;
+}
+
+hofks_status batch_set_state(hofks_ctx* c, const double* rho, const double* u,
+                             const double* theta) {
+  Batch* B = c->batch;
+  c->steps = 0;
+  c->cur = 0;
+  hofks_status st = zero_ints(c, B->flag, 16);
+  if (st) return st;
+  st = zero_ints(c, B->tflag, B->n);
+  if (st) return st;
+  st = zero_ints(c, B->done, 2 * B->n);
+  if (st) return st;
+  st = zero_ints(c, B->queue, 16);
+  if (st) return st;
+  st = zero_doubles(c, B->alpha, (size_t)B->n * 2 * ASTR);
+  if (st) return st;
+  long long cell0 = 0;
+  for (int i = 0; i < B->n; ++i) {
+    const TubeDev& T = B->tubes[i];
+    const Geom G = host_tube_geom(T);
+    Mat A;
+    for (int q = 0; q < 9; ++q) A.a[q] = T.A[q];
+    const size_t nx = T.Nx;
+    double* prim = B->dar + T.UE[0];  // rho | u | theta staging (3 x Nx)
+    double* U0 = B->dar + T.U[0];
+    double* cf = B->dar + T.cf;
+    double* part = B->dar + T.UE[1];
+    float* rec0 = B->rar + T.rec[0];
+    float* g0 = B->gar + T.g[0];
+    const VelNode* vt = B->vtar + T.vt;
+    double* al = B->alpha + (size_t)i * 2 * ASTR;
+    HIPCHK(c, hipMemcpyAsync(prim, rho + cell0, nx * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(prim + nx, u + cell0, nx * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(prim + 2 * nx, theta + cell0, nx * 8, hipMemcpyHostToDevice, c->stream));
+    st = zero_doubles(c, cf, 3 * nx);
+    if (st) return st;
+    hipLaunchKernelGGL((k_prim_to_moments<1>), dim3(nblk(nx)), dim3(256), 0, c->stream, prim, U0,
+                       (int)nx);
+    hipLaunchKernelGGL((k_cell_init<1, float>), dim3(nblk(nx)), dim3(256), 0, c->stream, U0, cf,
+                       rec0, vt, part, al, B->tflag + i, G, A, (int)MODE_REFRESH);
+    hipLaunchKernelGGL((k_fill_maxwellian<1, float>), dim3(nblk(nx * T.nv1)), dim3(256), 0,
+                       c->stream, g0, (const float*)rec0, G);
+    hipLaunchKernelGGL((k_piece_sums<1, float>), dim3(nblk(nx)), dim3(256), 0, c->stream,
+                       (const float*)g0, part, G);
+    st = zero_doubles(c, al, ASTR);
+    if (st) return st;
+    hipLaunchKernelGGL((k_cell_init<1, float>), dim3(nblk(nx)), dim3(256), 0, c->stream, U0, cf,
+                       rec0, vt, part, al, B->tflag + i, G, A, (int)MODE_INIT);
+    HIPCHK(c, hipGetLastError());
+    cell0 += (long long)nx;
+  }
+  c->ready = true;
+  st = batch_order(c);
+  if (st) return st;
+  return batch_read_flag(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+hofks_status hofks_batch_workspace_size(const hofks_grid_desc* descs, int n, size_t* bytes) {
+  if (!bytes) return HOFKS_EINVAL;
+  Batch B;
+  hofks_status st = batch_plan(descs, nullptr, n, &B, nullptr);
+  if (st) return st;
+  *bytes = B.total;
+  return HOFKS_OK;
+}
+
+hofks_status hofks_batch_create(const hofks_grid_desc* descs, const double* taus, int n,
+                                void* dev_ws, size_t ws_bytes, void* hip_stream,
+                                hofks_ctx** out) {
+  if (!out) return HOFKS_EINVAL;
+  *out = nullptr;
+  hofks_ctx* c = new (std::nothrow) hofks_ctx();
+  if (!c) return HOFKS_EINVAL;
+  Batch* B = new (std::nothrow) Batch();
+  if (!B) {
+    delete c;
+    return HOFKS_EINVAL;
+  }
+  c->batch = B;
+  hofks_status st = batch_plan(descs, taus, n, B, c->err);
+  if (st) {
+    delete B;
+    delete c;
+    return st;
+  }
+  if (!dev_ws || ws_bytes < B->total || ((uintptr_t)dev_ws & 255)) {
+    delete B;
+    delete c;
+    return HOFKS_ESIZE;
+  }
+  c->desc = descs[0];
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (unsigned char*)dev_ws;
+  B->gar = (float*)(c->ws + B->off_gar);
+  B->rar = (float*)(c->ws + B->off_rar);
+  B->dar = (double*)(c->ws + B->off_dar);
+  B->vtar = (VelNode*)(c->ws + B->off_vt);
+  B->tubes_d = (TubeDev*)(c->ws + B->off_tubes);
+  B->order = (int*)(c->ws + B->off_order);
+  B->items = (int2*)(c->ws + B->off_items);
+  B->queue = (int*)(c->ws + B->off_queue);
+  B->alpha = (double*)(c->ws + B->off_alpha);
+  B->done = (int*)(c->ws + B->off_done);
+  B->tube_s = (int*)(c->ws + B->off_s);
+  B->tflag = (int*)(c->ws + B->off_tflag);
+  B->flag = (int*)(c->ws + B->off_flag);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&B->ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    B->ncu = 256;
+  std::vector<VelNode> tab;
+  tab.reserve(B->nvt);
+  for (const TubeDev& T : B->tubes)
+    for (int i = 0; i < T.nv1; ++i) {
+      const double v = (i - T.kofs) * T.dv;
+      tab.push_back(VelNode{v, v * v, (float)v, (float)(0.5 * v * v), 0.0f, 0.0f});
+    }
+  if (hipMemcpyAsync(B->vtar, tab.data(), sizeof(VelNode) * tab.size(), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess ||
+      hipMemcpyAsync(B->tubes_d, B->tubes.data(), sizeof(TubeDev) * B->n, hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    delete B;
+    delete c;
+    return HOFKS_EDEVICE;
+  }
+  B->cells = 256;
+  B->unr = unroll_for(B, 256);
+  B->lds = lds_for(B, 256);
+  B->grid = B->ncu;
+  *out = c;
+  return HOFKS_OK;
+}
+
+hofks_status hofks_batch_tube_flags(hofks_ctx* c, int* flags) {
+  if (!c || !c->batch || !flags) return HOFKS_EINVAL;
+  HIPCHK(c, hipMemcpyAsync(flags, c->batch->tflag, sizeof(int) * c->batch->n,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return HOFKS_OK;
+}
+
+// Pick the item width (cells per kinetic item) and the persistent grid by
+// timing `steps` steps of each candidate on the current state (which is
+// advanced).  With a cache file, a matching line is reused without timing;
+// otherwise the result is appended.
+hofks_status hofks_autotune(hofks_ctx* c, int steps, const char* cache_path, int* choice) {
+  if (!c || !c->batch || !c->ready || steps < 1) return HOFKS_EINVAL;
+  Batch* B = c->batch;
+  std::ostringstream key;
+  key << "gfx950:batch:n=" << B->n << ":cells=" << B->total_cells << ":cv=" << B->total_cv
+      << ":ncu=" << B->ncu;
+  int best_cells = 0, best_grid = 0;
+  if (cache_path && *cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      const std::string k = "\"key\": \"" + key.str() + "\"";
+      if (line.find(k) == std::string::npos) continue;
+      int cc = 0, gg = 0;
+      const size_t pc = line.find("\"cells\": "), pg = line.find("\"grid\": ");
+      if (pc != std::string::npos && pg != std::string::npos) {
+        cc = std::atoi(line.c_str() + pc + 9);
+        gg = std::atoi(line.c_str() + pg + 8);
+      }
+      if ((cc == 128 || cc == 256 || cc == 512) && gg > 0) {
+        best_cells = cc;
+        best_grid = gg;
+      }
+    }
+  }
+  if (!best_cells) {
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    for (int cells : {128, 256, 512}) {
+      for (int mult : {1, 2}) {
+        const int grid = B->ncu * mult;
+        hofks_status st = batch_configure(c, cells, grid);
+        if (st) return st;
+        st = batch_step(c, 2, false);  // warm-up
+        if (st) return st;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        st = batch_step(c, steps, false);
+        if (st) return st;
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_cells = cells;
+          best_grid = grid;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (cache_path && *cache_path) {
+      std::ofstream o(cache_path, std::ios::app);
+      o << "{\"key\": \"" << key.str() << "\", \"cells\": " << best_cells
+        << ", \"grid\": " << best_grid << ", \"ms_per_step\": " << best_ms / steps << "}\n";
+    }
+  }
+  hofks_status st = batch_configure(c, best_cells, best_grid);
+  if (st) return st;
+  if (choice) {
+    choice[0] = best_cells;
+    choice[1] = best_grid;
+  }
+  return batch_read_flag(c);
 }
 
 }  // extern "C"
+
+namespace {
+
+hofks_status batch_read_moments(hofks_ctx* c, double* U) {
+  Batch* B = c->batch;
+  const int p = (int)(c->steps & 1);
+  long long o = 0;
+  for (const TubeDev& T : B->tubes) {
+    HIPCHK(c, hipMemcpyAsync(U + o, B->dar + T.U[p], sizeof(double) * 3 * T.Nx,
+                             hipMemcpyDeviceToHost, c->stream));
+    o += 3LL * T.Nx;
+  }
+  return batch_read_flag(c);
+}
+
+hofks_status batch_read_f(hofks_ctx* c, double* f, size_t bytes) {
+  Batch* B = c->batch;
+  if (bytes < sizeof(double) * (size_t)B->total_cv) return HOFKS_ESIZE;
+  const int p = (int)(c->steps & 1);
+  long long o = 0;
+  for (const TubeDev& T : B->tubes) {
+    const Geom G = host_tube_geom(T);
+    // stage FP64 planes in the idle piece buffer of the tube (half its planes
+    // fit at a time)
+    double* stage = reinterpret_cast<double*>(B->gar + T.g[p ^ 1]);
+    const int per = std::max(1, T.nv1 / 2);
+    for (int k0 = 0; k0 < T.nv1; k0 += per) {
+      const int nk = std::min(per, T.nv1 - k0);
+      hipLaunchKernelGGL((k_materialize<1, float>), dim3(nblk((size_t)nk * T.Nx)), dim3(256), 0,
+                         c->stream, (const float*)(B->gar + T.g[p]), B->dar + T.cf, stage, k0,
+                         nk, G);
+      HIPCHK(c, hipGetLastError());
+      HIPCHK(c, hipMemcpyAsync(f + o + (long long)k0 * T.Nx, stage,
+                               sizeof(double) * (size_t)nk * T.Nx, hipMemcpyDeviceToHost,
+                               c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    o += (long long)T.nv1 * T.Nx;
+  }
+  return batch_read_flag(c);
+}
+
+hofks_status batch_max_substeps(hofks_ctx* c, int* out) {
+  std::vector<int> ts(c->batch->n);
+  HIPCHK(c, hipMemcpyAsync(ts.data(), c->batch->tube_s, sizeof(int) * ts.size(),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *out = *std::max_element(ts.begin(), ts.end());
+  return HOFKS_OK;
+}
+
+double batch_dt(const hofks_ctx* c) { return c->batch->tubes[0].dt; }
+
+void batch_free(hofks_ctx* c) {
+  Batch* B = c->batch;
+  if (!B) return;
+  if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  if (B->cap) (void)hipStreamDestroy(B->cap);
+  delete B;
+  c->batch = nullptr;
+}
+
+}  // namespace
+
+extern "C" void hofks_destroy(hofks_ctx* c) {
+  if (!c) return;
+  batch_free(c);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+}

@@ -125,3 +125,80 @@ class Solver:
     @property
     def dt(self):
         return _lib.lib().hofks_dt(self._h)
+
+
+class Batch(Solver):
+    """Independent 1D-1V outflow tubes in FP32 pieces, advanced together (one
+    persistent launch per step, replayed from a captured graph).
+
+    ``tubes``: sequence of (n_cells, dx, n_vel, dv, tau).  Host arrays are
+    concatenated over tubes (see include/hofks.h)."""
+
+    def __init__(self, tubes, stream=None):
+        L = _lib.lib()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HOFKS library needs a ROCm GPU")
+        n = len(tubes)
+        descs = (_lib.GridDesc * n)()
+        taus = np.empty(n)
+        for i, (nx, dx, nv, dv, tau) in enumerate(tubes):
+            descs[i] = _lib.GridDesc(1, (ctypes.c_int * 3)(nx, 1, 1), float(dx), int(nv), float(dv),
+                                     (ctypes.c_int * 3)(1, 0, 0), 1, 0)
+            taus[i] = tau
+        self._descs, self.tubes = descs, list(tubes)
+        self.d, self.nm = 1, 3
+        self.nx = np.array([t[0] for t in tubes])
+        self.nvs = np.array([t[2] for t in tubes])
+        self.nc = int(self.nx.sum())
+        self.ncv = int((self.nx * self.nvs).sum())
+        self._h = None
+        size = ctypes.c_size_t(0)
+        self._check(L.hofks_batch_workspace_size(descs, n, ctypes.byref(size)),
+                    "batch_workspace_size", None)
+        self.workspace_bytes = size.value
+        self.workspace = torch.empty(size.value, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p(0)
+        self._check(L.hofks_batch_create(descs, _dp(taus), n,
+                                         ctypes.c_void_p(self.workspace.data_ptr()), size.value,
+                                         ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                    "batch_create", None)
+        self._h = h
+
+    def set_state_macro(self, rho, u, theta):
+        rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(self.nc)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(self.nc)
+        theta = np.ascontiguousarray(theta, dtype=np.float64).reshape(self.nc)
+        self._check(_lib.lib().hofks_set_state_macro(self._h, _dp(rho), _dp(u), _dp(theta)),
+                    "set_state_macro")
+
+    def read_moments(self):
+        """list of (3, Nx_i) arrays"""
+        U = np.empty(3 * self.nc, dtype=np.float64)
+        self._check(_lib.lib().hofks_read_moments(self._h, _dp(U)), "read_moments")
+        out, o = [], 0
+        for nx in self.nx:
+            out.append(U[o:o + 3 * nx].reshape(3, nx))
+            o += 3 * nx
+        return out
+
+    def read_f(self):
+        """list of (n_vel_i, Nx_i) arrays"""
+        f = np.empty(self.ncv, dtype=np.float64)
+        self._check(_lib.lib().hofks_read_f(self._h, _dp(f), f.nbytes), "read_f")
+        out, o = [], 0
+        for nx, nv in zip(self.nx, self.nvs):
+            out.append(f[o:o + nx * nv].reshape(nv, nx))
+            o += nx * nv
+        return out
+
+    def tube_flags(self):
+        fl = (ctypes.c_int * len(self.tubes))()
+        self._check(_lib.lib().hofks_batch_tube_flags(self._h, fl), "batch_tube_flags")
+        return np.array(list(fl))
+
+    def autotune(self, steps=4, cache_path=None):
+        ch = (ctypes.c_int * 2)()
+        cp = cache_path.encode() if cache_path else None
+        self._check(_lib.lib().hofks_autotune(self._h, int(steps), cp, ch), "autotune")
+        return int(ch[0]), int(ch[1])

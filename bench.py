@@ -34,6 +34,8 @@ def run_solver(wl, steps, warmup, precision, scheme=0):
     fields = W.initial_fields(wl)
     s = Solver(wl.d, wl.n, wl.dx, wl.nv, wl.dv, bc=wl.bc, precision=precision, scheme=scheme,
                tau=wl.tau)
+    s.set_state_macro(*fields)
+    tuned = s.autotune(steps=3)  # launch configuration picked by timing
     if warmup:
         s.set_state_macro(*fields)
         s.step(warmup)
@@ -64,10 +66,78 @@ def run_solver(wl, steps, warmup, precision, scheme=0):
         "kinetic_GBps": achieved,
         "kinetic_hbm_frac": achieved / HBM_PEAK_GBPS,
         "step_hbm_frac": bpcv * cv / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        "tuned": {"wavefronts_per_block": tuned[0], "loads_ahead": tuned[1]},
     }
     del s
     torch.cuda.empty_cache()
     return out
+
+
+def run_batch(steps, warmup):
+    """the batched form: 512 independent shock tubes (seed 4), FP32 pieces,
+    one persistent launch per step replayed from a captured graph"""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1212_0204_amd import Batch
+
+    tubes = W.batched_tubes()
+    fields = [np.concatenate(a) for a in zip(*[
+        (r, uu[0], th) for r, uu, th in (W.sod_tube(t.nx, left=t.left, right=t.right)
+                                          for t in tubes)])]
+    b = Batch([(t.nx, t.dx, t.nv, t.dv, t.tau) for t in tubes])
+    b.set_state_macro(*fields)
+    tuned = b.autotune(steps=4)
+    b.set_state_macro(*fields)
+    b.step(warmup)
+    b.sync()
+    b.set_state_macro(*fields)
+    b.kernel_timing(enable=True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    b.kernel_timing(enable=False)
+    b.sync()
+    flagged = int((b.tube_flags() != 0).sum())
+    cv = b.ncv * steps
+    out = {"workload": "batch512_tubes_seed4_fp32", "tubes": len(tubes), "cv_per_step": b.ncv,
+           "steps": steps, "cv_per_s": cv / (ms * 1e-3), "ms_per_step": ms / steps,
+           "hbm_frac": 8 * cv / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+           "tuned": {"cells_per_item": tuned[0], "blocks": tuned[1]},
+           "flagged_tubes": flagged}
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
+def copy_probe(mb, reps=5):
+    """a plain device-to-device copy of known size (torch's copy kernel): the
+    reachable HBM bandwidth, and the reference for scaling the FETCH_SIZE /
+    WRITE_SIZE counters of the profiled kernels"""
+    import torch
+    n = mb * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    moved = 2 * n * 4
+    del x, y
+    torch.cuda.empty_cache()
+    return {"bytes_read": n * 4, "bytes_written": n * 4, "ms": ms,
+            "GBps": moved / (ms * 1e-3) / 1e9}
 
 
 def cpu_baseline(wl, budget_s=12.0):
@@ -99,7 +169,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp32_3d,fp64_3d")
+    ap.add_argument("--forms", default="fp32_3d,fp64_3d,batched")
+    ap.add_argument("--copy-probe-mb", type=int, default=1024,
+                    help="size of a plain device copy timed after the run (0: skip)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -119,6 +191,8 @@ def main():
         elif name == "fp64_3d":
             forms[name] = dict(workload=W.GAS_3D.name.replace("fp32", "fp64"),
                                **run_solver(W.GAS_3D, W.GAS_3D.steps, 2, 0))
+        elif name == "batched":
+            forms[name] = run_batch(500, 16)
     if "fp32_3d" in forms and "fp64_3d" in forms:
         forms["fp32_3d"]["speedup_vs_fp64_same_workload"] = (
             forms["fp32_3d"]["cv_per_s"] / forms["fp64_3d"]["cv_per_s"])
@@ -147,6 +221,8 @@ def main():
         "kernel_ms_per_step": prim["kernel_ms_per_step"],
         "forms": forms,
     }
+    if args.copy_probe_mb:
+        line["copy_probe"] = copy_probe(args.copy_probe_mb)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)

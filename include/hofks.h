@@ -139,11 +139,16 @@ hofks_status hofks_batch_create(const hofks_grid_desc *descs, const double *taus
                                 void *hip_stream, hofks_ctx **out);
 /* Per-tube error bits (1 non-physical, 2 sub-step cap) to host flags[n]. */
 hofks_status hofks_batch_tube_flags(hofks_ctx *ctx, int *flags);
-/* Choose the kinetic item width and the persistent grid of a batch by timing
- * `steps` steps per candidate on the current state, which is advanced (set
- * the state again afterwards).  cache_path (may be NULL) is a JSON-lines file
- * of earlier choices keyed by the batch shape; a match skips the timing, a
- * new choice is appended.  choice[2] (may be NULL) gets (cells, grid). */
+/* Autotuner.  Times `steps` steps of each candidate launch configuration on
+ * the current state, which is advanced (set the state again afterwards), and
+ * keeps the fastest:
+ *   single grid: wavefronts per kinetic block and piece loads issued ahead,
+ *                choice = (wavefronts, loads);
+ *   batch:       cells per kinetic item and persistent grid size,
+ *                choice = (cells, blocks).
+ * cache_path (may be NULL) is a JSON-lines file of earlier choices keyed by
+ * the grid or batch shape; a match skips the timing, a new choice is
+ * appended.  choice[2] may be NULL. */
 hofks_status hofks_autotune(hofks_ctx *ctx, int steps, const char *cache_path,
                             int choice[2]);
 

@@ -79,6 +79,15 @@ int fmt_err(char* buf, const char* f, ...) {
   return 0;
 }
 
+// LDS of a kinetic block with ng wavefronts: the staged record segments and
+// the partial sums of the extra wavefronts
+size_t kin_lds(const Plan& P, int ng) {
+  const size_t sw = 64 + P.G.nv1 - 1;
+  const size_t stage = (P.d >= 2 ? ng : 1) * sw * P.RS * P.tsize;
+  const size_t red = (size_t)(ng - 1) * 64 * 2 * P.nm * sizeof(double);
+  return std::max(stage, red);
+}
+
 int rec_stride_rt(int d, int prec) {
   if (prec) return d == 1 ? rec_stride<1, float>() : d == 2 ? rec_stride<2, float>() : rec_stride<3, float>();
   return d == 1 ? rec_stride<1, double>() : d == 2 ? rec_stride<2, double>() : rec_stride<3, double>();
@@ -147,30 +156,29 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
   }
   if (!invert(nm, CCt, P->A.a)) return fmt_err(err, "C C^T is singular"), HOFKS_EINVAL;
 
-  // kinetic tiling: TX consecutive cells along x (a multiple of the 64-wide
-  // wavefront), TR rows per 256-thread block, velocity rows split in chunks
-  // so that the grid holds ~8 blocks per compute unit
+  // kinetic tiling: one block per 64 consecutive x cells of a row, four
+  // wavefronts over the velocities
   const int Nx = G.n[0];
-  P->TX = Nx >= 192 ? 256 : (Nx > 64 ? 128 : 64);
-  P->TR = 256 / P->TX;
-  P->nseg = (Nx + P->TX - 1) / P->TX;
   const int nrows = G.n[1] * G.n[2];
-  P->nrowgrp = (nrows + P->TR - 1) / P->TR;
+  P->TX = 64;
+  P->TR = 1;
+  P->nseg = (Nx + 63) / 64;
+  P->nrowgrp = nrows;
+  P->nchunk = 1;
   P->nvr = G.nv / G.nv1;
-  const long base = (long)P->nseg * P->nrowgrp;
-  long nch = (2048 + base - 1) / base;
-  P->nchunk = (int)std::max(1L, std::min<long>(nch, P->nvr));
-  // Euler group: at most one block per compute unit (so that the group is
-  // co-resident whatever else is running), grid-strided over cells
+  P->RS = rec_stride_rt(d, P->prec);
+  const size_t sw = 64 + G.nv1 - 1;
+  (void)sw;
+  P->lds = kin_lds(*P, 2);
+  if (P->lds > 65536) return fmt_err(err, "velocity grid too wide for the LDS tile"), HOFKS_EINVAL;
+  // Euler kernel: at most one block per compute unit (co-resident), grid-
+  // strided over cells
   int ncu = 0, dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       ncu < 1)
     ncu = 256;
   P->GE = (int)std::min<long>(std::min(256, ncu), ((long)G.nc + 255) / 256);
-  P->RS = rec_stride_rt(d, P->prec);
-  P->lds = (size_t)P->TR * P->RS * (P->TX + G.nv1 - 1) * P->tsize;
-  if (P->lds > 65536) return fmt_err(err, "velocity grid too wide for the LDS tile"), HOFKS_EINVAL;
 
   size_t off = 0;
   const size_t gbytes = (size_t)G.nv * G.nc * P->tsize;
@@ -199,8 +207,8 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
   off = align256(off + (size_t)P->nchunk * 2 * nm * G.nc * sizeof(double));
   P->off_slots = off;
   off = align256(off + 3 * (size_t)SET_D * sizeof(double));
-  P->off_tiles = off;
-  off = align256(off + (size_t)P->nseg * P->nrowgrp * sizeof(int));
+  P->off_tiles = off;  // per-block speed maxima of the Euler kernel
+  off = align256(off + (size_t)2 * 256 * ASTR * sizeof(double));
   P->off_flag = off;
   off = align256(off + 64);
   P->total = off;
@@ -225,6 +233,7 @@ struct hofks_ctx {
   int s_cap;
   long steps;
   bool ready;
+  int kng, kunr;  // kinetic kernel: wavefronts per block, loads issued ahead
   // optional per-kernel timing: hipEvents around each launch group
   bool timing;
   std::vector<hipEvent_t> ev_pool;
@@ -301,6 +310,40 @@ hofks_status launch_cell_init(hofks_ctx* c, int mode) {
   return HOFKS_OK;
 }
 
+// unroll depth that divides the k_x range of one wavefront
+int kin_unroll(const Plan& P, int ng, int unr) {
+  const int per = P.d >= 2 ? P.G.nv1 : P.G.nv1 / ng;
+  const bool even = P.d >= 2 || P.G.nv1 % ng == 0;
+  return (even && per % unr == 0) ? unr : 1;
+}
+
+template <int D, typename T, bool FT, bool EUL>
+void dispatch_kin(hofks_ctx* c, const StepArgs<T>& a, dim3 grid) {
+  constexpr bool CP = sizeof(T) == 4;  // compensated sums in the FP32 form
+  const Plan& P = c->P;
+  const int bcx = P.G.bc[0];
+  int ng = c->kng, unr = kin_unroll(P, c->kng, c->kunr);
+  if (FT || !EUL) {  // free transport and FKS steps: one configuration
+    ng = 4;
+    unr = kin_unroll(P, 4, 8);
+  }
+  const size_t lds = kin_lds(P, ng);
+#define K(BCX, NG, U)                                                                       \
+  hipLaunchKernelGGL((k_kinetic<D, T, FT, CP, BCX, U, EUL, NG>), grid, dim3(64 * NG), lds, \
+                     c->stream, a, P.G, P.A)
+#define KB(NG, U) \
+  if (bcx == 0) K(0, NG, U); else K(1, NG, U);
+  if (FT || !EUL) {
+    if (unr == 8) { KB(4, 8) } else { KB(4, 1) }
+  } else if (ng == 2) {
+    if (unr == 16) { KB(2, 16) } else if (unr == 8) { KB(2, 8) } else { KB(2, 1) }
+  } else {
+    if (unr == 16) { KB(4, 16) } else if (unr == 8) { KB(4, 8) } else { KB(4, 1) }
+  }
+#undef KB
+#undef K
+}
+
 template <int D, typename T>
 hofks_status launch_step(hofks_ctx* c) {
   const Plan& P = c->P;
@@ -317,46 +360,30 @@ hofks_status launch_step(hofks_ctx* c) {
   a.UE0 = c->UE[0];
   a.UE1 = c->UE[1];
   a.cf = c->cf;
-  a.part = c->part;
-  a.tile_cnt = c->tiles;
   a.set_r = slot_set(c, (int)(n % 3));
   a.set_w = slot_set(c, (int)((n + 1) % 3));
   a.set_z = slot_set(c, (int)((n + 2) % 3));
+  a.bmax = (double*)c->tiles;
   a.flag = c->flag;
-  a.TX = P.TX;
-  a.TR = P.TR;
   a.nseg = P.nseg;
-  a.nrowgrp = P.nrowgrp;
-  a.nchunk = P.nchunk;
-  a.nvr = P.nvr;
+  a.GE = P.GE;
   a.s_cap = c->s_cap;
   a.unlimited = (int)(c->desc.scheme == 2);
-  a.fks = (int)(c->desc.scheme == 1);
   const bool ft = (P.G.mu == 0.0);
   const bool eul = !ft && c->desc.scheme != 1;
-  a.GE = eul ? P.GE : 0;
-  constexpr bool CP = sizeof(T) == 4;  // compensated sums in the FP32 form
-  const int bcx = P.G.bc[0];
-  const bool unr = (P.G.nv1 % 8) == 0;
-  const dim3 grid((unsigned)(a.GE + (long)P.nseg * P.nrowgrp * P.nchunk));
-#define KLAUNCH(FT, BCX, UNR, EUL)                                                              \
-  hipLaunchKernelGGL((k_step<D, T, FT, CP, BCX, UNR, EUL>), grid, dim3(256), P.lds, c->stream, \
-                     a, P.G, P.A)
-#define KL2(FT, EUL)                                        \
-  if (bcx == 0) {                                           \
-    if (unr) KLAUNCH(FT, 0, 8, EUL); else KLAUNCH(FT, 0, 1, EUL); \
-  } else {                                                  \
-    if (unr) KLAUNCH(FT, 1, 8, EUL); else KLAUNCH(FT, 1, 1, EUL); \
+  if (eul) {
+    Mark m0(c, 0);
+    hipLaunchKernelGGL((k_euler<D, T>), dim3(P.GE), dim3(256), 0, c->stream, a, P.G);
+    HIPCHK(c, hipGetLastError());
   }
-  if (ft) {
-    KL2(true, false)
-  } else if (eul) {
-    KL2(false, true)
-  } else {
-    KL2(false, false)
-  }
-#undef KL2
-#undef KLAUNCH
+  const dim3 grid((unsigned)((long)P.nseg * P.nrowgrp));
+  Mark m(c, 1);
+  if (ft)
+    dispatch_kin<D, T, true, false>(c, a, grid);
+  else if (eul)
+    dispatch_kin<D, T, false, true>(c, a, grid);
+  else
+    dispatch_kin<D, T, false, false>(c, a, grid);
   HIPCHK(c, hipGetLastError());
   return HOFKS_OK;
 }
@@ -364,11 +391,7 @@ hofks_status launch_step(hofks_ctx* c) {
 template <int D, typename T>
 hofks_status step_impl(hofks_ctx* c, int nsteps) {
   for (int it = 0; it < nsteps; ++it) {
-    hofks_status st;
-    {
-      Mark m(c, 1);
-      st = launch_step<D, T>(c);
-    }
+    hofks_status st = launch_step<D, T>(c);
     if (st) return st;
     c->cur ^= 1;
     c->steps++;
@@ -450,8 +473,6 @@ hofks_status reset_counters(hofks_ctx* c) {
   c->steps = 0;
   hofks_status st = zero_ints(c, c->flag, 16);
   if (st) return st;
-  st = zero_ints(c, c->tiles, c->P.nseg * c->P.nrowgrp);
-  if (st) return st;
   return zero_doubles(c, c->slots, 3 * (size_t)SET_D);
 }
 
@@ -511,6 +532,11 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
   c->flag = (int*)(c->ws + P.off_flag);
   c->tau = INFINITY;
   c->s_cap = 1;
+  // kinetic configuration before any tuning: wider unroll in 2D/3D, two
+  // wavefronts per block for the FP64 2D grid
+  c->kng = (P.d == 2 && !P.prec) ? 2 : 4;
+  c->kunr = P.d >= 2 ? 16 : 8;
+  if (kin_lds(P, c->kng) > 65536) c->kng = 2;
   // velocity node table of one axis (the lattice, used by every kernel)
   std::vector<VelNode> tab(P.G.nv1);
   for (int i = 0; i < P.G.nv1; ++i) {
@@ -1109,6 +1135,71 @@ hofks_status batch_set_state(hofks_ctx* c, const double* rho, const double* u,
   return batch_read_flag(c);
 }
 
+// single grid: choose (wavefronts per kinetic block, loads issued ahead)
+hofks_status grid_autotune(hofks_ctx* c, int steps, const char* cache_path, int* choice) {
+  const Plan& P = c->P;
+  std::ostringstream key;
+  key << "gfx950:grid:d=" << P.d << ":n=" << P.G.n[0] << "x" << P.G.n[1] << "x" << P.G.n[2]
+      << ":nv=" << P.G.nv1 << ":prec=" << P.prec << ":bc=" << P.G.bc[0] << P.G.bc[1] << P.G.bc[2]
+      << ":scheme=" << c->desc.scheme;
+  int best_ng = 0, best_unr = 0;
+  if (cache_path && *cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    const std::string k = "\"key\": \"" + key.str() + "\"";
+    while (std::getline(in, line)) {
+      if (line.find(k) == std::string::npos) continue;
+      const size_t pn = line.find("\"ng\": "), pu = line.find("\"unr\": ");
+      if (pn == std::string::npos || pu == std::string::npos) continue;
+      const int ng = std::atoi(line.c_str() + pn + 6), unr = std::atoi(line.c_str() + pu + 7);
+      if ((ng == 2 || ng == 4) && (unr == 8 || unr == 16)) {
+        best_ng = ng;
+        best_unr = unr;
+      }
+    }
+  }
+  if (!best_ng) {
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const int cand[4][2] = {{4, 8}, {2, 16}, {4, 16}, {2, 8}};
+    for (const auto& cd : cand) {
+      if (kin_lds(P, cd[0]) > 65536) continue;
+      c->kng = cd[0];
+      c->kunr = cd[1];
+      hofks_status st = hofks_step(c, 1);
+      if (st) return st;
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+      st = hofks_step(c, steps);
+      if (st) return st;
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      HIPCHK(c, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_ng = cd[0];
+        best_unr = cd[1];
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (cache_path && *cache_path) {
+      std::ofstream o(cache_path, std::ios::app);
+      o << "{\"key\": \"" << key.str() << "\", \"ng\": " << best_ng << ", \"unr\": " << best_unr
+        << ", \"ms_per_step\": " << best_ms / steps << "}\n";
+    }
+  }
+  c->kng = best_ng;
+  c->kunr = best_unr;
+  if (choice) {
+    choice[0] = best_ng;
+    choice[1] = best_unr;
+  }
+  return read_flag(c);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1203,7 +1294,8 @@ hofks_status hofks_batch_tube_flags(hofks_ctx* c, int* flags) {
 // advanced).  With a cache file, a matching line is reused without timing;
 // otherwise the result is appended.
 hofks_status hofks_autotune(hofks_ctx* c, int steps, const char* cache_path, int* choice) {
-  if (!c || !c->batch || !c->ready || steps < 1) return HOFKS_EINVAL;
+  if (!c || !c->ready || steps < 1) return HOFKS_EINVAL;
+  if (!c->batch) return grid_autotune(c, steps, cache_path, choice);
   Batch* B = c->batch;
   std::ostringstream key;
   key << "gfx950:batch:n=" << B->n << ":cells=" << B->total_cells << ":cv=" << B->total_cv

@@ -18,14 +18,20 @@
 //              eq. (minimMax); a piece of velocity v leaving cell j' relaxes to
 //                f* = lambda g + (1-lambda) M + p.m(v),
 //                E  = M + e.m(v),   M = exp(lp - beta |v - u|^2).
-// One launch of k_step advances one time step: its first blocks run the s
-// Euler sub-steps of eq. (discmom) on U^n (grid barrier between sub-steps),
-// the other blocks relax, shift and sum the pieces tile by tile, and the last
-// velocity chunk to finish a tile forms delta, U^{n+1}, cf and the next
-// records of the tile's cells once the Euler group is done.
+// One time step is two launches: k_euler runs the s Euler sub-steps of eq.
+// (discmom) on U^n (co-resident blocks, barrier between sub-steps); k_kinetic
+// relaxes, shifts and sums the pieces of a 64-cell tile over all velocities
+// inside one block, then forms delta, U^{n+1}, cf and the next records of the
+// tile's cells.  No block waits on another block of the same launch except
+// the Euler barrier.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+// stream the pieces with non-temporal loads and stores
+#ifndef HOFKS_NT
+#define HOFKS_NT 1
+#endif
 
 namespace hofks {
 
@@ -60,11 +66,14 @@ __device__ __forceinline__ int map_axis(int i, int N, int bc) {
   return i < 0 ? 0 : (i >= N ? N - 1 : i);
 }
 
+// x index of the piece that reaches cell x with shift kx (|kx| <= N).  kx is
+// the same for the whole wavefront, so the offset is formed in scalar code.
 template <int BCX>
 __device__ __forceinline__ int map_x(int xN, int kx, int N) {
-  if (BCX == 0) {  // periodic: t = x + N - k in [0, 2N)
-    const unsigned t = (unsigned)(xN - kx);
-    return (int)min(t, t - (unsigned)N);
+  if (BCX == 0) {  // periodic: u = x - kx (+ N when kx > 0) lies in [0, 2N)
+    const int off = kx > 0 ? kx - N : kx;
+    const unsigned u = (unsigned)(xN - N - off);
+    return (int)min(u, u - (unsigned)N);
   }
   const int t = xN - N - kx;  // outflow: clamp to the boundary cell
   return min(max(t, 0), N - 1);
@@ -171,9 +180,9 @@ __device__ __forceinline__ void group_barrier(unsigned* cnt, unsigned target, in
     __threadfence();
     atomicAdd(cnt, 1u);
     spin_until_geq(cnt, target, flag);
+    __threadfence();  // acquire: invalidates this compute unit's caches for all its waves
   }
   __syncthreads();
-  __threadfence();  // acquire for every wave: the next sub-step reads other blocks' cells
 }
 
 // ===================================================================== MUSCL
@@ -234,50 +243,51 @@ __device__ __forceinline__ double vl_slope(double a, double b, int unlimited) {
 }
 
 // new value of cell j after one sub-step: in - dt_s/dx sum_a (psi_a+ - psi_a-).
-// Each face is formed from its own four cells (both neighbours of a face get
-// bit-identical fluxes, so the update conserves exactly up to the final sum).
+// All stencil values are loaded before any flux is formed, so the loads of
+// a sub-step overlap.  Each face is formed from its own four cells (both
+// neighbours of a face get bit-identical fluxes, so the update conserves
+// exactly up to the final sum).
 template <int D>
 __device__ __forceinline__ bool euler_cell(const double* __restrict__ in, int j,
                                            const double* alpha, double dts_dx, const Geom& G,
                                            int unl, double* Un) {
   constexpr int NM = D + 2;
   const int c[3] = {j % G.n[0], (j / G.n[0]) % G.n[1], j / (G.n[0] * G.n[1])};
+  double St[D][5][NM];  // cells j-2 .. j+2 along each axis
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      int cc[3] = {c[0], c[1], c[2]};
+      cc[a] = map_axis(c[a] + q - 2, G.n[a], G.bc[a]);
+      const int jj = (cc[2] * G.n[1] + cc[1]) * G.n[0] + cc[0];
+#pragma unroll
+      for (int r = 0; r < NM; ++r) St[a][q][r] = in[(size_t)r * G.nc + jj];
+    }
+  }
   double div[NM];
 #pragma unroll
   for (int r = 0; r < NM; ++r) div[r] = 0.0;
   bool phys = true;
-#pragma unroll 1
+#pragma unroll
   for (int a = 0; a < D; ++a) {
-#pragma unroll 1
-    for (int side = -1; side <= 0; ++side) {
-      // face between cells j+side and j+side+1: stencil j+side-1 .. j+side+2
-      double Wp[3][NM], Wm[3][NM];  // W+ of cells 0..2, W- of cells 1..3
+    double Wp[5][NM], Wm[5][NM];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        int cc[3] = {c[0], c[1], c[2]};
-        cc[a] = map_axis(c[a] + side - 1 + q, G.n[a], G.bc[a]);
-        const int jj = (cc[2] * G.n[1] + cc[1]) * G.n[0] + cc[0];
-        double Uq[NM], wp[NM], wm[NM];
+    for (int q = 0; q < 5; ++q) phys &= split_flux<D>(St[a][q], a, alpha[a], G.gam, Wp[q], Wm[q]);
 #pragma unroll
-        for (int r = 0; r < NM; ++r) Uq[r] = in[(size_t)r * G.nc + jj];
-        phys &= split_flux<D>(Uq, a, alpha[a], G.gam, wp, wm);
-#pragma unroll
-        for (int r = 0; r < NM; ++r) {
-          if (q < 3) Wp[q][r] = wp[r];
-          if (q > 0) Wm[q - 1][r] = wm[r];
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < NM; ++r) {
-        const double sp = vl_slope(Wp[1][r] - Wp[0][r], Wp[2][r] - Wp[1][r], unl);
-        const double sm = vl_slope(Wm[1][r] - Wm[0][r], Wm[2][r] - Wm[1][r], unl);
-        const double psi = 0.5 * (Wp[1][r] + Wm[1][r]) + 0.25 * (sp - sm);
-        div[r] += side == 0 ? psi : -psi;
-      }
+    for (int r = 0; r < NM; ++r) {
+      // face j-1/2 from cells 0..3, face j+1/2 from cells 1..4
+      const double spl = vl_slope(Wp[1][r] - Wp[0][r], Wp[2][r] - Wp[1][r], unl);
+      const double sml = vl_slope(Wm[2][r] - Wm[1][r], Wm[3][r] - Wm[2][r], unl);
+      const double spr = vl_slope(Wp[2][r] - Wp[1][r], Wp[3][r] - Wp[2][r], unl);
+      const double smr = vl_slope(Wm[3][r] - Wm[2][r], Wm[4][r] - Wm[3][r], unl);
+      const double psil = 0.5 * (Wp[1][r] + Wm[2][r]) + 0.25 * (spl - sml);
+      const double psir = 0.5 * (Wp[2][r] + Wm[3][r]) + 0.25 * (spr - smr);
+      div[r] += psir - psil;
     }
   }
 #pragma unroll
-  for (int r = 0; r < NM; ++r) Un[r] = in[(size_t)r * G.nc + j] - dts_dx * div[r];
+  for (int r = 0; r < NM; ++r) Un[r] = St[0][2][r] - dts_dx * div[r];
   return phys;
 }
 
@@ -382,19 +392,20 @@ struct StepArgs {
   double* UE0;
   double* UE1;
   double* cf;
-  double* part;       // nchunk x 2(d+2) x nc velocity-chunk sums
-  int* tile_cnt;      // chunks finished per tile
   double* set_r;      // speeds of U^n (row 0) and of the sub-steps; control
-  double* set_w;      // speeds of U^{n+1} (row 0), written by the epilogues
-  double* set_z;      // the set of the step after next, cleared here
+  double* set_w;      // speeds of U^{n+1} (row 0), written by the kinetic epilogue
+  double* set_z;      // the set of the step after next, cleared by the Euler kernel
+  double* bmax;       // [2][GE][ASTR] per-block speed maxima of the Euler sub-steps
   int* flag;
-  int TX, TR, nseg, nrowgrp, nchunk, nvr, GE, s_cap, unlimited, fks;
+  int nseg, GE, s_cap, unlimited;
 };
 
-// Euler group: blocks 0 .. GE-1 advance U^n over dt with s sub-steps; the
-// speeds of sub-step i+1 are reduced with atomics into row i+1 of set_r.
+// Euler kernel: GE co-resident blocks advance U^n over dt with s sub-steps
+// (grid-strided over cells); the speeds of sub-step i+1 are reduced with
+// atomics into row i+1 of set_r and the blocks meet at a barrier between
+// sub-steps.  The result is UE[s % 2].
 template <int D, typename T>
-__device__ void euler_group(const StepArgs<T>& a, const Geom& G) {
+__global__ __launch_bounds__(256) void k_euler(StepArgs<T> a, Geom G) {
   constexpr int NM = D + 2;
   double* S = a.set_r;
   unsigned* ctrl = reinterpret_cast<unsigned*>(S + (SMAX + 1) * ASTR);
@@ -408,13 +419,14 @@ __device__ void euler_group(const StepArgs<T>& a, const Geom& G) {
     }
   }
   const double dts_dx = (G.dt / s) / G.dx;
+  __shared__ double wmax[4][ASTR];
+  double alpha[3];
+#pragma unroll
+  for (int d2 = 0; d2 < D; ++d2)
+    alpha[d2] = __hip_atomic_load(S + d2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (int i = 0; i < s; ++i) {
     const double* in = (i == 0) ? a.U_in : ((i & 1) ? a.UE1 : a.UE0);
     double* out = ((i + 1) & 1) ? a.UE1 : a.UE0;
-    double alpha[3];
-#pragma unroll
-    for (int d2 = 0; d2 < D; ++d2)
-      alpha[d2] = __hip_atomic_load(S + i * ASTR + d2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     bool phys = true;
     double mx[3] = {0.0, 0.0, 0.0};
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < G.nc; j += a.GE * blockDim.x) {
@@ -431,66 +443,90 @@ __device__ void euler_group(const StepArgs<T>& a, const Geom& G) {
     }
     if (!phys) atomicOr(a.flag, FLAG_NONPHYS);
     if (i + 1 < s) {
+      // block maxima into bmax[(i+1) % 2][block], then every block reduces
+      // all of them after the barrier (max is exact: all blocks agree)
+      double* bm = a.bmax + (size_t)((i + 1) & 1) * a.GE * ASTR;
 #pragma unroll
       for (int d2 = 0; d2 < D; ++d2) {
         const double m = wave_max(mx[d2]);
-        if ((threadIdx.x & 63) == 0) atomic_max_pos(S + (i + 1) * ASTR + d2, m);
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6][d2] = m;
       }
+      __syncthreads();
+      if (threadIdx.x < D) {
+        double m = wmax[0][threadIdx.x];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, wmax[w][threadIdx.x]);
+        bm[(size_t)blockIdx.x * ASTR + threadIdx.x] = m;
+      }
+      group_barrier(ctrl, (unsigned)((i + 1) * a.GE), a.flag);
+#pragma unroll
+      for (int d2 = 0; d2 < D; ++d2) {
+        double m = 0.0;
+        for (int b = threadIdx.x; b < a.GE; b += blockDim.x) m = fmax(m, bm[(size_t)b * ASTR + d2]);
+        m = wave_max(m);
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6][d2] = m;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int d2 = 0; d2 < D; ++d2) {
+        double m = wmax[0][d2];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, wmax[w][d2]);
+        alpha[d2] = m;
+      }
+      __syncthreads();
     }
-    group_barrier(ctrl, (unsigned)((i + 1) * a.GE), a.flag);
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_store(ctrl + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// One kinetic block = TX x TR destination cells (TX consecutive x, TR rows)
-// and one chunk of velocity rows.  For every velocity row (k_y, k_z) the
-// records of the upstream row segment are staged in LDS; the loop over k_x
-// issues the loads of UNR pieces g(j - k, k) (coalesced along x) before using
-// them, relaxes each piece, writes it to cell j of the new buffer and sums
-// the moments of f* and of E.  The last chunk to finish a tile then forms the
-// new state of the tile's cells.
-template <int D, typename T, bool FT, bool COMP, int BCX, int UNR, bool EUL>
-__global__ __launch_bounds__(256) void k_step(StepArgs<T> a, Geom G, Mat A) {
-  if (EUL && (int)blockIdx.x < a.GE) {
-    euler_group<D, T>(a, G);
-    return;
-  }
+// wave-local LDS hand-off: LDS operations of one wavefront complete in order;
+// this keeps the compiler from moving them across and waits for them
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Kinetic kernel.  One block = 64 consecutive x cells of one row (one lane
+// per cell) and NG wavefronts, each taking 1/NG of the velocities (of the
+// velocity rows (k_y, k_z) in 2D/3D, of k_x in 1D).  Per
+// velocity row a wavefront stages the records of the upstream row segment in
+// its own LDS slice; its k_x loop issues UNR piece loads g(j - k, k) (coalesced
+// along x) before using them, relaxes each piece, writes it to cell j of the
+// new buffer and sums the moments of f* and of E.  The four partial sums are
+// combined in LDS and the first wavefront forms delta, U^{n+1}, cf and the
+// next record of its 64 cells; the Euler kernel of the step has finished.
+// (NG, UNR) is chosen per grid by the autotuner.
+template <int D, typename T, bool FT, bool COMP, int BCX, int UNR, bool EUL, int NG>
+__global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat A) {
   constexpr int NM = D + 2;
   constexpr int RS = rec_stride<D, T>();
   constexpr int PER16 = 16 / (int)sizeof(T);
   constexpr int NCH = (rec_values<D, T>() + PER16 - 1) / PER16;  // chunks read per piece
+  constexpr int C16 = RS / PER16;
   using V = typename Vec16<T>::type;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-  __shared__ int s_last;
   T* lds = reinterpret_cast<T*>(lds_raw);
-  const int TX = a.TX, TR = a.TR;
-  const int SW = TX + G.nv1 - 1;
+  const int SW = 64 + G.nv1 - 1;
 
-  int b = (int)blockIdx.x - (EUL ? a.GE : 0);
-  const int tile = b % (a.nseg * a.nrowgrp);
-  const int seg = b % a.nseg;
-  b /= a.nseg;
-  const int rg = b % a.nrowgrp;
-  const int chunk = b / a.nrowgrp;
-  const int tx = threadIdx.x % TX, tr = threadIdx.x / TX;
-  const int x0 = seg * TX;
-  const int x = x0 + tx;
+  const int seg = blockIdx.x % a.nseg;
+  const int row = blockIdx.x / a.nseg;
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int Nx = G.n[0];
-  const int xN = x + Nx;
-  const int nrows = G.n[1] * G.n[2];
-  const int row = rg * TR + tr;
-  const bool active = (x < Nx) && (row < nrows) && (tr < TR);
-  const int jy = active ? row % G.n[1] : 0;
-  const int jz = active ? row / G.n[1] : 0;
+  const int x0 = seg * 64;
+  const int x = x0 + lane;
+  const bool active = x < Nx;
+  const int jy = row % G.n[1], jz = row / G.n[1];
   const int dest = row * Nx + x;
-  const int vr0 = (int)((long)chunk * a.nvr / a.nchunk);
-  const int vr1 = (int)((long)(chunk + 1) * a.nvr / a.nchunk);
-  const int xlo = x0 - (G.nv1 - 1 - G.kofs);
+  const int xN = x + Nx;
   const int lofs = G.nv1 - 1 - G.kofs;
+  const int xlo = x0 - lofs;
   const T lam = (T)G.lam, mu = (T)G.mu;
+  const int nvr = G.nv / G.nv1;
+  // velocity rows of this wavefront (2D/3D) or k_x range (1D)
+  const int vr0 = (D >= 2) ? grp * nvr / NG : 0;
+  const int vr1 = (D >= 2) ? (grp + 1) * nvr / NG : 1;
+  const int ixa = (D >= 2) ? 0 : grp * G.nv1 / NG;
+  const int ixb = (D >= 2) ? G.nv1 : (grp + 1) * G.nv1 / NG;
+  T* Lw = lds + (D >= 2 ? (size_t)grp * SW * RS : 0);
 
   double SK[NM], SE[NM], CK[NM], CE[NM];
 #pragma unroll
@@ -503,49 +539,49 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<T> a, Geom G, Mat A) {
     const double vy = (D >= 2) ? a.vt[iy].v : 0.0;
     const double vz = (D >= 3) ? a.vt[iz].v : 0.0;
     const double hrow = (D >= 2 ? 0.5 * a.vt[iy].v2 : 0.0) + (D >= 3 ? 0.5 * a.vt[iz].v2 : 0.0);
-
-    // stage the records of the upstream row segments (16-byte chunks)
-    __syncthreads();
-    {
-      constexpr int C16 = RS / PER16;
-      const int total = TR * SW * C16;
-      V* ldsv = reinterpret_cast<V*>(lds);
-      const V* recv = reinterpret_cast<const V*>(a.rec_in);
-      for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        const int c = idx % C16;
-        const int cellslot = idx / C16;
-        const int r_ = cellslot / SW, i = cellslot - r_ * SW;
-        const int rw = rg * TR + r_;
-        if (rw < nrows) {
-          const int ry = rw % G.n[1], rz = rw / G.n[1];
-          const int uy = (D >= 2) ? map_axis(ry - ky, G.n[1], G.bc[1]) : 0;
-          const int uz = (D >= 3) ? map_axis(rz - kz, G.n[2], G.bc[2]) : 0;
-          const int ux = map_axis(xlo + i, Nx, G.bc[0]);
-          const int cell = (uz * G.n[1] + uy) * Nx + ux;
-          ldsv[idx] = recv[(size_t)cell * C16 + c];
-        }
-      }
-    }
-    __syncthreads();
-    if (!active) continue;
-
     const int uy = (D >= 2) ? map_axis(jy - ky, G.n[1], G.bc[1]) : 0;
     const int uz = (D >= 3) ? map_axis(jz - kz, G.n[2], G.bc[2]) : 0;
     const int ubase = (uz * G.n[1] + uy) * Nx;
-    const T* Lrow = lds + (size_t)tr * SW * RS;
+
+    // stage the records of the upstream row segment (16-byte chunks)
+    {
+      V* ldsv = reinterpret_cast<V*>(Lw);
+      const V* recv = reinterpret_cast<const V*>(a.rec_in);
+      if (D >= 2) {
+        wave_lds_sync();
+        for (int idx = lane; idx < SW * C16; idx += 64) {
+          const int c = idx % C16, i = idx / C16;
+          const int ux = map_axis(xlo + i, Nx, G.bc[0]);
+          ldsv[idx] = recv[(size_t)(ubase + ux) * C16 + c];
+        }
+        wave_lds_sync();
+      } else {
+        for (int idx = threadIdx.x; idx < SW * C16; idx += blockDim.x) {
+          const int c = idx % C16, i = idx / C16;
+          const int ux = map_axis(xlo + i, Nx, G.bc[0]);
+          ldsv[idx] = recv[(size_t)ux * C16 + c];
+        }
+        __syncthreads();
+      }
+    }
+    if (!active) continue;
+
     const size_t kbase = (size_t)vr * G.nv1;
     const T vyT = (T)vy, vzT = (T)vz;
     const T hrowT = (T)hrow;
     double aK0 = 0.0, aK1 = 0.0, aK2 = 0.0, aE0 = 0.0, aE1 = 0.0, aE2 = 0.0;
 
-    for (int ix0 = 0; ix0 < G.nv1; ix0 += UNR) {
+    for (int ix0 = ixa; ix0 < ixb; ix0 += UNR) {
       T gv[UNR];
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const int ix = ix0 + u;
         const int kx = ix - G.kofs;
         const T* gp = a.g_in + (kbase + ix) * (size_t)G.nc;
-        gv[u] = gp[ubase + map_x<BCX>(xN, kx, Nx)];
+        if (HOFKS_NT)
+          gv[u] = __builtin_nontemporal_load(gp + ubase + map_x<BCX>(xN, kx, Nx));
+        else
+          gv[u] = gp[ubase + map_x<BCX>(xN, kx, Nx)];
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
@@ -555,7 +591,7 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<T> a, Geom G, Mat A) {
         const double vx = vn.v;
         const T vxT = (sizeof(T) == 4) ? (T)vn.vf : (T)vn.v;
         const T vhT = (sizeof(T) == 4) ? (T)(hrowT + (T)vn.v2hf) : (T)(hrow + 0.5 * vn.v2);
-        const V* rp = reinterpret_cast<const V*>(Lrow + (tx - kx + lofs) * RS);
+        const V* rp = reinterpret_cast<const V*>(Lw + (lane - kx + lofs) * RS);
         T rv[NCH * PER16];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -603,7 +639,10 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<T> a, Geom G, Mat A) {
           aE2 += vn.v2 * Ed;
         }
         T* op = a.g_out + (kbase + ix) * (size_t)G.nc;
-        op[dest] = fs;
+        if (HOFKS_NT)
+          __builtin_nontemporal_store(fs, op + dest);
+        else
+          op[dest] = fs;
         const double fd = (double)fs;
         aK0 += fd;
         aK1 += vx * fd;
@@ -637,66 +676,64 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<T> a, Geom G, Mat A) {
       }
     }
   }
-  if (active) {
-    double* P = a.part + (size_t)chunk * 2 * NM * G.nc;
+
+  // ---------------------------------------------- combine the wavefronts
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(lds_raw);
+  if (grp > 0) {
+    double* q = red + ((size_t)(grp - 1) * 64 + lane) * (2 * NM);
 #pragma unroll
     for (int r = 0; r < NM; ++r) {
-      P[(size_t)r * G.nc + dest] = COMP ? SK[r] + CK[r] : SK[r];
-      if (!FT) P[(size_t)(NM + r) * G.nc + dest] = COMP ? SE[r] + CE[r] : SE[r];
+      q[r] = COMP ? SK[r] + CK[r] : SK[r];
+      q[NM + r] = COMP ? SE[r] + CE[r] : SE[r];
+    }
+  }
+  __syncthreads();
+  if (grp != 0) return;
+#pragma unroll
+  for (int r = 0; r < NM; ++r) {
+    if (COMP) {
+      SK[r] += CK[r];
+      SE[r] += CE[r];
+      CK[r] = CE[r] = 0.0;
+    }
+  }
+  for (int g2 = 1; g2 < NG; ++g2) {
+    const double* q = red + ((size_t)(g2 - 1) * 64 + lane) * (2 * NM);
+#pragma unroll
+    for (int r = 0; r < NM; ++r) {
+      if (COMP) {
+        two_sum(SK[r], CK[r], q[r]);
+        two_sum(SE[r], CE[r], q[NM + r]);
+      } else {
+        SK[r] += q[r];
+        SE[r] += q[NM + r];
+      }
     }
   }
 
-  // ------------------------------------------------ last chunk of the tile
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int old = atomicAdd(a.tile_cnt + tile, 1);
-    s_last = (old == a.nchunk - 1);
-    if (s_last) atomicExch(a.tile_cnt + tile, 0);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-
+  // ------------------------------------------------- per-cell update
   const bool need_eq = G.mu != 0.0;
-  int s = 0;
-  if (EUL) {
-    unsigned* ctrl = reinterpret_cast<unsigned*>(a.set_r + (SMAX + 1) * ASTR);
-    if (threadIdx.x == 0) spin_until_geq(ctrl + 1, 1u, a.flag);
-    __syncthreads();
-    __threadfence();
-    bool over;
-    s = substeps<D>(a.set_r, G, a.s_cap, &over);
-  }
   bool phys = true;
   double speed[3] = {0.0, 0.0, 0.0};
   if (active) {
-    double SKt[NM], SEt[NM];
-#pragma unroll
-    for (int r = 0; r < NM; ++r) SKt[r] = SEt[r] = 0.0;
-    for (int c = 0; c < a.nchunk; ++c) {
-      const double* P = a.part + (size_t)c * 2 * NM * G.nc;
-#pragma unroll
-      for (int r = 0; r < NM; ++r) {
-        SKt[r] += P[(size_t)r * G.nc + dest];
-        if (!FT) SEt[r] += P[(size_t)(NM + r) * G.nc + dest];
-      }
-    }
     double delta[NM];
 #pragma unroll
     for (int r = 0; r < NM; ++r) delta[r] = 0.0;
     if (EUL) {
+      bool over;
+      const int s = substeps<D>(a.set_r, G, a.s_cap, &over);
       const double* UEs = (s & 1) ? a.UE1 : a.UE0;
 #pragma unroll
       for (int r = 0; r < NM; ++r) {
-        const double UM = G.mu * (G.w * SEt[r]);
+        const double UM = G.mu * (G.w * (COMP ? SE[r] + CE[r] : SE[r]));
         const double UEv = G.mu * UEs[(size_t)r * G.nc + dest];
         delta[r] = UEv - UM;
       }
     }
     double Un[NM], cfv[NM];
 #pragma unroll
-    for (int r = 0; r < NM; ++r) Un[r] = G.w * SKt[r] + delta[r];
+    for (int r = 0; r < NM; ++r) Un[r] = G.w * (COMP ? SK[r] + CK[r] : SK[r]) + delta[r];
 #pragma unroll
     for (int r = 0; r < NM; ++r) {
       double acc = 0.0;
@@ -716,7 +753,7 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<T> a, Geom G, Mat A) {
 #pragma unroll
     for (int d2 = 0; d2 < D; ++d2) {
       const double m = wave_max(phys ? speed[d2] : 0.0);
-      if ((threadIdx.x & 63) == 0) atomic_max_pos(a.set_w + d2, m);
+      if (lane == 0) atomic_max_pos(a.set_w + d2, m);
     }
   }
 }

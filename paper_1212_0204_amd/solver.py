@@ -126,6 +126,14 @@ class Solver:
     def dt(self):
         return _lib.lib().hofks_dt(self._h)
 
+    def autotune(self, steps=4, cache_path=None):
+        """time the candidate launch configurations (advances the state: set
+        it again afterwards); returns the chosen pair"""
+        ch = (ctypes.c_int * 2)()
+        cp = cache_path.encode() if cache_path else None
+        self._check(_lib.lib().hofks_autotune(self._h, int(steps), cp, ch), "autotune")
+        return int(ch[0]), int(ch[1])
+
 
 class Batch(Solver):
     """Independent 1D-1V outflow tubes in FP32 pieces, advanced together (one
@@ -196,9 +204,3 @@ class Batch(Solver):
         fl = (ctypes.c_int * len(self.tubes))()
         self._check(_lib.lib().hofks_batch_tube_flags(self._h, fl), "batch_tube_flags")
         return np.array(list(fl))
-
-    def autotune(self, steps=4, cache_path=None):
-        ch = (ctypes.c_int * 2)()
-        cp = cache_path.encode() if cache_path else None
-        self._check(_lib.lib().hofks_autotune(self._h, int(steps), cp, ch), "autotune")
-        return int(ch[0]), int(ch[1])

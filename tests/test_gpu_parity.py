@@ -203,3 +203,27 @@ def test_tau_change_mid_run_matches_oracle():
         s.step(3)
     assert moment_errors(s.read_moments(), o.U, 1).max() < TOL64
     assert rel_inf(s.read_f(), o.f) < TOL64
+
+
+@gpu
+def test_grid_autotune_then_parity(tmp_path):
+    """the autotuner picks a kinetic configuration (and reuses a cached one);
+    results after re-initialisation still match the oracle"""
+    announce("grid autotune")
+    n = (96, 40)
+    rho, u, th = W.perturbed_gas(96, 2, 0.2, 0.1, 4, (51, 52))
+    rho = rho.reshape(96, 96)[:40].reshape(-1)
+    th = th.reshape(96, 96)[:40].reshape(-1)
+    u = u[:, :96 * 40]
+    s = _solver(dim=2, n_cells=n, dx=1 / 96, n_vel=16, dv=0.5, bc=(0, 0), tau=1e-3)
+    s.set_state_macro(rho, u, th)
+    cache = str(tmp_path / "tune.jsonl")
+    ng, unr = s.autotune(steps=2, cache_path=cache)
+    assert ng in (2, 4) and unr in (8, 16)
+    assert s.autotune(steps=2, cache_path=cache) == (ng, unr)
+    s.set_state_macro(rho, u, th)
+    s.step(6)
+    o = Oracle(2, n, 1 / 96, 16, 0.5, bc=(0, 0), tau=1e-3)
+    o.init_macro(rho, u, th)
+    o.step(6)
+    assert moment_errors(s.read_moments(), o.U, 2).max() < TOL64

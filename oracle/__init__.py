@@ -33,8 +33,8 @@ def _lib():
     global _LIB
     if _LIB is None:
         path = os.path.join(_HERE, "libhofks_oracle.so")
-        if not os.path.exists(path) or (
-                os.path.getmtime(path) < os.path.getmtime(_build.SRC)):
+        if not os.path.exists(path) or any(
+                os.path.getmtime(path) < os.path.getmtime(src) for src in _build.SOURCES):
             _build.build()
         lib = ctypes.CDLL(path)
         P = ctypes.POINTER
@@ -58,6 +58,11 @@ def _lib():
         lib.or_maxwellian.argtypes = [vp, dp, dp]
         lib.or_equilibrium.argtypes = [vp, dp, dp]
         lib.or_muscl.argtypes = [vp, dp, d, P(i)]
+        lib.mlp_nparam.restype = i
+        lib.mlp_forward.argtypes = [dp, dp, dp, i]
+        lib.mlp_loss_grad.argtypes = [dp, dp, dp, i, dp]
+        lib.mlp_loss_grad.restype = d
+        lib.mlp_adam.argtypes = [dp, dp, dp, dp, d, d, d, d, i]
         _LIB = lib
     return _LIB
 
@@ -182,3 +187,36 @@ class Oracle:
         if st:
             raise OracleError(st, "muscl")
         return U, ns.value
+
+
+# ------------------------------------------------------ closure network (FP64)
+MLP_NIN, MLP_NH, MLP_NOUT = 37, 64, 4
+
+
+def mlp_nparam():
+    return _lib().mlp_nparam()
+
+
+def mlp_forward(params, x):
+    """y = MLP(x) for x of shape (n, 37); FP64"""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, MLP_NIN)
+    y = np.empty((x.shape[0], MLP_NOUT))
+    _lib().mlp_forward(_dp(p), _dp(x), _dp(y), x.shape[0])
+    return y
+
+
+def mlp_loss_grad(params, x, t):
+    """(loss, gradient) of L = mean (y - t)^2 over samples and outputs"""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, MLP_NIN)
+    t = np.ascontiguousarray(t, dtype=np.float64).reshape(-1, MLP_NOUT)
+    g = np.empty(mlp_nparam())
+    loss = _lib().mlp_loss_grad(_dp(p), _dp(x), _dp(t), x.shape[0], _dp(g))
+    return loss, g
+
+
+def mlp_adam(params, grad, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8):
+    """one Adam step in place on params, m, v (FP64 arrays)"""
+    g = np.ascontiguousarray(grad, dtype=np.float64)
+    _lib().mlp_adam(_dp(params), _dp(g), _dp(m), _dp(v), lr, b1, b2, eps, int(step))

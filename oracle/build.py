@@ -9,6 +9,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hofks_oracle.c")
+SOURCES = [SRC, os.path.join(HERE, "mlp_oracle.c")]
 LIB = os.path.join(HERE, "libhofks_oracle.so")
 
 
@@ -16,7 +17,7 @@ def build(verbose: bool = False) -> str:
     # -ffp-contract=off keeps every product and sum as written (no fused FMA)
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
            "-fPIC", "-shared", "-std=c11", "-D_DEFAULT_SOURCE", "-Wall",
-           "-o", LIB + ".tmp", SRC, "-lm"]
+           "-o", LIB + ".tmp", *SOURCES, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,11 +1,10 @@
 // batch.hpp -- batched persistent form: many independent 1D-1V tubes (each
-// with its own cells, velocity grid, dt and tau) advanced by one launch per
-// step.  Blocks pull work items from a queue: first one Euler item per tube
-// (the tube's s MUSCL sub-steps inside one 1024-thread block, largest tubes
-// first), then kinetic items (a CELLS-cell segment of one tube, all its
-// velocities split over 1024/CELLS groups of threads).  A kinetic item ends
-// with the per-cell update of its segment once its tube's Euler item is done.
-// Every Euler item is dequeued before any kinetic item, so every wait ends.
+// with its own cells, velocity grid, dt and tau) advanced together.  A step is
+// two launches: the Euler launch runs every tube's s MUSCL sub-steps, one
+// 1024-thread block per tube (largest first); the kinetic launch is a
+// persistent grid pulling items from a queue, an item being a CELLS-cell
+// segment of one tube with all its velocities split over 1024/CELLS groups of
+// threads, ending with the per-cell update of the segment.
 #pragma once
 #include "kernels.hpp"
 
@@ -34,7 +33,7 @@ struct BatchArgs {
   int ntubes, nitems;
   int* queue;             // work counters by step parity
   double* alpha;          // [tube][parity][ASTR]: speeds of U^n / U^{n+1}
-  int* done;              // [tube][parity]: Euler item finished
+  int* done;              // unused
   int* tube_s;            // sub-steps of the current step, per tube
   int* tflag;             // per-tube error bits
   int* flag;              // launch-wide bits (bounded waits)
@@ -85,8 +84,7 @@ __device__ void batch_euler_item(const BatchArgs& a, int t, double* red) {
   bool over;
   const int s = substeps<1>(&alpha, G, a.s_cap, &over);
   if (threadIdx.x == 0) {
-    alpha_w[0] = 0.0;
-    a.done[(size_t)t * 2 + (p ^ 1)] = 0;
+    alpha_w[0] = 0.0;  // the kinetic launch reduces the speeds of U^{n+1} here
     a.tube_s[t] = s;
     if (over) atomicOr(a.tflag + t, FLAG_SUBSTEP);
   }
@@ -115,10 +113,6 @@ __device__ void batch_euler_item(const BatchArgs& a, int t, double* red) {
     }
     if (!phys) atomicOr(a.tflag + t, FLAG_NONPHYS);
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0)
-    __hip_atomic_store(a.done + (size_t)t * 2 + p, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int CELLS, int UNR>
@@ -211,10 +205,7 @@ __device__ void batch_kinetic_item(const BatchArgs& a, int it, unsigned char* ld
     q[4] = aE1;
     q[5] = aE2;
   }
-  // the tube's Euler solve must be finished before the update
-  if (threadIdx.x == 0) spin_until_geq((unsigned*)(a.done + (size_t)t * 2 + p), 1u, a.flag);
   __syncthreads();
-  __threadfence();
   if (vg != 0) return;
   bool phys = true;
   double speed = 0.0;
@@ -260,24 +251,28 @@ __device__ void batch_kinetic_item(const BatchArgs& a, int it, unsigned char* ld
   if ((threadIdx.x & 63) == 0) atomic_max_pos(a.alpha + ((size_t)t * 2 + (p ^ 1)) * ASTR, m);
 }
 
+// Euler launch: one 1024-thread block per tube, the tubes with the most
+// Euler work first.
+__global__ __launch_bounds__(1024) void k_batch_euler(BatchArgs a) {
+  __shared__ double red[16];
+  batch_euler_item(a, a.euler_order[blockIdx.x], red);
+}
+
+// Kinetic launch: persistent blocks pull (tube, segment) items from a queue,
+// the items with the most work first; the Euler launch of the step is done.
 template <int CELLS, int UNR>
-__global__ __launch_bounds__(1024) void k_batch_step(BatchArgs a) {
+__global__ __launch_bounds__(1024) void k_batch_kinetic(BatchArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   __shared__ int s_item;
-  __shared__ double red[16];
   const int p = a.parity;
   if (blockIdx.x == 0 && threadIdx.x == 0) a.queue[p ^ 1] = 0;  // for the next step
-  const int total = a.ntubes + a.nitems;
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) s_item = atomicAdd(a.queue + p, 1);
     __syncthreads();
     const int item = s_item;
-    if (item >= total) break;
-    if (item < a.ntubes)
-      batch_euler_item(a, a.euler_order[item], red);
-    else
-      batch_kinetic_item<CELLS, UNR>(a, item - a.ntubes, lds_raw);
+    if (item >= a.nitems) break;
+    batch_kinetic_item<CELLS, UNR>(a, item, lds_raw);
   }
 }
 

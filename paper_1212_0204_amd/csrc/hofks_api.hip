@@ -971,9 +971,10 @@ BatchArgs batch_args(hofks_ctx* c, int parity) {
 hofks_status batch_launch(hofks_ctx* c, hipStream_t stream, int parity) {
   Batch* B = c->batch;
   const BatchArgs a = batch_args(c, parity);
+  hipLaunchKernelGGL(k_batch_euler, dim3(B->n), dim3(1024), 0, stream, a);
   const dim3 grid(B->grid), block(1024);
 #define BL(CELLS, UNR) \
-  hipLaunchKernelGGL((k_batch_step<CELLS, UNR>), grid, block, B->lds, stream, a)
+  hipLaunchKernelGGL((k_batch_kinetic<CELLS, UNR>), grid, block, B->lds, stream, a)
   const int u = B->unr;
   switch (B->cells) {
     case 128:

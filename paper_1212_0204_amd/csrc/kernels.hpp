@@ -37,7 +37,10 @@ namespace hofks {
 
 constexpr int SMAX = 512;         // largest Euler sub-step count a plan may use
 constexpr int ASTR = 4;           // doubles per row of Lax-Friedrichs speeds
-constexpr int SET_D = (SMAX + 1) * ASTR + 8;  // doubles per slot set (+ 16 control ints)
+// doubles per slot set: speed rows, then control words (barrier counters,
+// each on its own 64-byte line)
+constexpr int CTRL_LINES = 10;
+constexpr int SET_D = (SMAX + 1) * ASTR + CTRL_LINES * 8;
 constexpr int FLAG_NONPHYS = 1;
 constexpr int FLAG_SUBSTEP = 2;
 constexpr int FLAG_SPIN = 4;      // a bounded wait gave up: results are invalid
@@ -196,14 +199,15 @@ template <int D>
 __device__ __forceinline__ bool split_flux(const double* U, int a, double alpha, double gam,
                                            double* Wp, double* Wm) {
   constexpr int NM = D + 2;
-  double rho = U[0], usq = 0.0, u[3];
+  const double rho = U[0], irho = 1.0 / rho;
+  double usq = 0.0, u[3];
 #pragma unroll
   for (int b = 0; b < D; ++b) {
-    u[b] = U[1 + b] / rho;
+    u[b] = U[1 + b] * irho;
     usq += u[b] * u[b];
   }
-  const double th = (2.0 * U[NM - 1] - rho * usq) / (D * rho);
-  const double p = rho * th;
+  // p = rho theta = (2E - rho |u|^2) / d
+  const double p = (2.0 * U[NM - 1] - rho * usq) * (1.0 / D);
   double F[NM];
   F[0] = U[1 + a];
 #pragma unroll
@@ -214,7 +218,7 @@ __device__ __forceinline__ bool split_flux(const double* U, int a, double alpha,
     Wp[r] = F[r] + alpha * U[r];
     Wm[r] = F[r] - alpha * U[r];
   }
-  return (rho > 0.0) && (th > 0.0) && isfinite(rho) && isfinite(th) && isfinite(usq);
+  return (rho > 0.0) && (p > 0.0) && isfinite(rho) && isfinite(p) && isfinite(usq);
 }
 
 // |u_a| + c for every axis; false if the state is not physical
@@ -236,10 +240,19 @@ __device__ __forceinline__ bool lf_speeds(const double* U, double gam, double* s
   return ok;
 }
 
+// Van Leer slope 2ab/(a+b) for ab > 0, else 0.  The quotient uses the
+// hardware reciprocal refined by two Newton steps (error within a few ulp of
+// the IEEE quotient); a + b cannot vanish when ab > 0.
 __device__ __forceinline__ double vl_slope(double a, double b, int unlimited) {
   if (unlimited) return b;
   const double ab = a * b;
-  return ab > 0.0 ? 2.0 * ab / (a + b) : 0.0;
+  if (!(ab > 0.0)) return 0.0;
+  const double den = a + b;
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(fma(-den, r, 1.0), r, r);
+  r = fma(fma(-den, r, 1.0), r, r);
+  const double q = 2.0 * ab * r;
+  return fma(fma(-den, q, 2.0 * ab), r, q);
 }
 
 // new value of cell j after one sub-step: in - dt_s/dx sum_a (psi_a+ - psi_a-).
@@ -443,9 +456,11 @@ __global__ __launch_bounds__(256) void k_euler(StepArgs<T> a, Geom G) {
     }
     if (!phys) atomicOr(a.flag, FLAG_NONPHYS);
     if (i + 1 < s) {
-      // block maxima into bmax[(i+1) % 2][block], then every block reduces
-      // all of them after the barrier (max is exact: all blocks agree)
-      double* bm = a.bmax + (size_t)((i + 1) & 1) * a.GE * ASTR;
+      // block maxima into bmax[block]; two-level barrier: blocks arrive on
+      // one of 8 group counters, the last of each group on the top counter,
+      // and the very last block reduces all maxima into row i+1 of set_r
+      // and releases everyone through the generation word
+      double* bm = a.bmax;
 #pragma unroll
       for (int d2 = 0; d2 < D; ++d2) {
         const double m = wave_max(mx[d2]);
@@ -457,21 +472,61 @@ __global__ __launch_bounds__(256) void k_euler(StepArgs<T> a, Geom G) {
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, wmax[w][threadIdx.x]);
         bm[(size_t)blockIdx.x * ASTR + threadIdx.x] = m;
       }
-      group_barrier(ctrl, (unsigned)((i + 1) * a.GE), a.flag);
+      __syncthreads();
+      __shared__ int s_last;
+      unsigned* gen = ctrl;  // line 0: generation
+      if (threadIdx.x == 0) {
+        const unsigned g = blockIdx.x & 7u;
+        const unsigned ng = (a.GE - g + 7) / 8;  // blocks in group g
+        const unsigned ngroups = a.GE < 8 ? a.GE : 8;
+        unsigned* top = ctrl + 16;               // line 1: top counter
+        unsigned* sub = ctrl + 32 + 16 * g;      // lines 2..9: group counters
+        __threadfence();
+        int last = 0;
+        const unsigned old = atomicAdd(sub, 1u);
+        if (old == (unsigned)(i + 1) * ng - 1) {
+          const unsigned t = atomicAdd(top, 1u);
+          last = (t == (unsigned)(i + 1) * ngroups - 1);
+        }
+        s_last = last;
+      }
+      __syncthreads();
+      if (s_last) {  // the whole last block reduces the block maxima
+        __threadfence();
+        double m[3] = {0.0, 0.0, 0.0};
+        for (int b = threadIdx.x; b < a.GE; b += blockDim.x)
 #pragma unroll
-      for (int d2 = 0; d2 < D; ++d2) {
-        double m = 0.0;
-        for (int b = threadIdx.x; b < a.GE; b += blockDim.x) m = fmax(m, bm[(size_t)b * ASTR + d2]);
-        m = wave_max(m);
-        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6][d2] = m;
+          for (int d2 = 0; d2 < D; ++d2)
+            m[d2] = fmax(m[d2], __hip_atomic_load(bm + (size_t)b * ASTR + d2, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT));
+#pragma unroll
+        for (int d2 = 0; d2 < D; ++d2) {
+          const double w = wave_max(m[d2]);
+          if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6][d2] = w;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll
+          for (int d2 = 0; d2 < D; ++d2) {
+            double w = wmax[0][d2];
+            for (int q = 1; q < (int)(blockDim.x >> 6); ++q) w = fmax(w, wmax[q][d2]);
+            __hip_atomic_store(S + (i + 1) * ASTR + d2, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          __threadfence();
+          __hip_atomic_store(gen, (unsigned)(i + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      if (threadIdx.x == 0) {
+        spin_until_geq(gen, (unsigned)(i + 1), a.flag);
+        __threadfence();
+#pragma unroll
+        for (int d2 = 0; d2 < D; ++d2)
+          wmax[0][d2] = __hip_atomic_load(S + (i + 1) * ASTR + d2, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
       }
       __syncthreads();
 #pragma unroll
-      for (int d2 = 0; d2 < D; ++d2) {
-        double m = wmax[0][d2];
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, wmax[w][d2]);
-        alpha[d2] = m;
-      }
+      for (int d2 = 0; d2 < D; ++d2) alpha[d2] = wmax[0][d2];
       __syncthreads();
     }
   }

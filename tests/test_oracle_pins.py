@@ -327,3 +327,43 @@ def test_bad_descriptors_rejected():
         Oracle(1, (2,), 0.1, 1, 0.5)
     with pytest.raises(OracleError):
         Oracle(1, (2,), 0.1, 8, 0.5, tau=-1.0)
+
+
+# -------------------------------------------- closure network (not in the paper)
+def test_mlp_gradient_matches_central_differences():
+    """back-propagated gradient of the FP64 closure network vs central finite
+    differences of its own forward pass"""
+    from oracle import mlp_forward, mlp_loss_grad, mlp_nparam
+    rng = np.random.default_rng(12)
+    p = 0.2 * rng.standard_normal(mlp_nparam())
+    x = rng.standard_normal((5, 37))
+    t = rng.standard_normal((5, 4))
+    loss, g = mlp_loss_grad(p, x, t)
+    assert abs(loss - ((mlp_forward(p, x) - t) ** 2).mean()) < 1e-14
+    idx = rng.choice(p.size, 60, replace=False)
+    h = 1e-6
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (mlp_loss_grad(pp, x, t)[0] - mlp_loss_grad(pm, x, t)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-9, (i, fd, g[i])
+
+
+def test_mlp_zero_weights_give_bias_and_adam_descends():
+    from oracle import mlp_adam, mlp_forward, mlp_loss_grad, mlp_nparam
+    n = mlp_nparam()
+    p = np.zeros(n)
+    p[-4:] = [0.1, -0.2, 0.3, -0.4]  # output bias
+    x = np.random.default_rng(0).standard_normal((3, 37))
+    np.testing.assert_array_equal(mlp_forward(p, x), np.tile(p[-4:], (3, 1)))
+    rng = np.random.default_rng(1)
+    p = 0.3 * rng.standard_normal(n)
+    x = rng.standard_normal((64, 37))
+    t = np.tanh(x[:, :4])
+    m, v = np.zeros(n), np.zeros(n)
+    l0 = mlp_loss_grad(p, x, t)[0]
+    for k in range(1, 51):
+        _, g = mlp_loss_grad(p, x, t)
+        mlp_adam(p, g, m, v, 1e-3, k)
+    assert mlp_loss_grad(p, x, t)[0] < 0.7 * l0

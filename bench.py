@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -60,8 +62,7 @@ def run_solver(wl, steps, warmup, precision, scheme=0):
     out = {
         "cv_per_s": cv / (ms * 1e-3),
         "ms_per_step": ms / steps,
-        "kernel_ms_per_step": {"euler": kms[0] / max(cnt[0], 1), "kinetic": kin_ms,
-                               "cell_update": kms[2] / max(cnt[2], 1)},
+        "kernel_ms_per_step": {"euler": kms[0] / max(cnt[0], 1), "kinetic": kin_ms},
         "euler_substeps_last_step": substeps,
         "kinetic_GBps": achieved,
         "kinetic_hbm_frac": achieved / HBM_PEAK_GBPS,
@@ -113,6 +114,74 @@ def run_batch(steps, warmup):
     del b
     torch.cuda.empty_cache()
     return out
+
+
+def run_closure(warmup=2):
+    """the learned-closure form on the 512^2 disk (FP32 pieces, tau = 1e-4,
+    100 steps).  The network is first trained with the library's kernels on
+    snapshots of nine 128^2 runs (same dx); then the plain FP32 run and the
+    closure run (threshold 1e-3) are timed from the same initial state.
+    Effective cv/s counts every cell and velocity of every step."""
+    import torch
+    import workloads as W
+    from paper_1212_0204_amd import Solver
+    from paper_1212_0204_amd.mlp import ClosureNet, collect_snapshots
+
+    t0 = time.perf_counter()
+    x, t = collect_snapshots(W.closure_runs(seed=21, count=9), steps_at=[1, 3, 6, 10, 16, 24])
+    net = ClosureNet(seed=0)
+    scale, losses, used = net.fit_closure(x, t, steps=4000, log_every=3999)
+    nsamp = int(x.shape[0])
+    del x, t
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+
+    wl = W.DISK_2D
+    fields = W.initial_fields(wl)
+
+    def timed(closure):
+        s = Solver(wl.d, wl.n, wl.dx, wl.nv, wl.dv, bc=wl.bc, precision=1, tau=wl.tau)
+        s.set_state_macro(*fields)
+        s.autotune(steps=3)
+        for phase in ("warmup", "timed"):
+            s.set_state_macro(*fields)
+            if closure:
+                s.closure_enable(net, threshold=1e-3)
+            if phase == "warmup":
+                s.step(warmup)
+                s.sync()
+                continue
+            s.kernel_timing(enable=True)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s.stream)
+            s.step(wl.steps)
+            e1.record(s.stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            kms, cnt = s.kernel_timing(enable=False)
+        U = s.read_moments()
+        cs, kin = s.closure_stats()
+        del s
+        torch.cuda.empty_cache()
+        per = [k / max(c, 1) for k, c in zip(kms, cnt)]
+        return ms, U, kin / max(cs * wl.nc, 1), per
+
+    ms_p, Up, _, per_p = timed(False)
+    ms_c, Uc, frac, per_c = timed(True)
+    cv = wl.cv * wl.steps
+    return {"workload": wl.name, "steps": wl.steps, "tau": wl.tau, "threshold": 1e-3,
+            "cv_per_s": cv / (ms_c * 1e-3), "ms_per_step": ms_c / wl.steps,
+            "plain_fp32_cv_per_s": cv / (ms_p * 1e-3), "plain_fp32_ms_per_step": ms_p / wl.steps,
+            "speedup_vs_plain_fp32_same_workload": ms_p / ms_c,
+            "l1_density_error_vs_plain_fp32": float(np.abs(Uc[0] - Up[0]).sum() / np.abs(Up[0]).sum()),
+            "kinetic_cell_fraction": frac,
+            "kernel_ms_per_step": {"euler": per_c[0], "kinetic": per_c[1], "closure_network": per_c[2]},
+            "plain_kernel_ms_per_step": {"euler": per_p[0], "kinetic": per_p[1]},
+            "training": {"seconds_incl_snapshots": train_s, "samples": nsamp, "used": used,
+                         "adam_steps": 4000, "loss_first_last": [losses[0][1], losses[-1][1]],
+                         "output_scales": [float(v) for v in scale]}}
 
 
 def copy_probe(mb, reps=5):
@@ -169,7 +238,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp32_3d,fp64_3d,batched")
+    ap.add_argument("--forms", default="fp32_3d,fp64_3d,batched,closure")
     ap.add_argument("--copy-probe-mb", type=int, default=1024,
                     help="size of a plain device copy timed after the run (0: skip)")
     args = ap.parse_args()
@@ -193,6 +262,8 @@ def main():
                                **run_solver(W.GAS_3D, W.GAS_3D.steps, 2, 0))
         elif name == "batched":
             forms[name] = run_batch(500, 16)
+        elif name == "closure":
+            forms[name] = run_closure()
     if "fp32_3d" in forms and "fp64_3d" in forms:
         forms["fp32_3d"]["speedup_vs_fp64_same_workload"] = (
             forms["fp32_3d"]["cv_per_s"] / forms["fp64_3d"]["cv_per_s"])

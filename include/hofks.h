@@ -106,7 +106,8 @@ hofks_status hofks_read_counters(hofks_ctx *ctx, int *substeps, long *steps);
 
 /* Per-kernel timing with hipEvents recorded on the context's stream around
  * each launch group of hofks_step: group 0 = the Euler sub-steps, 1 = the
- * kinetic kernel (relaxation, shift, moment sums), 2 = the per-cell update.
+ * kinetic kernel (relaxation, shift, moment sums, per-cell update), 2 = the
+ * closure network and its indicator (closure form only).
  * If ms/launches are non-null, synchronise and return the summed elapsed
  * milliseconds and the launch counts of each group since the last call, then
  * clear them; enable != 0 keeps recording for the following steps. */
@@ -151,6 +152,70 @@ hofks_status hofks_batch_tube_flags(hofks_ctx *ctx, int *flags);
  * appended.  choice[2] may be NULL. */
 hofks_status hofks_autotune(hofks_ctx *ctx, int steps, const char *cache_path,
                             int choice[2]);
+
+/* ------------------------------------------------- learned closure (2D-2V)
+ * Not part of the paper: near-equilibrium cells skip the pieces.  The moment
+ * update of eq. (UK) with (mom) splits into the transported equilibrium,
+ * the Euler part U_E and the non-equilibrium term
+ *   N_j = sum_k w m_k (f* - E)(j - k, k) = lambda sum_k w m_k (f - E)(j - k, k).
+ * In a closure cell U^{n+1} = lambda sum_k w m_k E(j - k, k) + U_E + N^ with
+ * N^ = lambda * sigma * (y - y0) (.) (rho, rho c, rho c, E)_j, y the network
+ * output on the 3 x 3 stencil of U^n (37 inputs, see hofks_closure_snapshot)
+ * and y0 its output on a uniform stencil.  A cell runs the full kinetic
+ * step (eqs. (UK), (mom), (minim_full)) when lambda sigma max|y - y0| >
+ * threshold, when its last kinetic step had lambda max|delta| / s >
+ * threshold (every cell counts as such for the first step after the state
+ * is set), or when such a cell lies within
+ * n_vel/2 cells along each axis; kinetic cells that read an upstream closure
+ * cell use its equilibrium.  Needs dim 2 and scheme 0; a step with tau = +inf
+ * or 0 runs the plain scheme. */
+
+/* Network: device pointer to hofks_mlp_packed_bytes() bytes (16-byte
+ * aligned) written by hofks_mlp_pack; owned by the caller and read by every
+ * following step until hofks_closure_disable.  sigma scales the output;
+ * threshold < 0 makes every cell kinetic, +INF every cell a closure cell
+ * (up to the delta marks, also compared with it). */
+hofks_status hofks_closure_enable(hofks_ctx *ctx, const void *packed_weights,
+                                  double sigma, double threshold);
+/* Back to the plain scheme; the next step runs every cell kinetic and
+ * rebuilds the pieces of former closure cells from their equilibrium. */
+hofks_status hofks_closure_disable(hofks_ctx *ctx);
+/* One plain step (every cell kinetic) that also writes, for each cell j,
+ * the network inputs of U^n to x[j][37] (device, FP32): for stencil cell
+ * c = 3 (dy + 1) + (dx + 1) the values rho_c/rho_j - 1, (u_c - u_j)/c_j (x,
+ * y), theta_c/theta_j - 1, then log10(tau/dt) clamped to [-8, 8]; and the target
+ * N_j / (lambda s_j) to t[j][4] (device, FP32), s_j = (rho, rho c, rho c, E)
+ * of U^n, c = sqrt(gamma theta).  Needs 1e-12 <= lambda < 1. */
+hofks_status hofks_closure_snapshot(hofks_ctx *ctx, float *x, float *t);
+/* Closure steps run since the state was set, and the kinetic cell-steps
+ * among them.  Synchronous. */
+hofks_status hofks_closure_stats(hofks_ctx *ctx, long *closure_steps,
+                                 unsigned long long *kinetic_cell_steps);
+
+/* The network, on the matrix cores: 37 -> 64 -> 64 -> 64 -> 4, tanh hidden
+ * layers, BF16 weights and activations, FP32 accumulation.  FP32 parameters
+ * are flat: W1[64][37] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[4][64]
+ * b4[4] (weights row-major, output index first).  All pointers are device
+ * pointers owned by the caller; calls are asynchronous on `stream` and
+ * return HOFKS_EINVAL for bad arguments, HOFKS_EDEVICE for a failed launch. */
+int hofks_mlp_nparam(void);          /* 11012 */
+size_t hofks_mlp_packed_bytes(void); /* bytes of the packed form */
+/* FP32 parameters -> packed BF16 form read by the kernels (16-byte aligned) */
+hofks_status hofks_mlp_pack(const float *params, void *packed, void *stream);
+/* y[n][4] = net(x[n][37]); y 16-byte aligned */
+hofks_status hofks_mlp_forward(const void *packed, const float *x, float *y, long n,
+                               void *stream);
+/* grad[11012] (overwritten) and *loss of L = (1/(4n)) sum (y - t)^2 over a
+ * batch of n samples, sample s being row idx[s] of x[.][37] and t[.][4]
+ * (row s if idx is NULL); evaluated at the packed weights. */
+hofks_status hofks_mlp_grad(const void *packed, const float *x, const float *t,
+                            const int *idx, long n, float *grad, float *loss,
+                            void *stream);
+/* One Adam step (bias-corrected, step counts from 1) on FP32 params, m, v.
+ * Pack again afterwards. */
+hofks_status hofks_mlp_adam(float *params, const float *grad, float *m, float *v,
+                            float lr, float beta1, float beta2, float eps, int step,
+                            void *stream);
 
 #ifdef __cplusplus
 }

@@ -19,6 +19,9 @@ SYMBOLS = [
     "hofks_set_state_f", "hofks_step", "hofks_sync", "hofks_read_moments", "hofks_read_f",
     "hofks_read_counters", "hofks_kernel_timing", "hofks_dt", "hofks_batch_workspace_size",
     "hofks_batch_create", "hofks_batch_tube_flags", "hofks_autotune", "hofks_last_error", "hofks_destroy",
+    "hofks_closure_enable", "hofks_closure_disable", "hofks_closure_snapshot", "hofks_closure_stats",
+    "hofks_mlp_nparam", "hofks_mlp_packed_bytes", "hofks_mlp_pack", "hofks_mlp_forward",
+    "hofks_mlp_grad", "hofks_mlp_adam",
 ]
 
 
@@ -64,5 +67,16 @@ def lib():
     L.hofks_last_error.restype = ctypes.c_char_p
     L.hofks_destroy.argtypes = [vp]
     L.hofks_destroy.restype = None
+    L.hofks_closure_enable.argtypes = [vp, vp, d, d]
+    L.hofks_closure_disable.argtypes = [vp]
+    L.hofks_closure_snapshot.argtypes = [vp, vp, vp]
+    L.hofks_closure_stats.argtypes = [vp, P(ctypes.c_long), P(ctypes.c_ulonglong)]
+    L.hofks_mlp_nparam.restype = i
+    L.hofks_mlp_packed_bytes.restype = sz
+    L.hofks_mlp_pack.argtypes = [vp, vp, vp]
+    L.hofks_mlp_forward.argtypes = [vp, vp, vp, ctypes.c_long, vp]
+    L.hofks_mlp_grad.argtypes = [vp, vp, vp, vp, ctypes.c_long, vp, vp, vp]
+    L.hofks_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, i, vp]
     _lib = L
     return L

@@ -22,7 +22,9 @@
 
 #include "hofks.h"
 #include "batch.hpp"
+#include "closure.hpp"
 #include "kernels.hpp"
+#include "mlp.hpp"
 
 using namespace hofks;
 
@@ -40,6 +42,7 @@ struct Plan {
   // workspace offsets (bytes)
   size_t off_g[2], off_U[2], off_UE[2], off_rec[2], off_vt, off_cf, off_part, off_slots,
       off_tiles, off_flag;
+  size_t off_clos;  // closure form (2D): N^, indicator, dilation, mode, delta marks, count
   size_t total;
 };
 
@@ -211,6 +214,12 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
   off = align256(off + (size_t)2 * 256 * ASTR * sizeof(double));
   P->off_flag = off;
   off = align256(off + 64);
+  if (d == 2) {
+    P->off_clos = off;
+    off = align256(off + (size_t)G.nc * sizeof(float4));
+    off = align256(off + 4 * (size_t)G.nc);
+    off = align256(off + 256);
+  }
   P->total = off;
   return HOFKS_OK;
 }
@@ -244,6 +253,17 @@ struct hofks_ctx {
   std::vector<MarkRec> ev_marks;
   size_t ev_next;
   struct Batch* batch;  // non-null for a batch of independent tubes
+  // closure form (2D-2V): network (caller's device memory), scale of its
+  // output, indicator threshold; per-cell arrays in the workspace
+  const void* clos_w;
+  double clos_sigma, clos_thr;
+  bool clos_on;
+  bool clos_dirty;  // some record marks a cell without pieces
+  float4* nhat;
+  unsigned char *cflag, *ctmp, *cmode, *cdfl;
+  unsigned long long* kcount;
+  float* clos_y0;
+  long clos_steps;
   char err[512];
 };
 
@@ -344,8 +364,11 @@ void dispatch_kin(hofks_ctx* c, const StepArgs<T>& a, dim3 grid) {
 #undef K
 }
 
+template <typename T>
+hofks_status launch_closure_step(hofks_ctx* c, StepArgs<T>& a, float* snap_x, float* snap_t);
+
 template <int D, typename T>
-hofks_status launch_step(hofks_ctx* c) {
+hofks_status launch_step(hofks_ctx* c, float* snap_x = nullptr, float* snap_t = nullptr) {
   const Plan& P = c->P;
   const int rp = rpar(c);
   const long n = c->steps;
@@ -369,8 +392,22 @@ hofks_status launch_step(hofks_ctx* c) {
   a.GE = P.GE;
   a.s_cap = c->s_cap;
   a.unlimited = (int)(c->desc.scheme == 2);
+  a.mode = nullptr;
+  a.nhat = nullptr;
+  a.dfl = nullptr;
+  a.tgt = nullptr;
+  a.kcount = nullptr;
+  a.thr = 0.0;
   const bool ft = (P.G.mu == 0.0);
   const bool eul = !ft && c->desc.scheme != 1;
+  if (c->clos_dirty && !eul) {
+    fmt_err(c->err, "after closure steps, run a step with finite tau and the HOFKS scheme first");
+    return HOFKS_ESTATE;
+  }
+  if constexpr (D == 2) {
+    if ((c->clos_on || snap_x || c->clos_dirty) && eul)
+      return launch_closure_step<T>(c, a, snap_x, snap_t);
+  }
   if (eul) {
     Mark m0(c, 0);
     hipLaunchKernelGGL((k_euler<D, T>), dim3(P.GE), dim3(256), 0, c->stream, a, P.G);
@@ -385,6 +422,83 @@ hofks_status launch_step(hofks_ctx* c) {
   else
     dispatch_kin<D, T, false, false>(c, a, grid);
   HIPCHK(c, hipGetLastError());
+  return HOFKS_OK;
+}
+
+// closure step (2D): indicator and N^ from the network (or, for a training
+// snapshot, every cell kinetic and the inputs of U^n stored), dilation by
+// the reach of one shift, Euler solve, kinetic kernel in its closure form
+template <typename T>
+hofks_status launch_closure_step(hofks_ctx* c, StepArgs<T>& a, float* snap_x, float* snap_t) {
+  const Plan& P = c->P;
+  const int nc = P.G.nc;
+  const double rt = c->tau / P.G.dt;
+  const float ftau = (float)std::min(8.0, std::max(-8.0, std::log10(rt)));
+  a.mode = c->cmode;
+  a.nhat = c->nhat;
+  a.dfl = c->cdfl;
+  a.kcount = c->kcount;
+  a.thr = c->clos_thr;
+  const bool all_kin = snap_x || !c->clos_on;  // snapshot, or clearing the marks
+  if (all_kin) {
+    a.tgt = snap_t;
+    Mark m2(c, 2);
+    hipLaunchKernelGGL(k_fill_u8, dim3(nblk(nc)), dim3(256), 0, c->stream, c->cmode, nc,
+                       (unsigned char)1);
+    if (snap_x)
+      hipLaunchKernelGGL(k_closure_features, dim3(nblk(nc)), dim3(256), 0, c->stream,
+                         (const double*)a.U_in, snap_x, P.G, ftau);
+  } else {
+    Mark m2(c, 2);
+    ClosureArgs ca;
+    ca.U = a.U_in;
+    ca.packed = c->clos_w;
+    ca.nhat = c->nhat;
+    ca.flagged = c->cflag;
+    ca.dfl = c->cdfl;
+    ca.y0 = c->clos_y0;
+    ca.ftau = ftau;
+    ca.lam = P.G.lam;
+    ca.sigma = c->clos_sigma;
+    ca.thr = c->clos_thr;
+    hipLaunchKernelGGL(k_closure_center, dim3(1), dim3(64), 0, c->stream, c->clos_w, c->clos_y0,
+                       ftau);
+    const unsigned tiles = (unsigned)((nc + 15) / 16);
+    const unsigned grid = std::min(2048u, (tiles + 3) / 4);
+    hipLaunchKernelGGL(k_closure_mlp, dim3(grid), dim3(256), 0, c->stream, ca, P.G);
+    const int h = P.G.nv1 / 2;
+    hipLaunchKernelGGL((k_dilate<0>), dim3(nblk(nc)), dim3(256), 0, c->stream,
+                       (const unsigned char*)c->cflag, c->ctmp, P.G, h);
+    hipLaunchKernelGGL((k_dilate<1>), dim3(nblk(nc)), dim3(256), 0, c->stream,
+                       (const unsigned char*)c->ctmp, c->cmode, P.G, h);
+  }
+  HIPCHK(c, hipGetLastError());
+  {
+    Mark m0(c, 0);
+    hipLaunchKernelGGL((k_euler<2, T>), dim3(P.GE), dim3(256), 0, c->stream, a, P.G);
+    HIPCHK(c, hipGetLastError());
+  }
+  const dim3 grid((unsigned)((long)P.nseg * P.nrowgrp));
+  Mark m(c, 1);
+  constexpr bool CP = sizeof(T) == 4;
+  const int ng = c->kng;
+  const bool u16 = P.G.nv1 % 16 == 0;
+  const size_t lds = kin_lds(P, ng);
+#define KC(BCX, NG, U)                                                                          \
+  hipLaunchKernelGGL((k_kinetic<2, T, false, CP, BCX, U, true, NG, true>), grid, dim3(64 * NG), \
+                     lds, c->stream, a, P.G, P.A)
+#define KCB(NG, U) \
+  if (P.G.bc[0] == 0) KC(0, NG, U); else KC(1, NG, U);
+  if (ng == 2) {
+    if (u16) { KCB(2, 16) } else { KCB(2, 1) }
+  } else {
+    if (u16) { KCB(4, 16) } else { KCB(4, 1) }
+  }
+#undef KCB
+#undef KC
+  HIPCHK(c, hipGetLastError());
+  if (!all_kin) c->clos_steps++;
+  c->clos_dirty = !all_kin;
   return HOFKS_OK;
 }
 
@@ -461,7 +575,7 @@ hofks_status refresh(hofks_ctx* c) {
   hofks_status st = zero_doubles(c, c->slots, 3 * (size_t)SET_D);
   if (st) return st;
   st = dispatch(c, [&](auto D, auto t) {
-    return launch_cell_init<decltype(D)::value, decltype(t)>(c, MODE_REFRESH);
+    return launch_cell_init<decltype(D)::value, decltype(t)>(c, MODE_RETAU);
   });
   if (st) return st;
   return plan_substeps(c);
@@ -473,6 +587,15 @@ hofks_status reset_counters(hofks_ctx* c) {
   c->steps = 0;
   hofks_status st = zero_ints(c, c->flag, 16);
   if (st) return st;
+  if (c->cdfl) {  // closure form: every cell marked kinetic for its first
+                  // step, no count, every cell keeps pieces
+    c->clos_dirty = false;
+    c->clos_steps = 0;
+    hipLaunchKernelGGL(k_fill_u8, dim3(nblk(c->P.G.nc)), dim3(256), 0, c->stream, c->cdfl,
+                       c->P.G.nc, (unsigned char)1);
+    st = zero_doubles(c, (double*)c->kcount, 1);
+    if (st) return st;
+  }
   return zero_doubles(c, c->slots, 3 * (size_t)SET_D);
 }
 
@@ -530,6 +653,19 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
   c->slots = (double*)(c->ws + P.off_slots);
   c->tiles = (int*)(c->ws + P.off_tiles);
   c->flag = (int*)(c->ws + P.off_flag);
+  if (P.d == 2) {
+    unsigned char* b = c->ws + P.off_clos;
+    const size_t nc = P.G.nc;
+    c->nhat = (float4*)b;
+    b += align256(nc * sizeof(float4));
+    c->cflag = b;
+    c->ctmp = b + nc;
+    c->cmode = b + 2 * nc;
+    c->cdfl = b + 3 * nc;
+    b += align256(4 * nc);
+    c->kcount = (unsigned long long*)b;
+    c->clos_y0 = (float*)(b + 16);
+  }
   c->tau = INFINITY;
   c->s_cap = 1;
   // kinetic configuration before any tuning: wider unroll in 2D/3D, two
@@ -689,7 +825,8 @@ hofks_status hofks_read_f(hofks_ctx* c, double* f, size_t bytes) {
       constexpr int DD = decltype(D)::value;
       using T = decltype(t);
       hipLaunchKernelGGL((k_materialize<DD, T>), dim3(nblk(nk * nc)), dim3(256), 0, c->stream,
-                         (const T*)c->g[c->cur], c->cf, stage, (int)k0, (int)nk, P.G);
+                         (const T*)c->g[c->cur], c->cf, stage, (int)k0, (int)nk, P.G,
+                         c->clos_dirty ? (const T*)c->rec[rpar(c)] : nullptr);
       HIPCHK(c, hipGetLastError());
       return HOFKS_OK;
     });
@@ -1428,6 +1565,118 @@ void batch_free(hofks_ctx* c) {
 }
 
 }  // namespace
+
+// ============================================================ closure ABI
+extern "C" {
+
+hofks_status hofks_closure_enable(hofks_ctx* c, const void* packed, double sigma,
+                                  double threshold) {
+  if (!c) return HOFKS_EINVAL;
+  if (c->batch || c->P.d != 2)
+    return fmt_err(c->err, "the closure form is defined for 2D-2V grids"), HOFKS_EINVAL;
+  if (c->desc.scheme != 0) return fmt_err(c->err, "the closure form needs the HOFKS scheme"), HOFKS_EINVAL;
+  if (!packed || ((uintptr_t)packed & 15))
+    return fmt_err(c->err, "network weights: 16-byte aligned device pointer expected"), HOFKS_EINVAL;
+  if (!std::isfinite(sigma) || std::isnan(threshold))
+    return fmt_err(c->err, "sigma must be finite and the threshold a number"), HOFKS_EINVAL;
+  c->clos_w = packed;
+  c->clos_sigma = sigma;
+  c->clos_thr = threshold;
+  c->clos_on = true;
+  return HOFKS_OK;
+}
+
+hofks_status hofks_closure_disable(hofks_ctx* c) {
+  if (!c) return HOFKS_EINVAL;
+  c->clos_on = false;
+  return HOFKS_OK;
+}
+
+hofks_status hofks_closure_snapshot(hofks_ctx* c, float* x, float* t) {
+  if (!c || !x || !t) return HOFKS_EINVAL;
+  if (c->batch || c->P.d != 2)
+    return fmt_err(c->err, "the closure form is defined for 2D-2V grids"), HOFKS_EINVAL;
+  if (!c->ready) return fmt_err(c->err, "set the state before stepping"), HOFKS_ESTATE;
+  if (c->desc.scheme != 0) return fmt_err(c->err, "the closure form needs the HOFKS scheme"), HOFKS_EINVAL;
+  if (!(c->P.G.lam >= 1e-12) || !(c->P.G.mu > 0.0))
+    return fmt_err(c->err, "training targets need 1e-12 <= lambda < 1 (finite tau, not too small)"),
+           HOFKS_EINVAL;
+  if (((uintptr_t)x & 3) || ((uintptr_t)t & 3)) return HOFKS_EINVAL;
+  hofks_status st = dispatch(c, [&](auto D, auto tt) -> hofks_status {
+    if constexpr (decltype(D)::value == 2) {
+      return launch_step<2, decltype(tt)>(c, x, t);
+    }
+    return HOFKS_EINVAL;
+  });
+  if (st) return st;
+  c->cur ^= 1;
+  c->steps++;
+  return HOFKS_OK;
+}
+
+hofks_status hofks_closure_stats(hofks_ctx* c, long* closure_steps,
+                                 unsigned long long* kinetic_cell_steps) {
+  if (!c) return HOFKS_EINVAL;
+  unsigned long long k = 0;
+  if (c->kcount) {
+    HIPCHK(c, hipMemcpyAsync(&k, c->kcount, sizeof(k), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  if (closure_steps) *closure_steps = c->clos_steps;
+  if (kinetic_cell_steps) *kinetic_cell_steps = k;
+  return HOFKS_OK;
+}
+
+int hofks_mlp_nparam(void) { return mlp::NPARAM; }
+
+size_t hofks_mlp_packed_bytes(void) { return mlp::PACKED_BYTES; }
+
+hofks_status hofks_mlp_pack(const float* params, void* packed, void* stream) {
+  if (!params || !packed || ((uintptr_t)packed & 15)) return HOFKS_EINVAL;
+  const int n = mlp::NFRAG * 64 * 4 + mlp::NBIAS;
+  hipLaunchKernelGGL(mlp::k_mlp_pack, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, params,
+                     packed);
+  return hipGetLastError() == hipSuccess ? HOFKS_OK : HOFKS_EDEVICE;
+}
+
+hofks_status hofks_mlp_forward(const void* packed, const float* x, float* y, long n,
+                               void* stream) {
+  if (!packed || ((uintptr_t)packed & 15) || n < 0) return HOFKS_EINVAL;
+  if (n == 0) return HOFKS_OK;
+  if (!x || !y || ((uintptr_t)y & 15) || ((uintptr_t)x & 3)) return HOFKS_EINVAL;
+  const long tiles = (n + 15) / 16;
+  const unsigned grid = (unsigned)std::min<long>(2048, (tiles + 3) / 4);
+  hipLaunchKernelGGL(mlp::k_mlp_forward, dim3(grid), dim3(256), 0, (hipStream_t)stream, packed,
+                     x, y, n);
+  return hipGetLastError() == hipSuccess ? HOFKS_OK : HOFKS_EDEVICE;
+}
+
+hofks_status hofks_mlp_grad(const void* packed, const float* x, const float* t, const int* idx,
+                            long n, float* grad, float* loss, void* stream) {
+  if (!packed || ((uintptr_t)packed & 15) || !grad || !loss || n < 1 || !x || !t)
+    return HOFKS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(mlp::k_mlp_zero, dim3(nblk(mlp::NPARAM)), dim3(256), 0, s, grad, mlp::NPARAM);
+  hipLaunchKernelGGL(mlp::k_mlp_zero, dim3(1), dim3(64), 0, s, loss, 1);
+  const long tiles = (n + 15) / 16;
+  const unsigned grid =
+      (unsigned)std::min<long>(128, (tiles + mlp::GRAD_WAVES - 1) / mlp::GRAD_WAVES);
+  hipLaunchKernelGGL(mlp::k_mlp_grad, dim3(grid), dim3(64 * mlp::GRAD_WAVES), mlp::GRAD_LDS, s,
+                     packed, x, t, idx, n, grad, loss);
+  return hipGetLastError() == hipSuccess ? HOFKS_OK : HOFKS_EDEVICE;
+}
+
+hofks_status hofks_mlp_adam(float* params, const float* grad, float* m, float* v, float lr,
+                            float b1, float b2, float eps, int step, void* stream) {
+  if (!params || !grad || !m || !v || step < 1) return HOFKS_EINVAL;
+  const float c1 = (float)(1.0 - std::pow((double)b1, step));
+  const float c2 = (float)(1.0 - std::pow((double)b2, step));
+  hipLaunchKernelGGL(mlp::k_mlp_adam, dim3(nblk(mlp::NPARAM)), dim3(256), 0, (hipStream_t)stream,
+                     params, grad, m, v, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError() == hipSuccess ? HOFKS_OK : HOFKS_EDEVICE;
+}
+
+}  // extern "C"
 
 extern "C" void hofks_destroy(hofks_ctx* c) {
   if (!c) return;

@@ -58,7 +58,8 @@ struct Mat {
   double a[25];
 };
 
-enum { MODE_STEP = 0, MODE_INIT = 1, MODE_INIT_FROM_SUMS = 2, MODE_REFRESH = 3 };
+// MODE_RETAU: as MODE_REFRESH, keeping the mark of cells without pieces
+enum { MODE_STEP = 0, MODE_INIT = 1, MODE_INIT_FROM_SUMS = 2, MODE_REFRESH = 3, MODE_RETAU = 4 };
 
 // ------------------------------------------------------------------ helpers
 __device__ __forceinline__ int map_axis(int i, int N, int bc) {
@@ -311,7 +312,8 @@ __device__ __forceinline__ bool euler_cell(const double* __restrict__ in, int j,
 template <int D, typename T>
 __device__ __forceinline__ bool cell_record(const double* Un, const double* cfv, const Geom& G,
                                             const Mat& A, const VelNode* __restrict__ vt,
-                                            T* __restrict__ rec_j, double* speed) {
+                                            T* __restrict__ rec_j, double* speed,
+                                            bool valid = true) {
   constexpr int NM = D + 2;
   const double rho = Un[0];
   double u[3] = {0.0, 0.0, 0.0}, usq = 0.0;
@@ -381,7 +383,7 @@ __device__ __forceinline__ bool cell_record(const double* Un, const double* cfv,
   rv[0] = (T)lp;
 #pragma unroll
   for (int a = 0; a < D; ++a) rv[1 + a] = (T)u[a];
-  rv[D + 1] = (T)beta;
+  rv[D + 1] = (T)(valid ? beta : -beta);  // negative: pieces of this cell not kept
 #pragma unroll
   for (int r = 0; r < NM; ++r) {
     rv[NM + r] = (T)(need_eq ? G.w * (G.lam * cfv[r] + G.mu * cE[r]) : G.w * (G.lam * cfv[r]));
@@ -411,6 +413,13 @@ struct StepArgs {
   double* bmax;       // [2][GE][ASTR] per-block speed maxima of the Euler sub-steps
   int* flag;
   int nseg, GE, s_cap, unlimited;
+  // closure form only
+  const unsigned char* mode;  // 1: the cell runs the kinetic step, 0: closure
+  const float4* nhat;         // network estimate of the non-equilibrium term
+  unsigned char* dfl;         // lam max|delta| / s above thr (kinetic cells)
+  float* tgt;                 // optional: training targets N / (lam s) per cell
+  unsigned long long* kcount;  // kinetic cell-steps (accumulated)
+  double thr;
 };
 
 // Euler kernel: GE co-resident blocks advance U^n over dt with s sub-steps
@@ -532,6 +541,51 @@ __global__ __launch_bounds__(256) void k_euler(StepArgs<T> a, Geom G) {
   }
 }
 
+// Closure form, per cell after the moment sums: closure cells add the
+// network estimate N^ to U^{n+1}; kinetic cells report whether
+// lam max|delta| / s exceeds the threshold; a snapshot step stores the
+// training target N / (lam s) with N = w (sum f* - sum E), s from U^n.
+template <int D, typename T>
+__device__ __forceinline__ void closure_epilogue(const StepArgs<T>& a, const Geom& G, int dest,
+                                                 bool kin, const double* SK, const double* CK,
+                                                 const double* SE, const double* CE, bool comp,
+                                                 const double* delta, double* Un) {
+  static_assert(D == 2, "closure form is 2D-2V");
+  if (!kin) {
+    const float4 nh = a.nhat[dest];
+    Un[0] += nh.x;
+    Un[1] += nh.y;
+    Un[2] += nh.z;
+    Un[3] += nh.w;
+  }
+  if (a.tgt) {
+    const double rho = a.U_in[dest];
+    const double ux = a.U_in[(size_t)G.nc + dest] / rho, uy = a.U_in[2 * (size_t)G.nc + dest] / rho;
+    const double En = a.U_in[3 * (size_t)G.nc + dest];
+    const double th = (2.0 * En - rho * (ux * ux + uy * uy)) / (2.0 * rho);
+    const double c = sqrt(G.gam * th);
+    const double sc[4] = {rho, rho * c, rho * c, En};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double N = G.w * ((comp ? SK[r] + CK[r] : SK[r]) - (comp ? SE[r] + CE[r] : SE[r]));
+      a.tgt[(size_t)dest * 4 + r] = (float)(N / (G.lam * sc[r]));
+    }
+  }
+  unsigned char df = 0;
+  if (kin) {
+    const double rho = Un[0];
+    const double ux = Un[1] / rho, uy = Un[2] / rho;
+    const double th = (2.0 * Un[3] - rho * (ux * ux + uy * uy)) / (2.0 * rho);
+    const double c = sqrt(G.gam * th);
+    const double sc[4] = {rho, rho * c, rho * c, Un[3]};
+    double m = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) m = fmax(m, fabs(delta[r]) / sc[r]);
+    df = (unsigned char)!(G.lam * m <= a.thr);
+  }
+  a.dfl[dest] = df;
+}
+
 // wave-local LDS hand-off: LDS operations of one wavefront complete in order;
 // this keeps the compiler from moving them across and waits for them
 __device__ __forceinline__ void wave_lds_sync() {
@@ -550,7 +604,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // combined in LDS and the first wavefront forms delta, U^{n+1}, cf and the
 // next record of its 64 cells; the Euler kernel of the step has finished.
 // (NG, UNR) is chosen per grid by the autotuner.
-template <int D, typename T, bool FT, bool COMP, int BCX, int UNR, bool EUL, int NG>
+template <int D, typename T, bool FT, bool COMP, int BCX, int UNR, bool EUL, int NG,
+          bool CLOS = false>
 __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat A) {
   constexpr int NM = D + 2;
   constexpr int RS = rec_stride<D, T>();
@@ -576,6 +631,10 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
   const int xlo = x0 - lofs;
   const T lam = (T)G.lam, mu = (T)G.mu;
   const int nvr = G.nv / G.nv1;
+  // closure form: kinetic lanes, and whether any cell of the tile is kinetic
+  // (all wavefronts of the block hold the same 64 cells)
+  const bool kin = !CLOS || (active && a.mode[dest] != 0);
+  const bool tile_kin = !CLOS || __ballot(kin) != 0;
   // velocity rows of this wavefront (2D/3D) or k_x range (1D)
   const int vr0 = (D >= 2) ? grp * nvr / NG : 0;
   const int vr1 = (D >= 2) ? (grp + 1) * nvr / NG : 1;
@@ -633,7 +692,9 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
         const int ix = ix0 + u;
         const int kx = ix - G.kofs;
         const T* gp = a.g_in + (kbase + ix) * (size_t)G.nc;
-        if (HOFKS_NT)
+        if (CLOS && !tile_kin)
+          gv[u] = (T)0;
+        else if (HOFKS_NT)
           gv[u] = __builtin_nontemporal_load(gp + ubase + map_x<BCX>(xN, kx, Nx));
         else
           gv[u] = gp[ubase + map_x<BCX>(xN, kx, Nx)];
@@ -681,23 +742,28 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
             const T dz_ = vzT - rv[3];
             q += dz_ * dz_;
           }
-          const T M = fast_exp<T>(rv[0] - rv[D + 1] * q);
+          const T M = fast_exp<T>(rv[0] - (CLOS ? fabs(rv[D + 1]) : rv[D + 1]) * q);
           T pe = rv[2 * NM + 0] + rv[2 * NM + 1] * vxT;
           if (D >= 2) pe += rv[2 * NM + 2] * vyT;
           if (D >= 3) pe += rv[2 * NM + 3] * vzT;
           pe += rv[3 * NM - 1] * vhT;
           const T E = M + pe;
           fs = lam * g + (mu * M + pp);
+          // closure form: closure cells, and upstream cells without pieces,
+          // take the equilibrium
+          if (CLOS) fs = (kin && rv[D + 1] > (T)0) ? fs : E;
           const double Ed = (double)E;
           aE0 += Ed;
           aE1 += vx * Ed;
           aE2 += vn.v2 * Ed;
         }
         T* op = a.g_out + (kbase + ix) * (size_t)G.nc;
-        if (HOFKS_NT)
+        if (CLOS && !kin) {
+        } else if (HOFKS_NT) {
           __builtin_nontemporal_store(fs, op + dest);
-        else
+        } else {
           op[dest] = fs;
+        }
         const double fd = (double)fs;
         aK0 += fd;
         aK1 += vx * fd;
@@ -789,6 +855,7 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
     double Un[NM], cfv[NM];
 #pragma unroll
     for (int r = 0; r < NM; ++r) Un[r] = G.w * (COMP ? SK[r] + CK[r] : SK[r]) + delta[r];
+    if constexpr (CLOS) closure_epilogue<D>(a, G, dest, kin, SK, CK, SE, CE, COMP, delta, Un);
 #pragma unroll
     for (int r = 0; r < NM; ++r) {
       double acc = 0.0;
@@ -796,7 +863,7 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
       for (int s2 = 0; s2 < NM; ++s2) acc += A.a[r * NM + s2] * delta[s2];
       cfv[r] = acc;
     }
-    phys = cell_record<D, T>(Un, cfv, G, A, a.vt, a.rec_out + (size_t)dest * RS, speed);
+    phys = cell_record<D, T>(Un, cfv, G, A, a.vt, a.rec_out + (size_t)dest * RS, speed, kin);
 #pragma unroll
     for (int r = 0; r < NM; ++r) {
       a.U_out[(size_t)r * G.nc + dest] = Un[r];
@@ -804,6 +871,10 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
     }
   }
   if (active && need_eq && !phys) atomicOr(a.flag, FLAG_NONPHYS);
+  if (CLOS) {
+    const unsigned long long bk = __ballot(kin);
+    if (lane == 0 && grp == 0 && bk) atomicAdd(a.kcount, (unsigned long long)__popcll(bk));
+  }
   if (EUL) {
 #pragma unroll
     for (int d2 = 0; d2 < D; ++d2) {
@@ -834,7 +905,7 @@ __global__ __launch_bounds__(256) void k_cell_init(double* __restrict__ U, doubl
   double speed[3] = {0.0, 0.0, 0.0};
   if (act) {
     double Un[NM], cfv[NM];
-    if (mode == MODE_REFRESH) {
+    if (mode == MODE_REFRESH || mode == MODE_RETAU) {
 #pragma unroll
       for (int r = 0; r < NM; ++r) {
         Un[r] = U[(size_t)r * G.nc + j];
@@ -855,7 +926,8 @@ __global__ __launch_bounds__(256) void k_cell_init(double* __restrict__ U, doubl
         cfv[r] = acc;
       }
     }
-    phys = cell_record<D, T>(Un, cfv, G, A, vt, rec + (size_t)j * RS, speed);
+    const bool valid = mode != MODE_RETAU || !(rec[(size_t)j * RS + D + 1] < (T)0);
+    phys = cell_record<D, T>(Un, cfv, G, A, vt, rec + (size_t)j * RS, speed, valid);
 #pragma unroll
     for (int r = 0; r < NM; ++r) {
       U[(size_t)r * G.nc + j] = Un[r];
@@ -935,22 +1007,39 @@ __global__ void k_piece_sums(const T* __restrict__ g, double* __restrict__ part,
   for (int r = 0; r < NM; ++r) part[(size_t)r * G.nc + j] = S[r];
 }
 
-// out(j, k) = g(j,k) + w m_k . cf(j) for planes [k0, k0 + nk)
+// out(j, k) = g(j,k) + w m_k . cf(j) for planes [k0, k0 + nk); with `rec`
+// given, cells whose record marks their pieces as not kept (closure form)
+// give their equilibrium E(j, k) instead
 template <int D, typename T>
 __global__ void k_materialize(const T* __restrict__ g, const double* __restrict__ cf,
-                              double* __restrict__ out, int k0, int nk, Geom G) {
+                              double* __restrict__ out, int k0, int nk, Geom G,
+                              const T* __restrict__ rec = nullptr) {
   constexpr int NM = D + 2;
+  constexpr int RS = rec_stride<D, T>();
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)nk * G.nc) return;
   const int j = (int)(idx % G.nc);
   int k = k0 + (int)(idx / G.nc);
-  double corr = cf[j], vsq = 0.0;
+  const bool eq = rec && rec[(size_t)j * RS + D + 1] < (T)0;
+  double corr = eq ? (double)rec[(size_t)j * RS + 2 * NM] : cf[j], vsq = 0.0, q = 0.0;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     const double v = (k % G.nv1 - G.kofs) * G.dv;
     k /= G.nv1;
-    corr += v * cf[(size_t)(1 + a) * G.nc + j];
+    if (eq) {
+      corr += v * (double)rec[(size_t)j * RS + 2 * NM + 1 + a];
+      const double du = v - (double)rec[(size_t)j * RS + 1 + a];
+      q += du * du;
+    } else {
+      corr += v * cf[(size_t)(1 + a) * G.nc + j];
+    }
     vsq += v * v;
+  }
+  if (eq) {  // e = w cE is stored, so no factor w here
+    corr += 0.5 * vsq * (double)rec[(size_t)j * RS + 3 * NM - 1];
+    const double M = exp((double)rec[(size_t)j * RS] + (double)rec[(size_t)j * RS + D + 1] * q);
+    out[idx] = M + corr;
+    return;
   }
   corr += 0.5 * vsq * cf[(size_t)(NM - 1) * G.nc + j];
   out[idx] = (double)g[(size_t)(k0 + (int)(idx / G.nc)) * G.nc + j] + G.w * corr;

@@ -134,6 +134,36 @@ class Solver:
         self._check(_lib.lib().hofks_autotune(self._h, int(steps), cp, ch), "autotune")
         return int(ch[0]), int(ch[1])
 
+    # ------------------------------------------------ closure form (2D-2V)
+    def closure_enable(self, net, threshold=1e-3):
+        """run the following steps in the closure form with ``net`` (a
+        ``ClosureNet``; its packed weights must stay alive)"""
+        self._net = net
+        self._check(_lib.lib().hofks_closure_enable(
+            self._h, ctypes.c_void_p(net.packed.data_ptr()), float(net.sigma), float(threshold)),
+            "closure_enable")
+
+    def closure_disable(self):
+        self._check(_lib.lib().hofks_closure_disable(self._h), "closure_disable")
+        self._net = None
+
+    def closure_snapshot(self):
+        """one plain step; returns the network inputs of U^n and the targets
+        N / (lambda s) as FP32 device tensors (nc x 37, nc x 4)"""
+        x = torch.empty((self.nc, 37), dtype=torch.float32, device="cuda")
+        t = torch.empty((self.nc, 4), dtype=torch.float32, device="cuda")
+        self._check(_lib.lib().hofks_closure_snapshot(
+            self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr())),
+            "closure_snapshot")
+        return x, t
+
+    def closure_stats(self):
+        """(closure steps, kinetic cell-steps among them)"""
+        s, k = ctypes.c_long(0), ctypes.c_ulonglong(0)
+        self._check(_lib.lib().hofks_closure_stats(self._h, ctypes.byref(s), ctypes.byref(k)),
+                    "closure_stats")
+        return s.value, k.value
+
 
 class Batch(Solver):
     """Independent 1D-1V outflow tubes in FP32 pieces, advanced together (one

@@ -1,0 +1,370 @@
+"""Closure form on the GPU: the network kernels against the FP64 network of
+the oracle, the closure update against the FP64 closure reference, and the
+closure run against the plain kinetic run (accuracy, gain of the network).
+
+The network runs in BF16 with FP32 accumulation; the oracle is given the
+same BF16-representable weights, so the remaining differences are the BF16
+roundings of inputs and activations.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Oracle, mlp_adam, mlp_forward, mlp_loss_grad
+from oracle import closure_ref as C
+from tests.helpers import moment_errors
+
+gpu = pytest.mark.gpu
+
+
+def announce(*a):
+    print("CASE", *a, flush=True)
+
+
+def bf16(p):
+    """FP32 -> BF16 (round to nearest even) -> FP64"""
+    u = np.asarray(p, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def net_and_params(seed, sigma=1.0):
+    from paper_1212_0204_amd.mlp import ClosureNet, init_params
+    p = init_params(seed)
+    return ClosureNet(p, sigma=sigma), p
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+# ------------------------------------------------------------------ network
+@gpu
+@pytest.mark.parametrize("n", [1, 16, 1000])
+def test_mlp_forward_matches_oracle(n):
+    import torch
+    announce("mlp forward", n)
+    net, p = net_and_params(1)
+    x = np.random.default_rng(n).standard_normal((n, 37)).astype(np.float32)
+    y = net.forward(torch.tensor(x, device="cuda")).cpu().numpy()
+    yo = mlp_forward(bf16(p), x.astype(np.float64))
+    assert rel(y, yo) < 1e-2
+
+
+@gpu
+def test_mlp_gradient_matches_oracle():
+    import torch
+    announce("mlp gradient")
+    net, p = net_and_params(2)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((777, 37)).astype(np.float32)
+    t = rng.standard_normal((777, 4)).astype(np.float32)
+    xt, tt = torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda")
+    g, loss = net.gradient(xt, tt)
+    g = g.cpu().numpy().astype(np.float64)
+    lo, go = mlp_loss_grad(bf16(p), x.astype(np.float64), t.astype(np.float64))
+    cos = g @ go / (np.linalg.norm(g) * np.linalg.norm(go))
+    assert cos >= 0.999, cos
+    assert np.linalg.norm(g - go) / np.linalg.norm(go) <= 1e-2
+    assert abs(float(loss.item()) - lo) <= 1e-2 * lo
+    # a batch given by row indices
+    idx = rng.choice(777, 300, replace=False).astype(np.int32)
+    g2, _ = net.gradient(xt, tt, torch.tensor(idx, device="cuda"))
+    g2 = g2.cpu().numpy().astype(np.float64)
+    _, go2 = mlp_loss_grad(bf16(p), x[idx].astype(np.float64), t[idx].astype(np.float64))
+    assert np.linalg.norm(g2 - go2) / np.linalg.norm(go2) <= 1e-2
+
+
+@gpu
+def test_adam_matches_oracle():
+    import torch
+    announce("adam")
+    net, p = net_and_params(3)
+    rng = np.random.default_rng(9)
+    pm, m, v = p.astype(np.float64), np.zeros(p.size), np.zeros(p.size)
+    # the same FP32-representable hyperparameters on both sides
+    lr, b1, b2, eps = (float(np.float32(a)) for a in (1e-3, 0.9, 0.999, 1e-8))
+    for k in range(1, 4):
+        g = rng.standard_normal(p.size).astype(np.float32) * 1e-2
+        net.grad.copy_(torch.tensor(g, device="cuda"))
+        net.adam(lr, b1, b2, eps)
+        mlp_adam(pm, g.astype(np.float64), m, v, lr, k, b1, b2, eps)
+    assert rel(net.params.cpu().numpy().astype(np.float64), pm) < 1e-5
+    assert rel(net.v.cpu().numpy().astype(np.float64), v) < 1e-5
+
+
+@gpu
+def test_training_fits_a_smooth_map():
+    import torch
+    announce("training")
+    net, _ = net_and_params(4)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((8192, 37)).astype(np.float32)
+    A = rng.standard_normal((37, 4)) / np.sqrt(37)
+    t = np.tanh(x @ A).astype(np.float32)
+    xt, tt = torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda")
+    losses = net.train(xt, tt, steps=400, batch=1024, lr=3e-3, log_every=399)
+    assert losses[-1][1] < 0.1 * losses[0][1], losses
+
+
+# ------------------------------------------------------------ closure steps
+def small(prec, tau, n=24, nv=16, dv=0.5, seed=6):
+    from paper_1212_0204_amd import Solver
+    rho, u, th = W.perturbed_gas(n, 2, 0.2, 0.1, 3, (seed, seed + 1))
+    s = Solver(2, (n, n), 1.0 / n, nv, dv, bc=(0, 0), precision=prec, tau=tau)
+    s.set_state_macro(rho, u, th)
+    o = Oracle(2, (n, n), 1.0 / n, nv, dv, bc=(0, 0), tau=tau)
+    o.init_macro(rho, u, th)
+    return s, o
+
+
+@gpu
+@pytest.mark.parametrize("prec", [0, 1])
+def test_snapshot_inputs_and_targets(prec):
+    announce("snapshot", prec)
+    tau = 0.05
+    s, o = small(prec, tau)
+    ftau = math.log10(tau / o.dt)
+    x0, t0 = s.closure_snapshot()
+    assert rel(x0.cpu().numpy(), C.features(o.U, (24, 24), ftau)) < 1e-6
+    assert np.abs(t0.cpu().numpy()).max() < (1e-9 if prec == 0 else 1e-4)  # f^0 = E[U^0]
+    o.step(3)
+    s.step(2)
+    x, t = s.closure_snapshot()
+    tr = C.targets(o, o.f, o.U)
+    xr = C.features(o.U, (24, 24), ftau)
+    t, x = t.cpu().numpy(), x.cpu().numpy()
+    assert rel(x, xr) < (1e-6 if prec == 0 else 1e-5)  # inputs are stored in FP32
+    # targets are stored in FP32: that rounding is the FP64 bar
+    for r in range(4):
+        assert rel(t[:, r], tr[:, r]) < (1e-6 if prec == 0 else 2e-3), r
+
+
+@gpu
+@pytest.mark.parametrize("prec", [0, 1])
+def test_all_kinetic_closure_run_equals_plain_run(prec):
+    announce("all kinetic", prec)
+    tau = 0.02
+    s1, _ = small(prec, tau)
+    s2, _ = small(prec, tau)
+    net, _ = net_and_params(5)
+    s2.closure_enable(net, threshold=-1.0)
+    s1.step(5)
+    s2.step(5)
+    U1, U2 = s1.read_moments(), s2.read_moments()
+    assert moment_errors(U2, U1, 2).max() < (1e-13 if prec == 0 else 1e-6)
+    steps, kin = s2.closure_stats()
+    assert steps == 5 and kin == 5 * 24 * 24
+
+
+@gpu
+@pytest.mark.parametrize("prec", [0, 1])
+def test_zero_network_closure_matches_reference(prec):
+    """first step kinetic (every cell is marked after the state is set),
+    then every cell a closure cell with N^ = 0: U <- lam KFVS(E) + U_E"""
+    announce("zero network", prec)
+    tau = 0.02
+    s, o = small(prec, tau)
+    net, _ = net_and_params(5, sigma=0.0)
+    s.closure_enable(net, threshold=math.inf)
+    o.step(1)
+    U = o.U.copy()
+    for _ in range(3):
+        U = C.closure_step(o, U, tau)
+    s.step(4)
+    assert moment_errors(s.read_moments(), U, 2).max() < (1e-12 if prec == 0 else 1e-5)
+    assert s.closure_stats() == (4, 24 * 24)
+
+
+@gpu
+def test_network_closure_step_matches_reference():
+    announce("network closure step")
+    tau = 0.02
+    s, o = small(0, tau)
+    sigma = 0.05
+    net, p = net_and_params(7, sigma=sigma)
+    s.closure_enable(net, threshold=math.inf)
+    s.step(2)  # a kinetic step, then a closure step
+    o.step(1)
+    U0 = o.U.copy()
+    lam = math.exp(-o.dt / tau)
+    ftau = math.log10(tau / o.dt)
+    y = mlp_forward(bf16(p), C.features(U0, (24, 24), ftau))
+    y0 = mlp_forward(bf16(p), C.uniform_input(ftau))
+    nhat = lam * sigma * (y - y0).T * C.scales(U0)
+    Uref = C.closure_step(o, U0, tau, nhat)
+    # BF16 error bound: a fraction of the network output's own size
+    bound = 2e-2 * lam * sigma * (np.abs(y).max(axis=1) * C.scales(U0)).max(axis=1)
+    d = np.abs(s.read_moments() - Uref).max(axis=1)
+    assert (d <= bound + 1e-12).all(), (d, bound)
+
+
+def dilate(flag, h):
+    out = np.zeros_like(flag)
+    for d in range(-h, h + 1):
+        out |= np.roll(flag, d, axis=1)
+    res = np.zeros_like(flag)
+    for d in range(-h, h + 1):
+        res |= np.roll(out, d, axis=0)
+    return res
+
+
+@gpu
+def test_indicator_and_dilation_count():
+    """The first closure step after the state is set runs every cell
+    kinetic; the kinetic cells of the second are the cells whose network
+    indicator or delta mark exceeds the threshold, dilated by n_v/2 cells
+    along each axis (periodic).  Cells within 2% of the threshold may go
+    either way (BF16 against FP64), so the count is bracketed."""
+    announce("indicator")
+    n, nv, tau = 40, 8, 0.02
+    from paper_1212_0204_amd import Solver
+    rho, u, th = W.perturbed_gas(n, 2, 0.2, 0.1, 3, (8, 9))
+    s = Solver(2, (n, n), 1.0 / n, nv, 0.5, bc=(0, 0), precision=0, tau=tau)
+    s.set_state_macro(rho, u, th)
+    o = Oracle(2, (n, n), 1.0 / n, nv, 0.5, bc=(0, 0), tau=tau)
+    o.init_macro(rho, u, th)
+    o.step(1)
+    sigma = 0.05
+    net, p = net_and_params(11, sigma=sigma)
+    lam = math.exp(-o.dt / tau)
+    ftau = math.log10(tau / o.dt)
+    y = mlp_forward(bf16(p), C.features(o.U, (n, n), ftau))
+    y0 = mlp_forward(bf16(p), C.uniform_input(ftau))
+    r = lam * sigma * np.abs(y - y0).max(axis=1)
+    dm = lam * (np.abs(o.delta) / C.scales(o.U)).max(axis=0)
+    ind = np.maximum(r, dm)
+    thr = float(np.quantile(ind, 0.97))
+    lo = dilate((ind > 1.02 * thr).reshape(n, n), nv // 2).sum()
+    hi = dilate((ind > 0.98 * thr).reshape(n, n), nv // 2).sum()
+    assert 0 < lo and hi < n * n
+    s.closure_enable(net, threshold=thr)
+    s.step(1)
+    assert s.closure_stats() == (1, n * n)
+    s.step(1)
+    steps, kin = s.closure_stats()
+    assert steps == 2 and lo <= kin - n * n <= hi, (lo, kin - n * n, hi)
+
+
+@gpu
+def test_tau_change_and_disable_after_closure_steps():
+    announce("tau change / disable")
+    tau = 0.02
+    s, o = small(1, tau)
+    tot0 = o.U.sum(axis=1)
+    net, _ = net_and_params(5, sigma=0.0)
+    s.closure_enable(net, threshold=math.inf)
+    s.step(2)
+    s.set_tau(0.03)  # keeps the marks of the closure cells
+    s.step(1)
+    s.closure_disable()
+    s.step(2)  # the first of these rebuilds the pieces from E
+    U = s.read_moments()
+    f = s.read_f()
+    assert np.isfinite(f).all()
+    assert abs(U[0].sum() - tot0[0]) < 1e-5 * abs(tot0[0])
+    assert abs(U[3].sum() - tot0[3]) < 1e-5 * abs(tot0[3])
+
+
+@gpu
+def test_free_transport_refused_after_closure_steps():
+    from paper_1212_0204_amd import HofksError
+    announce("free transport after closure")
+    s, _ = small(1, 0.02)
+    net, _ = net_and_params(5, sigma=0.0)
+    s.closure_enable(net, threshold=math.inf)
+    s.step(1)
+    s.closure_disable()
+    s.set_tau(math.inf)
+    with pytest.raises(HofksError):
+        s.step(1)
+
+
+# ------------------------------------------- trained network: accuracy/gain
+@pytest.fixture(scope="module")
+def trained():
+    from paper_1212_0204_amd.mlp import ClosureNet, collect_snapshots
+    announce("collect + train")
+    x, t = collect_snapshots(W.closure_runs(seed=21, count=9), steps_at=[1, 3, 6, 10, 16, 24])
+    net = ClosureNet(seed=0)
+    scale, losses, used = net.fit_closure(x, t, steps=4000, log_every=3999)
+    print("training loss", losses, "scales", scale, "samples", used, "of", x.shape[0], flush=True)
+    return net
+
+
+def disk_run(n, length, tau, steps, net=None, thr=1e-3, centre=None, radius=None):
+    from paper_1212_0204_amd import Solver
+    c = centre or (0.5 * length, 0.5 * length)
+    rad = radius or 0.1 * length
+    s = Solver(2, (n, n), length / n, 32, 0.5, bc=(0, 0), precision=1, tau=tau)
+    s.set_state_macro(*W.disk_2d(n, length, c, rad))
+    if net is not None:
+        s.closure_enable(net, threshold=thr)
+    s.step(steps)
+    U = s.read_moments()
+    stats = s.closure_stats()
+    return U, stats
+
+
+def l1(a, b):
+    return np.abs(a - b).sum() / np.abs(b).sum()
+
+
+def gas_run(n, tau, steps, net=None, thr=1e-3, seeds=(77, 78)):
+    from paper_1212_0204_amd import Solver
+    s = Solver(2, (n, n), 1.0 / 256, 32, 0.5, bc=(0, 0), precision=1, tau=tau)
+    s.set_state_macro(*W.perturbed_gas(n, 2, 0.2, 0.1, 4, seeds))
+    if net is not None:
+        s.closure_enable(net, threshold=thr)
+    s.step(steps)
+    return s.read_moments(), s.closure_stats()
+
+
+@gpu
+@pytest.mark.parametrize("tau", [5e-3, 2e-3])
+def test_network_beats_zero_closure(trained, tau):
+    """smooth flow (a perturbed gas not in the training set), every cell a
+    closure cell after the first step: the trained N^ gives a smaller L1
+    density error against the plain kinetic run than N^ = 0"""
+    from paper_1212_0204_amd.mlp import ClosureNet
+    announce("gain", tau)
+    n, steps = 128, 20
+    Up, _ = gas_run(n, tau, steps)
+    Ut, _ = gas_run(n, tau, steps, trained, thr=math.inf)
+    zero = ClosureNet(sigma=0.0)
+    Uz, _ = gas_run(n, tau, steps, zero, thr=math.inf)
+    et, ez = l1(Ut[0], Up[0]), l1(Uz[0], Up[0])
+    print("L1 trained", et, "zero", ez, flush=True)
+    # training is not bit-reproducible (atomic gradient sums); observed
+    # ratios 0.68 - 0.83
+    assert et < 0.9 * ez
+
+
+@gpu
+@pytest.mark.parametrize("tau", [1e-2, 1e-3, 1e-4, 1e-5])
+def test_adaptive_closure_accuracy(trained, tau):
+    """the adaptive closure (threshold 1e-3) stays within 1e-3 L1 density
+    error of the plain kinetic run on the disk problem"""
+    announce("adaptive", tau)
+    n, length, steps = 128, 0.5, 30
+    Up, _ = disk_run(n, length, tau, steps)
+    Uc, (cs, kin) = disk_run(n, length, tau, steps, trained)
+    e = l1(Uc[0], Up[0])
+    print("tau", tau, "L1", e, "kinetic fraction", kin / (cs * n * n), flush=True)
+    assert e <= 1e-3
+
+
+@gpu
+def test_full_size_disk_closure(trained):
+    """512^2 disk, tau = 1e-4, 100 steps: closure vs plain kinetic run"""
+    announce("full disk")
+    wl = W.DISK_2D
+    Up, _ = disk_run(wl.n[0], wl.length, wl.tau, wl.steps, centre=(1.0, 1.0), radius=0.2)
+    Uc, (cs, kin) = disk_run(wl.n[0], wl.length, wl.tau, wl.steps, trained,
+                             centre=(1.0, 1.0), radius=0.2)
+    e = l1(Uc[0], Up[0])
+    print("L1", e, "kinetic fraction", kin / (cs * wl.nc), flush=True)
+    assert e <= 1e-3
+    assert np.isfinite(Uc).all()

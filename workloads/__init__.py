@@ -112,6 +112,75 @@ def disk_2d(n, length=2.0, centre=(1.0, 1.0), radius=0.2,
     return rho, np.zeros((2, n * n)), p / rho
 
 
+def planar_2d(n, length, angle, offset, left, right):
+    """Planar Riemann data across the line through the domain centre shifted
+    by `offset` along the normal (cos a, sin a); (rho, p) left/right, u = 0.
+    The domain is periodic, so the data also jumps at the edges."""
+    x = cell_centres(n, length)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    s = (X - 0.5 * length) * np.cos(angle) + (Y - 0.5 * length) * np.sin(angle) - offset
+    lhs = (s < 0.0).reshape(-1)
+    rho = np.where(lhs, left[0], right[0]).astype(np.float64)
+    p = np.where(lhs, left[1], right[1]).astype(np.float64)
+    return rho, np.zeros((2, n * n)), p / rho
+
+
+@dataclass(frozen=True)
+class ClosureRun:
+    """One 2D-2V run that feeds the closure network (periodic square)."""
+    kind: str            # "gas", "disk" or "planar"
+    n: int
+    length: float
+    nv: int
+    dv: float
+    tau: float
+    inside: tuple        # disk/planar: (rho, p) inside / left; gas: (rho_amp, theta_amp)
+    outside: tuple
+    geom: tuple          # disk: (cx, cy, r); planar: (angle, offset); gas: (modes, seed)
+
+    def fields(self):
+        if self.kind == "gas":
+            modes, seed = self.geom
+            return perturbed_gas(self.n, 2, self.inside[0], self.inside[1], modes,
+                                 (seed, seed + 1))
+        if self.kind == "disk":
+            cx, cy, r = self.geom
+            return disk_2d(self.n, self.length, (cx, cy), r, self.inside, self.outside)
+        return planar_2d(self.n, self.length, self.geom[0], self.geom[1], self.inside,
+                         self.outside)
+
+
+def closure_runs(seed, count, n=128, dx=1.0 / 256, nv=32, dv=0.5, tau_range=(3e-4, 1e-2)):
+    """Runs with the spacing of the 512^2 disk (dx = 1/256) and tau
+    log-uniform: index i % 3 == 0 a smooth perturbed gas (density and
+    temperature amplitudes U(0.05, 0.3), Fourier modes up to 2..6), 1 a disk
+    and 2 a planar front at a random angle with rho ~ U(0.1, 1) and
+    theta ~ U(0.6, 1.2) on each side (the velocity grid, |v| <= 8, spans six
+    thermal widths)."""
+    rng = np.random.default_rng(seed)
+    length = n * dx
+    out = []
+    for i in range(count):
+        tau = float(10.0 ** rng.uniform(np.log10(tau_range[0]), np.log10(tau_range[1])))
+        if i % 3 == 0:
+            amp = (float(rng.uniform(0.05, 0.3)), float(rng.uniform(0.05, 0.3)))
+            geom = (int(rng.integers(2, 7)), int(rng.integers(1000, 100000)))
+            out.append(ClosureRun("gas", n, length, nv, dv, tau, amp, (), geom))
+            continue
+        rl, rr = rng.uniform(0.1, 1.0, 2)
+        pl, pr = rl * rng.uniform(0.6, 1.2), rr * rng.uniform(0.6, 1.2)
+        if i % 3 == 1:
+            geom = (float(rng.uniform(0.35, 0.65) * length), float(rng.uniform(0.35, 0.65) * length),
+                    float(rng.uniform(0.1, 0.3) * length))
+            kind = "disk"
+        else:
+            geom = (float(rng.uniform(0.0, np.pi)), float(rng.uniform(-0.1, 0.1) * length))
+            kind = "planar"
+        out.append(ClosureRun(kind, n, length, nv, dv, tau, (float(rl), float(pl)),
+                              (float(rr), float(pr)), geom))
+    return out
+
+
 # -------------------------------------------------------- batched shock tubes
 @dataclass(frozen=True)
 class Tube:

@@ -36,7 +36,7 @@ struct Plan {
   Mat A;
   int prec;
   size_t tsize;  // bytes per stored piece
-  int TX, TR, nseg, nrowgrp, nchunk, nvr, GE;
+  int TX, TR, nseg, nrowgrp, nchunk, nvr, GE, ETPB;
   size_t lds;
   int RS;  // record stride (values)
   // workspace offsets (bytes)
@@ -45,6 +45,10 @@ struct Plan {
   size_t off_clos;  // closure form (2D): N^, indicator, dilation, mode, delta marks, count
   size_t total;
 };
+
+#ifndef HOFKS_EULER_TPB_MAX
+#define HOFKS_EULER_TPB_MAX 256
+#endif
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -181,7 +185,16 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       ncu < 1)
     ncu = 256;
-  P->GE = (int)std::min<long>(std::min(256, ncu), ((long)G.nc + 255) / 256);
+  // threads per Euler block: up to one cell per thread when the grid is
+  // large enough to fill every compute unit with wider blocks
+  const int ge = std::min(256, ncu);
+  P->ETPB = 256;
+  for (int tpb = HOFKS_EULER_TPB_MAX; tpb > 256; tpb /= 2)
+    if ((long)G.nc >= (long)ge * tpb) {
+      P->ETPB = tpb;
+      break;
+    }
+  P->GE = (int)std::min<long>(ge, ((long)G.nc + P->ETPB - 1) / P->ETPB);
 
   size_t off = 0;
   const size_t gbytes = (size_t)G.nv * G.nc * P->tsize;
@@ -240,6 +253,7 @@ struct hofks_ctx {
   int* flag;
   double tau;
   int s_cap;
+  int s_known;  // Euler sub-steps of the last step seen by the host
   long steps;
   bool ready;
   int kng, kunr;  // kinetic kernel: wavefronts per block, loads issued ahead
@@ -357,6 +371,8 @@ void dispatch_kin(hofks_ctx* c, const StepArgs<T>& a, dim3 grid) {
     if (unr == 8) { KB(4, 8) } else { KB(4, 1) }
   } else if (ng == 2) {
     if (unr == 16) { KB(2, 16) } else if (unr == 8) { KB(2, 8) } else { KB(2, 1) }
+  } else if (ng == 8 && D >= 2) {
+    if (unr == 16) { KB(8, 16) } else if (unr == 8) { KB(8, 8) } else { KB(8, 1) }
   } else {
     if (unr == 16) { KB(4, 16) } else if (unr == 8) { KB(4, 8) } else { KB(4, 1) }
   }
@@ -366,6 +382,25 @@ void dispatch_kin(hofks_ctx* c, const StepArgs<T>& a, dim3 grid) {
 
 template <typename T>
 hofks_status launch_closure_step(hofks_ctx* c, StepArgs<T>& a, float* snap_x, float* snap_t);
+
+// Euler solve of a step: one launch per sub-step for the first K = (last
+// known count + 1) sub-steps (the kernel boundary is the grid-wide barrier),
+// then a persistent tail that runs any further sub-steps with an in-kernel
+// barrier (it returns at once when K >= s)
+template <int D, typename T>
+void launch_euler(hofks_ctx* c, const StepArgs<T>& a) {
+  const Plan& P = c->P;
+  const int K = std::max(1, std::min(c->s_cap, c->s_known + 1));
+  for (int i = 0; i < K; ++i)
+    hipLaunchKernelGGL((k_euler_sub<D, T>), dim3(nblk(P.G.nc)), dim3(256), 0, c->stream, a, P.G,
+                       i);
+  if (P.ETPB == 1024)
+    hipLaunchKernelGGL((k_euler<D, T, 1024>), dim3(P.GE), dim3(1024), 0, c->stream, a, P.G, K);
+  else if (P.ETPB == 512)
+    hipLaunchKernelGGL((k_euler<D, T, 512>), dim3(P.GE), dim3(512), 0, c->stream, a, P.G, K);
+  else
+    hipLaunchKernelGGL((k_euler<D, T, 256>), dim3(P.GE), dim3(256), 0, c->stream, a, P.G, K);
+}
 
 template <int D, typename T>
 hofks_status launch_step(hofks_ctx* c, float* snap_x = nullptr, float* snap_t = nullptr) {
@@ -410,7 +445,7 @@ hofks_status launch_step(hofks_ctx* c, float* snap_x = nullptr, float* snap_t = 
   }
   if (eul) {
     Mark m0(c, 0);
-    hipLaunchKernelGGL((k_euler<D, T>), dim3(P.GE), dim3(256), 0, c->stream, a, P.G);
+    launch_euler<D, T>(c, a);
     HIPCHK(c, hipGetLastError());
   }
   const dim3 grid((unsigned)((long)P.nseg * P.nrowgrp));
@@ -475,7 +510,7 @@ hofks_status launch_closure_step(hofks_ctx* c, StepArgs<T>& a, float* snap_x, fl
   HIPCHK(c, hipGetLastError());
   {
     Mark m0(c, 0);
-    hipLaunchKernelGGL((k_euler<2, T>), dim3(P.GE), dim3(256), 0, c->stream, a, P.G);
+    launch_euler<2, T>(c, a);
     HIPCHK(c, hipGetLastError());
   }
   const dim3 grid((unsigned)((long)P.nseg * P.nrowgrp));
@@ -491,6 +526,8 @@ hofks_status launch_closure_step(hofks_ctx* c, StepArgs<T>& a, float* snap_x, fl
   if (P.G.bc[0] == 0) KC(0, NG, U); else KC(1, NG, U);
   if (ng == 2) {
     if (u16) { KCB(2, 16) } else { KCB(2, 1) }
+  } else if (ng == 8) {
+    if (u16) { KCB(8, 16) } else { KCB(8, 1) }
   } else {
     if (u16) { KCB(4, 16) } else { KCB(4, 1) }
   }
@@ -542,6 +579,7 @@ hofks_status read_flag(hofks_ctx* c) {
   int h[2] = {0, 0};
   HIPCHK(c, hipMemcpyAsync(h, c->flag, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (h[1] > 0) c->s_known = h[1];
   if (h[0] & FLAG_SPIN) {
     fmt_err(c->err, "a bounded wait of the step kernel gave up; results are invalid");
     return HOFKS_EDEVICE;
@@ -567,6 +605,7 @@ hofks_status plan_substeps(hofks_ctx* c) {
   const double sv = std::ceil(2.0 * c->P.G.dt * sum / c->P.G.dx);
   const int s0 = (sv >= 1.0 && sv < SMAX) ? (int)sv : (sv >= SMAX ? SMAX : 1);
   c->s_cap = std::min(SMAX, std::max(2 * s0, s0 + 8));
+  c->s_known = s0;
   return HOFKS_OK;
 }
 
@@ -668,6 +707,7 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
   }
   c->tau = INFINITY;
   c->s_cap = 1;
+  c->s_known = 1;
   // kinetic configuration before any tuning: wider unroll in 2D/3D, two
   // wavefronts per block for the FP64 2D grid
   c->kng = (P.d == 2 && !P.prec) ? 2 : 4;
@@ -1290,7 +1330,7 @@ hofks_status grid_autotune(hofks_ctx* c, int steps, const char* cache_path, int*
       const size_t pn = line.find("\"ng\": "), pu = line.find("\"unr\": ");
       if (pn == std::string::npos || pu == std::string::npos) continue;
       const int ng = std::atoi(line.c_str() + pn + 6), unr = std::atoi(line.c_str() + pu + 7);
-      if ((ng == 2 || ng == 4) && (unr == 8 || unr == 16)) {
+      if ((ng == 2 || ng == 4 || (ng == 8 && P.d >= 2)) && (unr == 8 || unr == 16)) {
         best_ng = ng;
         best_unr = unr;
       }
@@ -1301,9 +1341,9 @@ hofks_status grid_autotune(hofks_ctx* c, int steps, const char* cache_path, int*
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    const int cand[4][2] = {{4, 8}, {2, 16}, {4, 16}, {2, 8}};
+    const int cand[6][2] = {{4, 8}, {2, 16}, {4, 16}, {2, 8}, {8, 16}, {8, 8}};
     for (const auto& cd : cand) {
-      if (kin_lds(P, cd[0]) > 65536) continue;
+      if (kin_lds(P, cd[0]) > 65536 || (cd[0] == 8 && P.d < 2)) continue;
       c->kng = cd[0];
       c->kunr = cd[1];
       hofks_status st = hofks_step(c, 1);

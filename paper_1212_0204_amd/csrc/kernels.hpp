@@ -29,6 +29,9 @@
 #include <stdint.h>
 
 // stream the pieces with non-temporal loads and stores
+#ifndef HOFKS_EULER_NT
+#define HOFKS_EULER_NT 0
+#endif
 #ifndef HOFKS_NT
 #define HOFKS_NT 1
 #endif
@@ -37,10 +40,14 @@ namespace hofks {
 
 constexpr int SMAX = 512;         // largest Euler sub-step count a plan may use
 constexpr int ASTR = 4;           // doubles per row of Lax-Friedrichs speeds
-// doubles per slot set: speed rows, then control words (barrier counters,
-// each on its own 64-byte line)
+// doubles per slot set: row 0 (speeds of U^n), rows 1..SMAX of sub-step
+// speeds with NSLOT partial maxima each (slot = block index mod NSLOT, one
+// 32-byte group per slot, so the atomics of one row spread over lines),
+// then control words (barrier counters, each on its own 64-byte line)
+constexpr int NSLOT = 8;
 constexpr int CTRL_LINES = 10;
-constexpr int SET_D = (SMAX + 1) * ASTR + CTRL_LINES * 8;
+constexpr int SET_CTRL = ASTR + SMAX * NSLOT * ASTR;
+constexpr int SET_D = SET_CTRL + CTRL_LINES * 8;
 constexpr int FLAG_NONPHYS = 1;
 constexpr int FLAG_SUBSTEP = 2;
 constexpr int FLAG_SPIN = 4;      // a bounded wait gave up: results are invalid
@@ -109,6 +116,26 @@ __device__ __forceinline__ int substeps(const double* alpha0, const Geom& G, int
   int s = (sv >= 1.0) ? (sv <= (double)s_cap ? (int)sv : s_cap + 1) : 1;
   *over = (s > s_cap);
   return s > s_cap ? s_cap : s;
+}
+
+// slot `slot` of speed row r of a set (row 0 has one slot)
+__device__ __forceinline__ double* speed_row(double* S, int r, int slot) {
+  return r == 0 ? S : S + ASTR + ((size_t)(r - 1) * NSLOT + slot) * ASTR;
+}
+
+// speeds of row r: the maximum over its slots
+template <int D>
+__device__ __forceinline__ void row_speeds(const double* S, int r, double* alpha) {
+#pragma unroll
+  for (int d = 0; d < D; ++d) alpha[d] = S[d];
+  if (r == 0) return;
+  const double* p = S + ASTR + (size_t)(r - 1) * NSLOT * ASTR;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    double m = p[d];
+    for (int q = 1; q < NSLOT; ++q) m = fmax(m, p[q * ASTR + d]);
+    alpha[d] = m;
+  }
 }
 
 __device__ __forceinline__ void two_sum(double& s, double& c, double x) {
@@ -422,31 +449,81 @@ struct StepArgs {
   double thr;
 };
 
-// Euler kernel: GE co-resident blocks advance U^n over dt with s sub-steps
-// (grid-strided over cells); the speeds of sub-step i+1 are reduced with
-// atomics into row i+1 of set_r and the blocks meet at a barrier between
-// sub-steps.  The result is UE[s % 2].
+// Euler sub-step i (eq. (discmom) with the flux of section 4.3), one cell per
+// thread over the whole grid: sub-step 0 also clears the set of the step
+// after next and records s; launches with i >= s return at once.  The
+// speeds of the result are reduced per block and folded into row i+1 with
+// one atomic maximum per block on slot (block mod NSLOT).  Sub-step i reads
+// UE[i % 2] (U^n for i = 0) and writes UE[(i + 1) % 2].
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_euler(StepArgs<T> a, Geom G) {
+__global__ __launch_bounds__(256) void k_euler_sub(StepArgs<T> a, Geom G, int i) {
   constexpr int NM = D + 2;
   double* S = a.set_r;
-  unsigned* ctrl = reinterpret_cast<unsigned*>(S + (SMAX + 1) * ASTR);
   bool over;
   const int s = substeps<D>(S, G, a.s_cap, &over);
-  if (blockIdx.x == 0) {
-    for (int q = threadIdx.x; q < SET_D; q += blockDim.x) a.set_z[q] = 0.0;
-    if (threadIdx.x == 0) {
+  if (i == 0) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < SET_D; q += gridDim.x * blockDim.x)
+      a.set_z[q] = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
       if (over) atomicOr(a.flag, FLAG_SUBSTEP);
       a.flag[1] = s;
     }
   }
-  const double dts_dx = (G.dt / s) / G.dx;
-  __shared__ double wmax[4][ASTR];
+  if (i >= s) return;
   double alpha[3];
+  row_speeds<D>(S, i, alpha);
+  const double dts_dx = (G.dt / s) / G.dx;
+  const double* in = (i == 0) ? a.U_in : ((i & 1) ? a.UE1 : a.UE0);
+  double* out = ((i + 1) & 1) ? a.UE1 : a.UE0;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  bool phys = true;
+  double mx[3] = {0.0, 0.0, 0.0};
+  if (j < G.nc) {
+    double Un[NM];
+    phys = euler_cell<D>(in, j, alpha, dts_dx, G, a.unlimited, Un);
 #pragma unroll
-  for (int d2 = 0; d2 < D; ++d2)
-    alpha[d2] = __hip_atomic_load(S + d2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (int i = 0; i < s; ++i) {
+    for (int r = 0; r < NM; ++r) out[(size_t)r * G.nc + j] = Un[r];
+    if (i + 1 < s) {
+      double sp[3];
+      phys &= lf_speeds<D>(Un, G.gam, sp);
+#pragma unroll
+      for (int d2 = 0; d2 < D; ++d2) mx[d2] = sp[d2];
+    }
+  }
+  if (!phys) atomicOr(a.flag, FLAG_NONPHYS);
+  if (i + 1 < s) {
+    __shared__ double wm[4][ASTR];
+#pragma unroll
+    for (int d2 = 0; d2 < D; ++d2) {
+      const double m = wave_max(mx[d2]);
+      if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6][d2] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x < D) {
+      double m = wm[0][threadIdx.x];
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, wm[w][threadIdx.x]);
+      atomic_max_pos(speed_row(S, i + 1, blockIdx.x % NSLOT) + threadIdx.x, m);
+    }
+  }
+}
+
+// Euler tail: GE co-resident blocks continue from sub-step K to s when the
+// sub-step launches of the step stopped short (grid-strided over cells);
+// the speeds of sub-step i+1 are reduced through per-block maxima into slot
+// 0 of row i+1 and the blocks meet at a barrier between sub-steps.
+template <int D, typename T, int TPB>
+__global__ __launch_bounds__(TPB) void k_euler(StepArgs<T> a, Geom G, int K) {
+  constexpr int NM = D + 2;
+  double* S = a.set_r;
+  unsigned* ctrl = reinterpret_cast<unsigned*>(S + SET_CTRL);
+  bool over;
+  const int s = substeps<D>(S, G, a.s_cap, &over);
+  if (K >= s) return;  // the sub-step launches covered every sub-step
+  const double dts_dx = (G.dt / s) / G.dx;
+  __shared__ double wmax[TPB / 64][ASTR];
+  double alpha[3];
+  row_speeds<D>(S, K, alpha);
+  for (int i = K; i < s; ++i) {
     const double* in = (i == 0) ? a.U_in : ((i & 1) ? a.UE1 : a.UE0);
     double* out = ((i + 1) & 1) ? a.UE1 : a.UE0;
     bool phys = true;
@@ -455,7 +532,12 @@ __global__ __launch_bounds__(256) void k_euler(StepArgs<T> a, Geom G) {
       double Un[NM];
       phys &= euler_cell<D>(in, j, alpha, dts_dx, G, a.unlimited, Un);
 #pragma unroll
-      for (int r = 0; r < NM; ++r) out[(size_t)r * G.nc + j] = Un[r];
+      for (int r = 0; r < NM; ++r) {
+        if (HOFKS_EULER_NT)
+          __builtin_nontemporal_store(Un[r], out + (size_t)r * G.nc + j);
+        else
+          out[(size_t)r * G.nc + j] = Un[r];
+      }
       if (i + 1 < s) {
         double sp[3];
         phys &= lf_speeds<D>(Un, G.gam, sp);
@@ -492,10 +574,11 @@ __global__ __launch_bounds__(256) void k_euler(StepArgs<T> a, Geom G) {
         unsigned* sub = ctrl + 32 + 16 * g;      // lines 2..9: group counters
         __threadfence();
         int last = 0;
+        const unsigned nb = (unsigned)(i - K + 1);  // barriers of this launch so far
         const unsigned old = atomicAdd(sub, 1u);
-        if (old == (unsigned)(i + 1) * ng - 1) {
+        if (old == nb * ng - 1) {
           const unsigned t = atomicAdd(top, 1u);
-          last = (t == (unsigned)(i + 1) * ngroups - 1);
+          last = (t == nb * ngroups - 1);
         }
         s_last = last;
       }
@@ -519,18 +602,19 @@ __global__ __launch_bounds__(256) void k_euler(StepArgs<T> a, Geom G) {
           for (int d2 = 0; d2 < D; ++d2) {
             double w = wmax[0][d2];
             for (int q = 1; q < (int)(blockDim.x >> 6); ++q) w = fmax(w, wmax[q][d2]);
-            __hip_atomic_store(S + (i + 1) * ASTR + d2, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(speed_row(S, i + 1, 0) + d2, w, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
           }
           __threadfence();
-          __hip_atomic_store(gen, (unsigned)(i + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(gen, (unsigned)(i - K + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
       if (threadIdx.x == 0) {
-        spin_until_geq(gen, (unsigned)(i + 1), a.flag);
+        spin_until_geq(gen, (unsigned)(i - K + 1), a.flag);
         __threadfence();
 #pragma unroll
         for (int d2 = 0; d2 < D; ++d2)
-          wmax[0][d2] = __hip_atomic_load(S + (i + 1) * ASTR + d2, __ATOMIC_RELAXED,
+          wmax[0][d2] = __hip_atomic_load(speed_row(S, i + 1, 0) + d2, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
       }
       __syncthreads();

@@ -384,13 +384,13 @@ template <typename T>
 hofks_status launch_closure_step(hofks_ctx* c, StepArgs<T>& a, float* snap_x, float* snap_t);
 
 // Euler solve of a step: one launch per sub-step for the first K = (last
-// known count + 1) sub-steps (the kernel boundary is the grid-wide barrier),
+// known count + 2) sub-steps (the kernel boundary is the grid-wide barrier),
 // then a persistent tail that runs any further sub-steps with an in-kernel
 // barrier (it returns at once when K >= s)
 template <int D, typename T>
 void launch_euler(hofks_ctx* c, const StepArgs<T>& a) {
   const Plan& P = c->P;
-  const int K = std::max(1, std::min(c->s_cap, c->s_known + 1));
+  const int K = std::max(1, std::min(c->s_cap, c->s_known + 2));
   for (int i = 0; i < K; ++i)
     hipLaunchKernelGGL((k_euler_sub<D, T>), dim3(nblk(P.G.nc)), dim3(256), 0, c->stream, a, P.G,
                        i);

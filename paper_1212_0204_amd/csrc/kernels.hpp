@@ -118,6 +118,17 @@ __device__ __forceinline__ int substeps(const double* alpha0, const Geom& G, int
   return s > s_cap ? s_cap : s;
 }
 
+// Blocks are dispatched to the NXCD accelerator dies round-robin (block b
+// to die b mod NXCD), and each die has its own L2.  Tile index of block b
+// such that every die takes one contiguous range of tiles: neighbouring
+// rows, whose upstream records overlap, then share that die's L2.
+constexpr unsigned NXCD = 8;
+__device__ __forceinline__ int xcd_tile(unsigned b, unsigned nb) {
+  const unsigned x = b % NXCD, i = b / NXCD;
+  const unsigned per = nb / NXCD, rem = nb % NXCD;
+  return (int)(x * per + (x < rem ? x : rem) + i);
+}
+
 // slot `slot` of speed row r of a set (row 0 has one slot)
 __device__ __forceinline__ double* speed_row(double* S, int r, int slot) {
   return r == 0 ? S : S + ASTR + ((size_t)(r - 1) * NSLOT + slot) * ASTR;
@@ -701,8 +712,9 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
   T* lds = reinterpret_cast<T*>(lds_raw);
   const int SW = 64 + G.nv1 - 1;
 
-  const int seg = blockIdx.x % a.nseg;
-  const int row = blockIdx.x / a.nseg;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int seg = tile % a.nseg;
+  const int row = tile / a.nseg;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int Nx = G.n[0];
   const int x0 = seg * 64;

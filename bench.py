@@ -13,6 +13,7 @@ on the library's stream.  Extra forms (FP32 precision form, ...) are reported
 under ``forms``.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -26,6 +27,36 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "cell·velocity updates/s and % HBM peak, FP32/batched/MLP vs plain FP64"
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kinetic_gas2d_fp64_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1212_0204_amd", "csrc", "kernels.hpp")
+
+
+def kernel_source_hash():
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def profiled_traffic(ng, unr):
+    """HBM bytes per launch of the kinetic kernel in configuration (ng, unr)
+    from the committed rocprofv3 counter passes (FETCH_SIZE and WRITE_SIZE,
+    scaled by the copy kernel), or None when the kernel source has changed
+    since they were taken or the configuration was not profiled"""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals, rows = {}, {}
+    for line in open(TRAFFIC_FILE):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "config":
+            rows[(int(f[1]), int(f[2]))] = (float(f[3]), float(f[4]))
+        else:
+            vals[f[0]] = f[1]
+    if vals.get("source_hash") != kernel_source_hash() or (ng, unr) not in rows:
+        return None
+    fk, wk = rows[(ng, unr)]
+    return 1024.0 * (fk * float(vals["fetch_scale"]) + wk * float(vals["write_scale"]))
 
 
 def run_solver(wl, steps, warmup, precision, scheme=0):
@@ -290,7 +321,10 @@ def main():
         "config": {"workload": wl.name, "cells": list(wl.n), "velocities_per_axis": wl.nv,
                    "dv": wl.dv, "tau": wl.tau, "bc": "periodic", "hbm_step_frac": prim["step_hbm_frac"]},
         "roofline": {"bound": "hbm", "achieved": prim["kinetic_GBps"], "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": prim["kinetic_hbm_frac"], "traffic": None,
+                     "unit": "GB/s", "frac": prim["kinetic_hbm_frac"],
+                     "traffic": profiled_traffic(prim["tuned"]["wavefronts_per_block"],
+                                                 prim["tuned"]["loads_ahead"]),
+                     "traffic_unit": "bytes per launch",
                      "kernel": "k_kinetic<2,double>",
                      "algorithmic_bytes_per_launch": 16 * wl.cv},
         "kernel_ms_per_step": prim["kernel_ms_per_step"],

@@ -5,6 +5,7 @@ routine, a closed form, an invariant, an exact solution or a textbook value.
 Section numbers refer to arXiv:1212.0204.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -266,10 +267,16 @@ def test_tau_zero_sod_converges_to_exact_riemann():
 
 
 def test_exact_riemann_solver_textbook_sod():
-    """the exact solver itself: Sod's problem at gamma = 1.4 has the textbook
-    star state p* = 0.30313, u* = 0.92745 (5 digits)."""
-    ps, us = XR.star_state((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4)
-    assert abs(ps - 0.30313) < 5e-6 and abs(us - 0.92745) < 5e-6
+    """the exact solver itself: Sod's problem at gamma = 1.4 against the
+    textbook star state stored in tests/golden (5 digits)."""
+    vals = {}
+    path = os.path.join(os.path.dirname(__file__), "golden", "sod_star_state_gamma14.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, *v = line.split()
+            vals[k] = [float(x) for x in v]
+    ps, us = XR.star_state(tuple(vals["left"]), tuple(vals["right"]), vals["gamma"][0])
+    assert abs(ps - vals["p_star"][0]) < 5e-6 and abs(us - vals["u_star"][0]) < 5e-6
 
 
 def test_mirror_symmetry_odd_velocity_set():

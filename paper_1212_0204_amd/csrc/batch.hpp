@@ -1,10 +1,11 @@
 // batch.hpp -- batched persistent form: many independent 1D-1V tubes (each
 // with its own cells, velocity grid, dt and tau) advanced together.  A step is
-// two launches: the Euler launch runs every tube's s MUSCL sub-steps, one
-// 1024-thread block per tube (largest first); the kinetic launch is a
-// persistent grid pulling items from a queue, an item being a CELLS-cell
-// segment of one tube with all its velocities split over 1024/CELLS groups of
-// threads, ending with the per-cell update of the segment.
+// two launches: a persistent grid pulls from one queue first the Euler solves
+// of the tubes (one 1024-thread block per tube, s MUSCL sub-steps, largest
+// first) and then the kinetic items (a CELLS-cell segment of one tube with
+// all its velocities split over 1024/CELLS groups of threads, writing the
+// moment sums of its cells), so the two run side by side; the update launch
+// then forms U^{n+1} and the next records cell by cell.
 #pragma once
 #include "kernels.hpp"
 
@@ -16,6 +17,7 @@ struct TubeDev {
   long long U[2];    // moment offsets (doubles), 3 x Nx each
   long long UE[2];   // Euler sub-step buffers (doubles)
   long long cf;      // pending correction (doubles)
+  long long S;       // moment sums of f* and E per cell (doubles), 6 x Nx
   int vt;            // first velocity node of the tube in the node arena
   int Nx, nv1, kofs;
   double dx, dv, dt, w, lam, mu, gam;
@@ -61,7 +63,7 @@ __device__ __forceinline__ Geom tube_geom(const TubeDev& T) {
   return G;
 }
 
-// max over a 1024-thread block, result in every thread
+// max over the block (up to 1024 threads), result in every thread
 __device__ __forceinline__ double block_max_1024(double v, double* red) {
   v = wave_max(v);
   const int w = threadIdx.x >> 6;
@@ -73,7 +75,18 @@ __device__ __forceinline__ double block_max_1024(double v, double* red) {
   return m;
 }
 
-__device__ void batch_euler_item(const BatchArgs& a, int t, double* red) {
+// Euler solve of one tube by segments of EUL_TPB cells (eq. (discmom) with
+// the limited slopes of section 4.3.2): per sub-step and segment the block
+// evaluates the split fluxes W+- of the segment and two cells on each side
+// once into LDS, then the face fluxes psi of the segment's faces into LDS,
+// then the new cell values, written out of place to the other sub-step
+// buffer.  Every flux and every face is computed once (the global-memory
+// form evaluates five fluxes and two faces per cell).  Same arithmetic per
+// face as `euler_cell`; the result is UE[s % 2].
+constexpr int EUL_TPB = 1024;
+constexpr size_t EUL_LDS = (size_t)((EUL_TPB + 4) * 6 + (EUL_TPB + 1) * 3) * sizeof(double);
+
+__device__ void batch_euler_seg(const BatchArgs& a, int t, double* L, double* red) {
   t = __builtin_amdgcn_readfirstlane(t);
   const TubeDev T = a.tubes[t];
   const Geom G = tube_geom(T);
@@ -88,31 +101,65 @@ __device__ void batch_euler_item(const BatchArgs& a, int t, double* red) {
     a.tube_s[t] = s;
     if (over) atomicOr(a.tflag + t, FLAG_SUBSTEP);
   }
-  const bool need = G.mu != 0.0;
-  if (need) {
-    const double* U = a.dar + T.U[p];
-    double* UE0 = a.dar + T.UE[0];
-    double* UE1 = a.dar + T.UE[1];
-    const double dts_dx = (G.dt / s) / G.dx;
-    bool phys = true;
-    for (int i = 0; i < s; ++i) {
-      const double* in = (i == 0) ? U : ((i & 1) ? UE1 : UE0);
-      double* out = ((i + 1) & 1) ? UE1 : UE0;
-      double mx = 0.0;
-      for (int j = threadIdx.x; j < G.nc; j += blockDim.x) {
-        double Un[3];
-        phys &= euler_cell<1>(in, j, &alpha, dts_dx, G, 0, Un);
-        out[j] = Un[0];
-        out[(size_t)G.nc + j] = Un[1];
-        out[2 * (size_t)G.nc + j] = Un[2];
-        double sp;
-        phys &= lf_speeds<1>(Un, G.gam, &sp);
-        mx = fmax(mx, sp);
+  if (G.mu == 0.0) return;
+  const int Nx = G.nc;
+  double* Wl = L;                           // [EUL_TPB + 4][6]: W+ (3), W- (3)
+  double* Pl = L + (EUL_TPB + 4) * 6;       // [EUL_TPB + 1][3]: face fluxes
+  const double* U0 = a.dar + (p ? T.U[1] : T.U[0]);
+  double* UE0 = a.dar + T.UE[0];
+  double* UE1 = a.dar + T.UE[1];
+  const double dts_dx = (G.dt / s) / G.dx;
+  bool phys = true;
+  for (int i = 0; i < s; ++i) {
+    const double* in = (i == 0) ? U0 : ((i & 1) ? UE1 : UE0);
+    double* out = ((i + 1) & 1) ? UE1 : UE0;
+    double mx = 0.0;
+    for (int x0 = 0; x0 < Nx; x0 += EUL_TPB) {
+      // fluxes of cells x0-2 .. x0+EUL_TPB+1 (outflow: clamped)
+      for (int q = threadIdx.x; q < EUL_TPB + 4; q += blockDim.x) {
+        const int jj = min(max(x0 - 2 + q, 0), Nx - 1);
+        const double Uq[3] = {in[jj], in[(size_t)Nx + jj], in[2 * (size_t)Nx + jj]};
+        double Wp[3], Wm[3];
+        phys &= split_flux<1>(Uq, 0, alpha, G.gam, Wp, Wm);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          Wl[q * 6 + r] = Wp[r];
+          Wl[q * 6 + 3 + r] = Wm[r];
+        }
       }
-      alpha = block_max_1024(mx, red);  // also orders this sub-step's writes
+      __syncthreads();
+      // face f between cells x0+f-1 and x0+f uses the fluxes of cells
+      // x0+f-2 .. x0+f+1, i.e. entries f .. f+3
+      for (int f = threadIdx.x; f <= EUL_TPB; f += blockDim.x) {
+        const double* w = Wl + f * 6;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const double spl = vl_slope(w[6 + r] - w[r], w[12 + r] - w[6 + r], 0);
+          const double sml = vl_slope(w[15 + r] - w[9 + r], w[21 + r] - w[15 + r], 0);
+          Pl[f * 3 + r] = 0.5 * (w[6 + r] + w[15 + r]) + 0.25 * (spl - sml);
+        }
+      }
+      __syncthreads();
+      const int j = x0 + threadIdx.x;
+      if (threadIdx.x < EUL_TPB && j < Nx) {
+        const int c = threadIdx.x;
+        double Un[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          Un[r] = in[(size_t)r * Nx + j] - dts_dx * (Pl[(c + 1) * 3 + r] - Pl[c * 3 + r]);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) out[(size_t)r * Nx + j] = Un[r];
+        if (i + 1 < s) {
+          double sp;
+          phys &= lf_speeds<1>(Un, G.gam, &sp);
+          mx = fmax(mx, sp);
+        }
+      }
+      __syncthreads();  // the next segment overwrites the LDS tiles
     }
-    if (!phys) atomicOr(a.tflag + t, FLAG_NONPHYS);
+    if (i + 1 < s) alpha = block_max_1024(mx, red);  // also orders this sub-step's writes
   }
+  if (!phys) atomicOr(a.tflag + t, FLAG_NONPHYS);
 }
 
 template <int CELLS, int UNR>
@@ -126,10 +173,11 @@ __device__ void batch_kinetic_item(const BatchArgs& a, int it, unsigned char* ld
   const TubeDev T = a.tubes[t];
   const Geom G = tube_geom(T);
   const int p = a.parity;
-  const float* gin = a.gar + T.g[p];
-  float* gout = a.gar + T.g[p ^ 1];
-  const float* recin = a.rar + T.rec[p];
-  float* recout = a.rar + T.rec[p ^ 1];
+  // (selects, not indexes: a dynamic index would put the tube record in scratch)
+  const float* gin = a.gar + (p ? T.g[1] : T.g[0]);
+  float* gout = a.gar + (p ? T.g[0] : T.g[1]);
+  const float* recin = a.rar + (p ? T.rec[1] : T.rec[0]);
+  float* recout = a.rar + (p ? T.rec[0] : T.rec[1]);
   const VelNode* vt = a.vtar + T.vt;
   const int Nx = G.n[0];
   const int cl = threadIdx.x % CELLS, vg = threadIdx.x / CELLS;
@@ -206,22 +254,42 @@ __device__ void batch_kinetic_item(const BatchArgs& a, int it, unsigned char* ld
     q[5] = aE2;
   }
   __syncthreads();
-  if (vg != 0) return;
+  if (vg != 0 || !active) return;
+  double S[6] = {aK0, aK1, aK2, aE0, aE1, aE2}, C[6] = {0, 0, 0, 0, 0, 0};
+  for (int g2 = 1; g2 < VG; ++g2) {
+    const double* q = red + ((size_t)(g2 - 1) * CELLS + cl) * 6;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) two_sum(S[r], C[r], q[r]);
+  }
+  double* Sg = a.dar + T.S;
+#pragma unroll
+  for (int r = 0; r < 6; ++r) Sg[(size_t)r * Nx + x] = S[r] + C[r];
+}
+
+// Per-cell update of one item after the Euler solve of its tube: delta,
+// U^{n+1}, cf and the next record from the moment sums (eqs. (UK), (mom),
+// (minim_full)); the speeds of U^{n+1} go to the tube's next speed row.
+__device__ void batch_update_item(const BatchArgs& a, int it) {
+  constexpr int RS = rec_stride<1, float>();
+  it = __builtin_amdgcn_readfirstlane(it);
+  const int2 item = a.items[it];
+  const int t = __builtin_amdgcn_readfirstlane(item.x);
+  const TubeDev T = a.tubes[t];
+  const Geom G = tube_geom(T);
+  const int p = a.parity;
+  const int Nx = G.n[0];
+  const int x = item.y * (int)blockDim.x + (int)threadIdx.x;
   bool phys = true;
   double speed = 0.0;
-  if (active) {
-    double S[6] = {aK0, aK1, aK2, aE0, aE1, aE2}, C[6] = {0, 0, 0, 0, 0, 0};
-    for (int g2 = 1; g2 < VG; ++g2) {
-      const double* q = red + ((size_t)(g2 - 1) * CELLS + cl) * 6;
+  if (x < Nx) {
+    const double* Sg = a.dar + T.S;
+    double S[6];
 #pragma unroll
-      for (int r = 0; r < 6; ++r) two_sum(S[r], C[r], q[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < 6; ++r) S[r] += C[r];
+    for (int r = 0; r < 6; ++r) S[r] = Sg[(size_t)r * Nx + x];
     const double SK[3] = {S[0], S[1], 0.5 * S[2]};
     const double SE[3] = {S[3], S[4], 0.5 * S[5]};
     const int s = a.tube_s[t];
-    const double* UEs = a.dar + T.UE[s & 1];
+    const double* UEs = a.dar + ((s & 1) ? T.UE[1] : T.UE[0]);
     double delta[3] = {0.0, 0.0, 0.0};
     if (G.mu != 0.0) {
 #pragma unroll
@@ -237,8 +305,9 @@ __device__ void batch_kinetic_item(const BatchArgs& a, int it, unsigned char* ld
     Mat A;
 #pragma unroll
     for (int q = 0; q < 9; ++q) A.a[q] = T.A[q];
-    phys = cell_record<1, float>(Un, cfv, G, A, vt, recout + (size_t)x * RS, &speed);
-    double* Uo = a.dar + T.U[p ^ 1];
+    float* recout = a.rar + (p ? T.rec[0] : T.rec[1]);
+    phys = cell_record<1, float>(Un, cfv, G, A, a.vtar + T.vt, recout + (size_t)x * RS, &speed);
+    double* Uo = a.dar + (p ? T.U[0] : T.U[1]);
     double* cf = a.dar + T.cf;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -251,18 +320,15 @@ __device__ void batch_kinetic_item(const BatchArgs& a, int it, unsigned char* ld
   if ((threadIdx.x & 63) == 0) atomic_max_pos(a.alpha + ((size_t)t * 2 + (p ^ 1)) * ASTR, m);
 }
 
-// Euler launch: one 1024-thread block per tube, the tubes with the most
-// Euler work first.
-__global__ __launch_bounds__(1024) void k_batch_euler(BatchArgs a) {
-  __shared__ double red[16];
-  batch_euler_item(a, a.euler_order[blockIdx.x], red);
-}
-
-// Kinetic launch: persistent blocks pull (tube, segment) items from a queue,
-// the items with the most work first; the Euler launch of the step is done.
+// Step launch: persistent 1024-thread blocks pull work from one queue: the
+// Euler solves of the tubes first (most Euler work first), then the kinetic
+// items (relaxation, shift and moment sums of a (tube, segment), most work
+// first), which need nothing from the Euler solves.  (1024, 4): four waves
+// per SIMD.
 template <int CELLS, int UNR>
-__global__ __launch_bounds__(1024) void k_batch_kinetic(BatchArgs a) {
+__global__ __launch_bounds__(1024, 4) void k_batch_step(BatchArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  __shared__ double red[16];
   __shared__ int s_item;
   const int p = a.parity;
   if (blockIdx.x == 0 && threadIdx.x == 0) a.queue[p ^ 1] = 0;  // for the next step
@@ -270,10 +336,19 @@ __global__ __launch_bounds__(1024) void k_batch_kinetic(BatchArgs a) {
     __syncthreads();
     if (threadIdx.x == 0) s_item = atomicAdd(a.queue + p, 1);
     __syncthreads();
-    const int item = s_item;
-    if (item >= a.nitems) break;
-    batch_kinetic_item<CELLS, UNR>(a, item, lds_raw);
+    const int w = s_item;
+    if (w < a.ntubes)
+      batch_euler_seg(a, a.euler_order[w], reinterpret_cast<double*>(lds_raw), red);
+    else if (w < a.ntubes + a.nitems)
+      batch_kinetic_item<CELLS, UNR>(a, w - a.ntubes, lds_raw);
+    else
+      break;
   }
+}
+
+// Update launch: one block of CELLS threads per kinetic item.
+__global__ __launch_bounds__(512) void k_batch_update(BatchArgs a) {
+  batch_update_item(a, blockIdx.x);
 }
 
 }  // namespace hofks

@@ -371,15 +371,49 @@ __device__ __forceinline__ bool cell_record(const double* Un, const double* cfv,
     beta = 0.5 / th;
     const double pref = rho * pow(2.0 * M_PI * th, -0.5 * D);
     lp = log(rho) - 0.5 * D * log(2.0 * M_PI * th);
+    // 1D sums of exp(-beta (v_i - u_a)^2) over the nodes: from the node
+    // nearest to u_a outwards, each value is the previous one times a ratio
+    // that itself changes by the constant factor exp(-2 beta dv^2); both are
+    // recomputed every 16 nodes so that rounding stays within ~16 ulp.
+    // Values only decrease away from the peak, so an underflow to zero is
+    // where the true value is below the FP64 range.
     double G0[3], G1[3], G2[3];
+    const double dv = G.dv;
+    const double qf = exp(-2.0 * beta * dv * dv);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-      for (int i = 0; i < G.nv1; ++i) {
-        const double v = vt[i].v;
-        const double e = exp(-beta * (v - u[a]) * (v - u[a]));
+      int ip = (int)rint(u[a] / dv) + G.kofs;
+      ip = ip < 0 ? 0 : (ip >= G.nv1 ? G.nv1 - 1 : ip);
+      const double dp = vt[ip].v - u[a];
+      const double ep = exp(-beta * dp * dp);
+      double s0 = ep, s1 = vt[ip].v * ep, s2 = vt[ip].v2 * ep;
+      double e = ep, r = exp(-beta * (2.0 * dp * dv + dv * dv));
+      for (int i = ip + 1; i < G.nv1; ++i) {
+        if (((i - ip) & 15) == 0) {
+          const double d = vt[i].v - u[a];
+          e = exp(-beta * d * d);
+          r = exp(-beta * (2.0 * d * dv + dv * dv));
+        } else {
+          e *= r;
+          r *= qf;
+        }
         s0 += e;
-        s1 += v * e;
+        s1 += vt[i].v * e;
+        s2 += vt[i].v2 * e;
+      }
+      e = ep;
+      r = exp(-beta * (dv * dv - 2.0 * dp * dv));
+      for (int i = ip - 1; i >= 0; --i) {
+        if (((ip - i) & 15) == 0) {
+          const double d = vt[i].v - u[a];
+          e = exp(-beta * d * d);
+          r = exp(-beta * (dv * dv - 2.0 * d * dv));
+        } else {
+          e *= r;
+          r *= qf;
+        }
+        s0 += e;
+        s1 += vt[i].v * e;
         s2 += vt[i].v2 * e;
       }
       G0[a] = s0;

@@ -93,7 +93,8 @@ def run_solver(wl, steps, warmup, precision, scheme=0):
     out = {
         "cv_per_s": cv / (ms * 1e-3),
         "ms_per_step": ms / steps,
-        "kernel_ms_per_step": {"euler": kms[0] / max(cnt[0], 1), "kinetic": kin_ms},
+        "kernel_ms_per_step": {"euler": kms[0] / max(cnt[0], 1), "kinetic": kin_ms,
+                               "cell_update": kms[2] / max(cnt[2], 1)},
         "euler_substeps_last_step": substeps,
         "kinetic_GBps": achieved,
         "kinetic_hbm_frac": achieved / HBM_PEAK_GBPS,
@@ -210,8 +211,9 @@ def run_closure(warmup=2):
             "speedup_vs_plain_fp32_same_workload": ms_p / ms_c,
             "l1_density_error_vs_plain_fp32": float(np.abs(Uc[0] - Up[0]).sum() / np.abs(Up[0]).sum()),
             "kinetic_cell_fraction": frac,
-            "kernel_ms_per_step": {"euler": per_c[0], "kinetic": per_c[1], "closure_network": per_c[2]},
-            "plain_kernel_ms_per_step": {"euler": per_p[0], "kinetic": per_p[1]},
+            "kernel_ms_per_step": {"euler": per_c[0], "kinetic": per_c[1], "cell_update": per_c[2],
+                                   "closure_network": per_c[3]},
+            "plain_kernel_ms_per_step": {"euler": per_p[0], "kinetic": per_p[1], "cell_update": per_p[2]},
             "tuned": {"wavefronts_per_block": tuned_c[0], "loads_ahead": tuned_c[1]},
             "plain_tuned": {"wavefronts_per_block": tuned_p[0], "loads_ahead": tuned_p[1]},
             "training": {"seconds_incl_snapshots": train_s, "samples": nsamp, "used": used,

@@ -104,15 +104,16 @@ hofks_status hofks_read_f(hofks_ctx *ctx, double *f, size_t bytes);
  * the steps taken so far.  Synchronous. */
 hofks_status hofks_read_counters(hofks_ctx *ctx, int *substeps, long *steps);
 
-/* Per-kernel timing with hipEvents recorded on the context's stream around
- * each launch group of hofks_step: group 0 = the Euler sub-steps, 1 = the
- * kinetic kernel (relaxation, shift, moment sums, per-cell update), 2 = the
- * closure network and its indicator (closure form only).
- * If ms/launches are non-null, synchronise and return the summed elapsed
- * milliseconds and the launch counts of each group since the last call, then
- * clear them; enable != 0 keeps recording for the following steps. */
-hofks_status hofks_kernel_timing(hofks_ctx *ctx, int enable, double ms[3],
-                                 int launches[3]);
+/* Per-kernel timing with hipEvents recorded around each launch group of
+ * hofks_step: group 0 = the Euler sub-steps (on the library's auxiliary
+ * stream, beside group 1), 1 = the kinetic kernel (relaxation, shift, moment
+ * sums), 2 = the per-cell update, 3 = the closure network and its indicator
+ * (closure form only).  If ms/launches are non-null, synchronise and return
+ * the summed elapsed milliseconds and the launch counts of each group since
+ * the last call, then clear them; enable != 0 keeps recording for the
+ * following steps. */
+hofks_status hofks_kernel_timing(hofks_ctx *ctx, int enable, double ms[4],
+                                 int launches[4]);
 
 double hofks_dt(const hofks_ctx *ctx);
 const char *hofks_last_error(const hofks_ctx *ctx);

@@ -23,6 +23,7 @@
 #include "hofks.h"
 #include "batch.hpp"
 #include "closure.hpp"
+#include "euler2d.hpp"
 #include "kernels.hpp"
 #include "mlp.hpp"
 
@@ -43,6 +44,7 @@ struct Plan {
   size_t off_g[2], off_U[2], off_UE[2], off_rec[2], off_vt, off_cf, off_part, off_slots,
       off_tiles, off_flag;
   size_t off_clos;  // closure form (2D): N^, indicator, dilation, mode, delta marks, count
+  size_t off_sums;  // kinetic moment sums per cell, 2 (d+2) doubles
   size_t total;
 };
 
@@ -227,6 +229,8 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
   off = align256(off + (size_t)2 * 256 * ASTR * sizeof(double));
   P->off_flag = off;
   off = align256(off + 64);
+  P->off_sums = off;
+  off = align256(off + (size_t)2 * nm * G.nc * sizeof(double));
   if (d == 2) {
     P->off_clos = off;
     off = align256(off + (size_t)G.nc * sizeof(float4));
@@ -267,6 +271,10 @@ struct hofks_ctx {
   std::vector<MarkRec> ev_marks;
   size_t ev_next;
   struct Batch* batch;  // non-null for a batch of independent tubes
+  // the Euler solve of a step runs on `aux`, forked from and joined to the
+  // caller's stream with two events, beside the kinetic kernel
+  hipStream_t aux;
+  hipEvent_t ev_fork, ev_join;
   // closure form (2D-2V): network (caller's device memory), scale of its
   // output, indicator threshold; per-cell arrays in the workspace
   const void* clos_w;
@@ -314,18 +322,20 @@ hipEvent_t next_event(hofks_ctx* c) {
 struct Mark {
   hofks_ctx* c;
   int group, count;
+  hipStream_t st;
   hipEvent_t a = nullptr;
-  Mark(hofks_ctx* c_, int g, int n = 1) : c(c_), group(g), count(n) {
+  Mark(hofks_ctx* c_, int g, int n = 1, hipStream_t s_ = nullptr)
+      : c(c_), group(g), count(n), st(s_ ? s_ : c_->stream) {
     if (c->timing) {
       a = next_event(c);
-      if (a) (void)hipEventRecord(a, c->stream);
+      if (a) (void)hipEventRecord(a, st);
     }
   }
   ~Mark() {
     if (c->timing && a) {
       hipEvent_t b = next_event(c);
       if (b) {
-        (void)hipEventRecord(b, c->stream);
+        (void)hipEventRecord(b, st);
         c->ev_marks.push_back({group, count, a, b});
       }
     }
@@ -383,23 +393,58 @@ void dispatch_kin(hofks_ctx* c, const StepArgs<T>& a, dim3 grid) {
 template <typename T>
 hofks_status launch_closure_step(hofks_ctx* c, StepArgs<T>& a, float* snap_x, float* snap_t);
 
+template <int D, typename T>
+void launch_euler(hofks_ctx* c, const StepArgs<T>& a, hipStream_t st);
+
+// Euler launches of the step on the auxiliary stream, after everything
+// already queued on the caller's stream
+template <int D, typename T>
+hofks_status fork_euler(hofks_ctx* c, const StepArgs<T>& a) {
+  HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+  HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+  {
+    Mark m0(c, 0, 1, c->aux);
+    launch_euler<D, T>(c, a, c->aux);
+    HIPCHK(c, hipGetLastError());
+  }
+  HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
+  return HOFKS_OK;
+}
+
+// join the Euler launches and run the per-cell update on the caller's stream
+template <int D, typename T, bool CLOS>
+hofks_status join_update(hofks_ctx* c, const StepArgs<T>& a) {
+  const Plan& P = c->P;
+  HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+  Mark m(c, 2);
+  hipLaunchKernelGGL((k_cell_update<D, T, CLOS>), dim3(nblk(P.G.nc)), dim3(256), 0, c->stream, a,
+                     P.G, P.A);
+  HIPCHK(c, hipGetLastError());
+  return HOFKS_OK;
+}
+
 // Euler solve of a step: one launch per sub-step for the first K = (last
 // known count + 2) sub-steps (the kernel boundary is the grid-wide barrier),
 // then a persistent tail that runs any further sub-steps with an in-kernel
 // barrier (it returns at once when K >= s)
 template <int D, typename T>
-void launch_euler(hofks_ctx* c, const StepArgs<T>& a) {
+void launch_euler(hofks_ctx* c, const StepArgs<T>& a, hipStream_t st) {
   const Plan& P = c->P;
   const int K = std::max(1, std::min(c->s_cap, c->s_known + 2));
-  for (int i = 0; i < K; ++i)
-    hipLaunchKernelGGL((k_euler_sub<D, T>), dim3(nblk(P.G.nc)), dim3(256), 0, c->stream, a, P.G,
-                       i);
+  if constexpr (D == 2) {  // 16 x 16 LDS tiles
+    const int ntx = (P.G.n[0] + ET - 1) / ET, nty = (P.G.n[1] + ET - 1) / ET;
+    for (int i = 0; i < K; ++i)
+      hipLaunchKernelGGL((k_euler_sub_tile<T>), dim3(ntx * nty), dim3(256), 0, st, a, P.G, i, ntx);
+  } else {
+    for (int i = 0; i < K; ++i)
+      hipLaunchKernelGGL((k_euler_sub<D, T>), dim3(nblk(P.G.nc)), dim3(256), 0, st, a, P.G, i);
+  }
   if (P.ETPB == 1024)
-    hipLaunchKernelGGL((k_euler<D, T, 1024>), dim3(P.GE), dim3(1024), 0, c->stream, a, P.G, K);
+    hipLaunchKernelGGL((k_euler<D, T, 1024>), dim3(P.GE), dim3(1024), 0, st, a, P.G, K);
   else if (P.ETPB == 512)
-    hipLaunchKernelGGL((k_euler<D, T, 512>), dim3(P.GE), dim3(512), 0, c->stream, a, P.G, K);
+    hipLaunchKernelGGL((k_euler<D, T, 512>), dim3(P.GE), dim3(512), 0, st, a, P.G, K);
   else
-    hipLaunchKernelGGL((k_euler<D, T, 256>), dim3(P.GE), dim3(256), 0, c->stream, a, P.G, K);
+    hipLaunchKernelGGL((k_euler<D, T, 256>), dim3(P.GE), dim3(256), 0, st, a, P.G, K);
 }
 
 template <int D, typename T>
@@ -433,6 +478,7 @@ hofks_status launch_step(hofks_ctx* c, float* snap_x = nullptr, float* snap_t = 
   a.tgt = nullptr;
   a.kcount = nullptr;
   a.thr = 0.0;
+  a.sums = (double*)(c->ws + P.off_sums);
   const bool ft = (P.G.mu == 0.0);
   const bool eul = !ft && c->desc.scheme != 1;
   if (c->clos_dirty && !eul) {
@@ -444,19 +490,21 @@ hofks_status launch_step(hofks_ctx* c, float* snap_x = nullptr, float* snap_t = 
       return launch_closure_step<T>(c, a, snap_x, snap_t);
   }
   if (eul) {
-    Mark m0(c, 0);
-    launch_euler<D, T>(c, a);
-    HIPCHK(c, hipGetLastError());
+    hofks_status st = fork_euler<D, T>(c, a);
+    if (st) return st;
   }
   const dim3 grid((unsigned)((long)P.nseg * P.nrowgrp));
-  Mark m(c, 1);
-  if (ft)
-    dispatch_kin<D, T, true, false>(c, a, grid);
-  else if (eul)
-    dispatch_kin<D, T, false, true>(c, a, grid);
-  else
-    dispatch_kin<D, T, false, false>(c, a, grid);
-  HIPCHK(c, hipGetLastError());
+  {
+    Mark m(c, 1);
+    if (ft)
+      dispatch_kin<D, T, true, false>(c, a, grid);
+    else if (eul)
+      dispatch_kin<D, T, false, true>(c, a, grid);
+    else
+      dispatch_kin<D, T, false, false>(c, a, grid);
+    HIPCHK(c, hipGetLastError());
+  }
+  if (eul) return join_update<D, T, false>(c, a);
   return HOFKS_OK;
 }
 
@@ -474,17 +522,21 @@ hofks_status launch_closure_step(hofks_ctx* c, StepArgs<T>& a, float* snap_x, fl
   a.dfl = c->cdfl;
   a.kcount = c->kcount;
   a.thr = c->clos_thr;
+  {
+    hofks_status st = fork_euler<2, T>(c, a);
+    if (st) return st;
+  }
   const bool all_kin = snap_x || !c->clos_on;  // snapshot, or clearing the marks
   if (all_kin) {
     a.tgt = snap_t;
-    Mark m2(c, 2);
+    Mark m2(c, 3);
     hipLaunchKernelGGL(k_fill_u8, dim3(nblk(nc)), dim3(256), 0, c->stream, c->cmode, nc,
                        (unsigned char)1);
     if (snap_x)
       hipLaunchKernelGGL(k_closure_features, dim3(nblk(nc)), dim3(256), 0, c->stream,
                          (const double*)a.U_in, snap_x, P.G, ftau);
   } else {
-    Mark m2(c, 2);
+    Mark m2(c, 3);
     ClosureArgs ca;
     ca.U = a.U_in;
     ca.packed = c->clos_w;
@@ -508,11 +560,6 @@ hofks_status launch_closure_step(hofks_ctx* c, StepArgs<T>& a, float* snap_x, fl
                        (const unsigned char*)c->ctmp, c->cmode, P.G, h);
   }
   HIPCHK(c, hipGetLastError());
-  {
-    Mark m0(c, 0);
-    launch_euler<2, T>(c, a);
-    HIPCHK(c, hipGetLastError());
-  }
   const dim3 grid((unsigned)((long)P.nseg * P.nrowgrp));
   Mark m(c, 1);
   constexpr bool CP = sizeof(T) == 4;
@@ -534,6 +581,8 @@ hofks_status launch_closure_step(hofks_ctx* c, StepArgs<T>& a, float* snap_x, fl
 #undef KCB
 #undef KC
   HIPCHK(c, hipGetLastError());
+  hofks_status st = join_update<2, T, true>(c, a);
+  if (st) return st;
   if (!all_kin) c->clos_steps++;
   c->clos_dirty = !all_kin;
   return HOFKS_OK;
@@ -704,6 +753,12 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
     b += align256(4 * nc);
     c->kcount = (unsigned long long*)b;
     c->clos_y0 = (float*)(b + 16);
+  }
+  if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return HOFKS_EDEVICE;
   }
   c->tau = INFINITY;
   c->s_cap = 1;
@@ -896,15 +951,15 @@ hofks_status hofks_kernel_timing(hofks_ctx* c, int enable, double* ms, int* laun
   if (!c) return HOFKS_EINVAL;
   if (ms || launches) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double acc[3] = {0.0, 0.0, 0.0};
-    int cnt[3] = {0, 0, 0};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int cnt[4] = {0, 0, 0, 0};
     for (auto& m : c->ev_marks) {
       float t = 0.0f;
       HIPCHK(c, hipEventElapsedTime(&t, m.a, m.b));
       acc[m.group] += t;
       cnt[m.group] += m.count;
     }
-    for (int g = 0; g < 3; ++g) {
+    for (int g = 0; g < 4; ++g) {
       if (ms) ms[g] = acc[g];
       if (launches) launches[g] = cnt[g];
     }
@@ -1747,5 +1802,11 @@ extern "C" void hofks_destroy(hofks_ctx* c) {
   if (!c) return;
   batch_free(c);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->aux) {
+    (void)hipStreamSynchronize(c->aux);
+    (void)hipStreamDestroy(c->aux);
+  }
   delete c;
 }

@@ -492,6 +492,7 @@ struct StepArgs {
   float* tgt;                 // optional: training targets N / (lam s) per cell
   unsigned long long* kcount;  // kinetic cell-steps (accumulated)
   double thr;
+  double* sums;  // [2 (d+2)][nc]: moment sums of f* and of E, for k_cell_update
 };
 
 // Euler sub-step i (eq. (discmom) with the flux of section 4.3), one cell per
@@ -963,6 +964,19 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
     }
   }
 
+  if constexpr (EUL) {
+    // the Euler solve of the step runs on another stream meanwhile: store the
+    // sums; k_cell_update forms delta, U^{n+1}, cf and the next record
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < NM; ++r) {
+        a.sums[(size_t)r * G.nc + dest] = COMP ? SK[r] + CK[r] : SK[r];
+        a.sums[(size_t)(NM + r) * G.nc + dest] = COMP ? SE[r] + CE[r] : SE[r];
+      }
+    }
+    return;
+  }
+
   // ------------------------------------------------- per-cell update
   const bool need_eq = G.mu != 0.0;
   bool phys = true;
@@ -1011,6 +1025,67 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
       const double m = wave_max(phys ? speed[d2] : 0.0);
       if (lane == 0) atomic_max_pos(a.set_w + d2, m);
     }
+  }
+}
+
+// Per-cell update of a step after its kinetic sums and its Euler solve
+// (eqs. (UK), (mom), (minim_full)): delta = U_E - U_M, U^{n+1} = U_* + U_E,
+// cf = A delta, the next record and the speeds of U^{n+1}; in the closure
+// form also N^ for closure cells, the delta marks and the kinetic count.
+template <int D, typename T, bool CLOS>
+__global__ __launch_bounds__(256) void k_cell_update(StepArgs<T> a, Geom G, Mat A) {
+  constexpr int NM = D + 2;
+  constexpr int RS = rec_stride<D, T>();
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = j < G.nc;
+  const bool kin = !CLOS || (active && a.mode[j] != 0);
+  bool phys = true;
+  double speed[3] = {0.0, 0.0, 0.0};
+  if (active) {
+    double SK[NM], SE[NM], Z[NM];
+#pragma unroll
+    for (int r = 0; r < NM; ++r) {
+      SK[r] = a.sums[(size_t)r * G.nc + j];
+      SE[r] = a.sums[(size_t)(NM + r) * G.nc + j];
+      Z[r] = 0.0;
+    }
+    bool over;
+    const int s = substeps<D>(a.set_r, G, a.s_cap, &over);
+    const double* UEs = (s & 1) ? a.UE1 : a.UE0;
+    double delta[NM], Un[NM], cfv[NM];
+#pragma unroll
+    for (int r = 0; r < NM; ++r) {
+      const double UM = G.mu * (G.w * SE[r]);
+      const double UEv = G.mu * UEs[(size_t)r * G.nc + j];
+      delta[r] = UEv - UM;
+    }
+#pragma unroll
+    for (int r = 0; r < NM; ++r) Un[r] = G.w * SK[r] + delta[r];
+    if constexpr (CLOS) closure_epilogue<D>(a, G, j, kin, SK, Z, SE, Z, false, delta, Un);
+#pragma unroll
+    for (int r = 0; r < NM; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int s2 = 0; s2 < NM; ++s2) acc += A.a[r * NM + s2] * delta[s2];
+      cfv[r] = acc;
+    }
+    phys = cell_record<D, T>(Un, cfv, G, A, a.vt, a.rec_out + (size_t)j * RS, speed, kin);
+#pragma unroll
+    for (int r = 0; r < NM; ++r) {
+      a.U_out[(size_t)r * G.nc + j] = Un[r];
+      a.cf[(size_t)r * G.nc + j] = cfv[r];
+    }
+  }
+  if (active && G.mu != 0.0 && !phys) atomicOr(a.flag, FLAG_NONPHYS);
+  const int lane = threadIdx.x & 63;
+  if (CLOS) {
+    const unsigned long long bk = __ballot(kin);
+    if (lane == 0 && bk) atomicAdd(a.kcount, (unsigned long long)__popcll(bk));
+  }
+#pragma unroll
+  for (int d2 = 0; d2 < D; ++d2) {
+    const double m = wave_max(phys ? speed[d2] : 0.0);
+    if (lane == 0) atomic_max_pos(a.set_w + d2, m);
   }
 }
 

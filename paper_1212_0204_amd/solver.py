@@ -114,10 +114,11 @@ class Solver:
         return s.value, n.value
 
     def kernel_timing(self, enable=True):
-        """(ms[3], launches[3]) of the Euler, kinetic and cell-update groups
-        since the previous call; keeps recording while ``enable``."""
-        ms = np.zeros(3)
-        cnt = (ctypes.c_int * 3)()
+        """(ms[4], launches[4]) of the Euler, kinetic, per-cell update and
+        closure-network groups since the previous call; keeps recording
+        while ``enable``."""
+        ms = np.zeros(4)
+        cnt = (ctypes.c_int * 4)()
         self._check(_lib.lib().hofks_kernel_timing(self._h, int(enable), _dp(ms), cnt),
                     "kernel_timing")
         return ms, list(cnt)

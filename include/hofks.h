@@ -100,6 +100,18 @@ hofks_status hofks_read_moments(hofks_ctx *ctx, double *U);
  * Synchronous.  Uses the idle half of the piece buffers as staging. */
 hofks_status hofks_read_f(hofks_ctx *ctx, double *f, size_t bytes);
 
+/* Checkpoint and resume.  hofks_state_bytes gives the size of a host image
+ * of the state (header with the grid, tau, step count and the speeds of U^n,
+ * then U^n, the pending correction, the records and the pieces);
+ * hofks_read_state fills it (synchronous; HOFKS_ESTATE while closure cells
+ * hold no pieces), hofks_write_state restores it into a context of the same
+ * grid (HOFKS_EINVAL otherwise), after which stepping continues exactly as
+ * from the saved step.  Host buffers belong to the caller.  Not available
+ * for batches. */
+hofks_status hofks_state_bytes(hofks_ctx *ctx, size_t *bytes);
+hofks_status hofks_read_state(hofks_ctx *ctx, void *host, size_t bytes);
+hofks_status hofks_write_state(hofks_ctx *ctx, const void *host, size_t bytes);
+
 /* Number of Euler sub-steps of the last completed step (0 if none ran) and
  * the steps taken so far.  Synchronous. */
 hofks_status hofks_read_counters(hofks_ctx *ctx, int *substeps, long *steps);

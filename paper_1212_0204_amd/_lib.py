@@ -21,7 +21,7 @@ SYMBOLS = [
     "hofks_batch_create", "hofks_batch_tube_flags", "hofks_autotune", "hofks_last_error", "hofks_destroy",
     "hofks_closure_enable", "hofks_closure_disable", "hofks_closure_snapshot", "hofks_closure_stats",
     "hofks_mlp_nparam", "hofks_mlp_packed_bytes", "hofks_mlp_pack", "hofks_mlp_forward",
-    "hofks_mlp_grad", "hofks_mlp_adam",
+    "hofks_mlp_grad", "hofks_mlp_adam", "hofks_state_bytes", "hofks_read_state", "hofks_write_state",
 ]
 
 
@@ -67,6 +67,9 @@ def lib():
     L.hofks_last_error.restype = ctypes.c_char_p
     L.hofks_destroy.argtypes = [vp]
     L.hofks_destroy.restype = None
+    L.hofks_state_bytes.argtypes = [vp, P(sz)]
+    L.hofks_read_state.argtypes = [vp, vp, sz]
+    L.hofks_write_state.argtypes = [vp, vp, sz]
     L.hofks_closure_enable.argtypes = [vp, vp, d, d]
     L.hofks_closure_disable.argtypes = [vp]
     L.hofks_closure_snapshot.argtypes = [vp, vp, vp]

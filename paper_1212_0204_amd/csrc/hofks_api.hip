@@ -932,6 +932,106 @@ hofks_status hofks_read_f(hofks_ctx* c, double* f, size_t bytes) {
   return read_flag(c);
 }
 
+// ------------------------------------------------------------ checkpoint
+// Host image of the state: a header (shape, tau, step count, speeds of U^n)
+// then U^n, the pending correction cf, the records and the pieces (the
+// Eulerian pieces g; f = g + w m.cf).  Enough to continue stepping exactly.
+struct StateHeader {
+  char magic[8];
+  int version, dim, n[3], nv1, precision, scheme, bc[3];
+  double dx, dv, tau;
+  long long steps;
+  double speeds[ASTR];
+};
+
+size_t state_bytes(const Plan& P) {
+  return sizeof(StateHeader) + 2 * (size_t)P.nm * P.G.nc * sizeof(double) +
+         (size_t)P.RS * P.G.nc * P.tsize + (size_t)P.G.nv * P.G.nc * P.tsize;
+}
+
+hofks_status hofks_state_bytes(hofks_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return HOFKS_EINVAL;
+  if (c->batch) return fmt_err(c->err, "not available for batches"), HOFKS_EINVAL;
+  *bytes = state_bytes(c->P);
+  return HOFKS_OK;
+}
+
+hofks_status hofks_read_state(hofks_ctx* c, void* host, size_t bytes) {
+  if (!c || !host) return HOFKS_EINVAL;
+  if (c->batch) return fmt_err(c->err, "not available for batches"), HOFKS_EINVAL;
+  if (!c->ready) return fmt_err(c->err, "no state to read"), HOFKS_ESTATE;
+  if (c->clos_dirty)
+    return fmt_err(c->err, "closure cells hold no pieces: run a step without the closure first"),
+           HOFKS_ESTATE;
+  const Plan& P = c->P;
+  if (bytes < state_bytes(P)) return HOFKS_ESIZE;
+  hofks_status st = read_flag(c);
+  if (st) return st;
+  StateHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, "HOFKSST1", 8);
+  h.version = 1;
+  h.dim = P.d;
+  for (int a = 0; a < 3; ++a) {
+    h.n[a] = P.G.n[a];
+    h.bc[a] = P.G.bc[a];
+  }
+  h.nv1 = P.G.nv1;
+  h.precision = P.prec;
+  h.scheme = c->desc.scheme;
+  h.dx = P.G.dx;
+  h.dv = P.G.dv;
+  h.tau = c->tau;
+  h.steps = c->steps;
+  HIPCHK(c, hipMemcpyAsync(h.speeds, slot_set(c, rset(c)), sizeof(h.speeds), hipMemcpyDeviceToHost,
+                           c->stream));
+  unsigned char* o = (unsigned char*)host + sizeof(StateHeader);
+  const size_t ub = (size_t)P.nm * P.G.nc * sizeof(double);
+  const size_t rb = (size_t)P.RS * P.G.nc * P.tsize, gb = (size_t)P.G.nv * P.G.nc * P.tsize;
+  const int rp = rpar(c);
+  HIPCHK(c, hipMemcpyAsync(o, c->U[rp], ub, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(o + ub, c->cf, ub, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(o + 2 * ub, c->rec[rp], rb, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(o + 2 * ub + rb, c->g[c->cur], gb, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::memcpy(host, &h, sizeof(h));
+  return HOFKS_OK;
+}
+
+hofks_status hofks_write_state(hofks_ctx* c, const void* host, size_t bytes) {
+  if (!c || !host) return HOFKS_EINVAL;
+  if (c->batch) return fmt_err(c->err, "not available for batches"), HOFKS_EINVAL;
+  const Plan& P = c->P;
+  if (bytes < state_bytes(P)) return HOFKS_ESIZE;
+  StateHeader h;
+  std::memcpy(&h, host, sizeof(h));
+  bool same = std::memcmp(h.magic, "HOFKSST1", 8) == 0 && h.version == 1 && h.dim == P.d &&
+              h.nv1 == P.G.nv1 && h.precision == P.prec && h.scheme == c->desc.scheme &&
+              h.dx == P.G.dx && h.dv == P.G.dv && h.steps >= 0;
+  for (int a = 0; a < 3; ++a) same = same && h.n[a] == P.G.n[a] && h.bc[a] == P.G.bc[a];
+  if (!same) return fmt_err(c->err, "state image does not match this grid"), HOFKS_EINVAL;
+  hofks_status st = hofks_set_tau(c, h.tau);  // lambda of the stored records
+  if (st) return st;
+  st = reset_counters(c);
+  if (st) return st;
+  c->steps = h.steps;
+  c->cur = 0;
+  const unsigned char* o = (const unsigned char*)host + sizeof(StateHeader);
+  const size_t ub = (size_t)P.nm * P.G.nc * sizeof(double);
+  const size_t rb = (size_t)P.RS * P.G.nc * P.tsize, gb = (size_t)P.G.nv * P.G.nc * P.tsize;
+  const int rp = rpar(c);
+  HIPCHK(c, hipMemcpyAsync(c->U[rp], o, ub, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->cf, o + ub, ub, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->rec[rp], o + 2 * ub, rb, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->g[0], o + 2 * ub + rb, gb, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(slot_set(c, rset(c)), h.speeds, sizeof(h.speeds),
+                           hipMemcpyHostToDevice, c->stream));
+  c->ready = true;
+  st = plan_substeps(c);
+  if (st) return st;
+  return read_flag(c);
+}
+
 hofks_status hofks_read_counters(hofks_ctx* c, int* substeps, long* steps) {
   if (!c) return HOFKS_EINVAL;
   int h[2] = {0, 0};

@@ -107,6 +107,20 @@ class Solver:
         self._check(_lib.lib().hofks_read_f(self._h, _dp(f), f.nbytes), "read_f")
         return f
 
+    def read_state(self):
+        """host image of the state (bytes) to resume from with write_state"""
+        n = ctypes.c_size_t(0)
+        self._check(_lib.lib().hofks_state_bytes(self._h, ctypes.byref(n)), "state_bytes")
+        buf = np.empty(n.value, dtype=np.uint8)
+        self._check(_lib.lib().hofks_read_state(self._h, buf.ctypes.data_as(ctypes.c_void_p),
+                                                buf.nbytes), "read_state")
+        return buf
+
+    def write_state(self, image):
+        buf = np.ascontiguousarray(image, dtype=np.uint8)
+        self._check(_lib.lib().hofks_write_state(self._h, buf.ctypes.data_as(ctypes.c_void_p),
+                                                 buf.nbytes), "write_state")
+
     def counters(self):
         s, n = ctypes.c_int(0), ctypes.c_long(0)
         self._check(_lib.lib().hofks_read_counters(self._h, ctypes.byref(s), ctypes.byref(n)),

@@ -227,3 +227,33 @@ def test_grid_autotune_then_parity(tmp_path):
     o.init_macro(rho, u, th)
     o.step(6)
     assert moment_errors(s.read_moments(), o.U, 2).max() < TOL64
+
+
+@gpu
+@pytest.mark.parametrize("d,n,nv,prec,bc", [(2, (70, 37), 10, 0, (0, 0)), (3, (20, 12, 10), 6, 1, (0, 1, 0)),
+                                             (1, (150,), 16, 0, (1,))])
+def test_checkpoint_resume_is_exact(d, n, nv, prec, bc):
+    """a state image taken after 3 steps, restored into a fresh context,
+    continues bit for bit like the original run"""
+    announce("checkpoint", d, n, nv, prec, bc)
+    from paper_1212_0204_amd import HofksError, Solver
+    rng_fields = W.perturbed_gas(n[0], d, 0.2, 0.1, 2, (11, 12)) if d > 1 else W.sod_tube(n[0])
+    if d == 2 and n[0] != n[1] or d == 3:
+        rho = 1.0 + 0.1 * np.sin(np.arange(int(np.prod(n))) * 0.37)
+        rng_fields = (rho, np.zeros((d, rho.size)), np.ones(rho.size))
+    dx = 1.0 / n[0]
+    s1 = Solver(d, n, dx, nv, 0.5, bc=bc, precision=prec, tau=2e-2)
+    s1.set_state_macro(*rng_fields)
+    s1.step(3)
+    img = s1.read_state()
+    s1.step(4)
+    Ua, fa = s1.read_moments(), s1.read_f()
+    s2 = Solver(d, n, dx, nv, 0.5, bc=bc, precision=prec, tau=1.0)
+    s2.write_state(img)
+    assert s2.counters()[1] == 3
+    s2.step(4)
+    assert np.array_equal(s2.read_moments(), Ua)
+    assert np.array_equal(s2.read_f(), fa)
+    s3 = Solver(d, n, dx, nv + 2, 0.5, bc=bc, precision=prec, tau=2e-2)
+    with pytest.raises(HofksError):
+        s3.write_state(img)

@@ -246,27 +246,36 @@ def copy_probe(mb, reps=5):
             "GBps": moved / (ms * 1e-3) / 1e9}
 
 
-def cpu_baseline(wl, budget_s=12.0):
+def cpu_baseline(wl, budget_s=12.0, single_s=6.0):
     """the oracle on the host cores, on the same workload: as many whole steps
-    of the full grid as fit in ~budget_s (at least one)."""
+    of the full grid as fit in ~budget_s (at least one) with all threads,
+    then ~single_s with one thread."""
     import workloads as W
-    from oracle import Oracle
+    from oracle import Oracle, max_threads, set_threads
 
-    o = Oracle(wl.d, wl.n, wl.dx, wl.nv, wl.dv, bc=wl.bc, tau=wl.tau)
-    o.init_macro(*W.initial_fields(wl))
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        o.step(1)
-        n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    el = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    def timed(budget):
+        o = Oracle(wl.d, wl.n, wl.dx, wl.nv, wl.dv, bc=wl.bc, tau=wl.tau)
+        o.init_macro(*W.initial_fields(wl))
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            o.step(1)
+            n += 1
+            if time.perf_counter() - t0 > budget:
+                break
+        return n, time.perf_counter() - t0
+
+    cores = max_threads()
+    n, el = timed(budget_s)
+    set_threads(1)
+    n1, el1 = timed(single_s)
+    set_threads(cores)
     return {"value": wl.cv * n / el, "unit": "cell-velocity updates/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{wl.name}: {n} full steps of the {wl.nc}-cell x {wl.nvel}-velocity grid "
-                      f"from the initial state ({el:.1f} s, OpenMP over cells, plain FP64 C)"}
+                      f"from the initial state ({el:.1f} s, OpenMP over cells, plain FP64 C)",
+            "single_thread": {"value": wl.cv * n1 / el1, "cores": 1,
+                              "sample": f"{n1} full steps ({el1:.1f} s)"}}
 
 
 def main():

@@ -51,6 +51,8 @@ def _lib():
                      "or_get_velocities"):
             getattr(lib, name).argtypes = [vp, dp]
         lib.or_last_substeps.argtypes = [vp]
+        lib.or_set_threads.argtypes = [i]
+        lib.or_max_threads.restype = i
         lib.or_dt.argtypes = [vp]
         lib.or_dt.restype = d
         lib.or_lambda.argtypes = [vp]
@@ -220,3 +222,12 @@ def mlp_adam(params, grad, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8):
     """one Adam step in place on params, m, v (FP64 arrays)"""
     g = np.ascontiguousarray(grad, dtype=np.float64)
     _lib().mlp_adam(_dp(params), _dp(g), _dp(m), _dp(v), lr, b1, b2, eps, int(step))
+
+
+def set_threads(n):
+    """threads of the oracle's OpenMP loops"""
+    _lib().or_set_threads(int(n))
+
+
+def max_threads():
+    return _lib().or_max_threads()

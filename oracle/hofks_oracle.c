@@ -58,6 +58,9 @@
  * x-fastest, k = (iz*n + iy)*n + ix with k_a = i_a - n/2 (integer division).
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -612,6 +615,23 @@ void or_get_delta(const or_state *S, double *dl) {
   memcpy(dl, S->delta, sizeof(double) * S->nm * S->nc);
 }
 int or_last_substeps(const or_state *S) { return S->last_substeps; }
+
+/* threads of the OpenMP loops (for timing with one thread and with all) */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int or_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 double or_dt(const or_state *S) { return S->dt; }
 double or_lambda(const or_state *S) { return S->lam; }
 void or_get_A(const or_state *S, double *A) {

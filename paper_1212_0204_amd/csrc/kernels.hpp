@@ -816,6 +816,32 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
     const T hrowT = (T)hrow;
     double aK0 = 0.0, aK1 = 0.0, aK2 = 0.0, aE0 = 0.0, aE1 = 0.0, aE2 = 0.0;
 
+    if constexpr (CLOS) {
+      if (!tile_kin) {
+        // closure tile: every piece is the equilibrium of its upstream cell,
+        // so only E is evaluated (record chunks without p) and summed once;
+        // the sums of f* equal those of E
+        for (int ix = ixa; ix < ixb; ++ix) {
+          const int kx = ix - G.kofs;
+          const VelNode vn = a.vt[ix];
+          const T vxT = (sizeof(T) == 4) ? (T)vn.vf : (T)vn.v;
+          const T vhT = (sizeof(T) == 4) ? (T)(hrowT + (T)vn.v2hf) : (T)(hrow + 0.5 * vn.v2);
+          // record: [lp, u_x, u_y, beta | p_0..p_3 | e_0..e_3]
+          const T* rr = Lw + (lane - kx + lofs) * RS;
+          const T dx_ = vxT - rr[1], dy_ = vyT - rr[2];
+          const T M = fast_exp<T>(rr[0] - fabs(rr[3]) * (dx_ * dx_ + dy_ * dy_));
+          const T E = M + (rr[8] + rr[9] * vxT + rr[10] * vyT + rr[11] * vhT);
+          const double Ed = (double)E;
+          aE0 += Ed;
+          aE1 += vn.v * Ed;
+          aE2 += vn.v2 * Ed;
+        }
+        aK0 = aE0;
+        aK1 = aE1;
+        aK2 = aE2;
+        goto row_done;
+      }
+    }
     for (int ix0 = ixa; ix0 < ixb; ix0 += UNR) {
       T gv[UNR];
 #pragma unroll
@@ -901,6 +927,7 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
         aK2 += vn.v2 * fd;
       }
     }
+  row_done:
     // fold the row into the totals: m = (1, v_x, v_y, v_z, |v|^2/2)
     double rk[NM + 2], re[NM + 2];  // padded: the D >= 3 branch indexes [3]
     rk[0] = aK0;

@@ -1,13 +1,14 @@
 // Euler sub-step on a 2D grid with LDS tiles (section 4.3.2, eq. (discmom)
 // with the limited slopes of the MUSCL flux).  One block advances a 16 x 16
 // tile of cells: it loads the tile and two halo cells on every side into
-// LDS, evaluates the split fluxes W+- = F_a(U) +- alpha_a U once per cell and
-// axis (x fluxes for the 20 x 16 cells the x faces need, y fluxes for the
-// 16 x 20 cells the y faces need), then every thread forms the four faces of
-// its cell and the new value.  The per-cell form `euler_cell` evaluates ten
-// fluxes and reads 36 values from memory per cell; here it is 2.5 fluxes and
-// about 1.6 values.  Same arithmetic per face; the speeds, the sub-step
-// count and the output buffers follow `k_euler_sub`.
+// LDS, then for each axis in turn evaluates the split fluxes
+// W+- = F_a(U) +- alpha_a U once per cell (x: the 20 x 16 cells the x faces
+// need; y: the 16 x 20 cells the y faces need) into one buffer, every thread
+// adding the difference of its cell's two faces along that axis; then the
+// new value.  The per-cell form `euler_cell` evaluates ten fluxes and reads
+// 36 values from memory per cell; here it is 2.5 fluxes and about 1.6
+// values.  Same arithmetic per face; the speeds, the sub-step count and the
+// output buffers follow `k_euler_sub`.
 #pragma once
 #include "kernels.hpp"
 
@@ -41,8 +42,9 @@ __global__ __launch_bounds__(256) void k_euler_sub_tile(StepArgs<T> a, Geom G, i
   const int t = threadIdx.x;
 
   __shared__ double Ut[NM][EH][EH];
-  __shared__ double Wx[2][NM][ET][EH];  // [+/-][r][y][x + 2]
-  __shared__ double Wy[2][NM][EH][ET];  // [+/-][r][y + 2][x]
+  // split fluxes along one axis at a time (x, then y) in one buffer:
+  // x: [+/-][r][y][x + 2] over 16 x 20 cells; y: [+/-][r][y + 2][x] over 20 x 16
+  __shared__ double Wb[2][NM][ET * EH];
 
   // tile + halo (periodic wrap or outflow clamp, as the per-cell form)
   for (int q = t; q < EH * EH; q += blockDim.x) {
@@ -55,61 +57,52 @@ __global__ __launch_bounds__(256) void k_euler_sub_tile(StepArgs<T> a, Geom G, i
   }
   __syncthreads();
   bool phys = true;
-  // x fluxes of cells (x = -2..17, y = 0..15), y fluxes of (x = 0..15, y = -2..17)
-  for (int q = t; q < 2 * ET * EH; q += blockDim.x) {
-    const int ax = q < ET * EH ? 0 : 1;
-    const int qq = ax == 0 ? q : q - ET * EH;
-    const int hx = ax == 0 ? qq % EH : qq % ET + 2;
-    const int hy = ax == 0 ? qq / EH + 2 : qq / ET;
-    double Uq[NM];
+  const int lx = t % ET, ly = t / ET;
+  const int gx = X0 + lx, gy = Y0 + ly;
+  const bool own = gx < Nx && gy < Ny;
+  double div[NM] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int r = 0; r < NM; ++r) Uq[r] = Ut[r][hy][hx];
-    double Wp[NM], Wm[NM];
-    phys &= split_flux<2>(Uq, ax, alpha[ax], G.gam, Wp, Wm);
+  for (int ax = 0; ax < 2; ++ax) {
+    if (ax == 1) __syncthreads();  // the x faces have been read
+    // fluxes along ax: x for cells (x = -2..17, y = 0..15), y for (x = 0..15, y = -2..17)
+    for (int q = t; q < ET * EH; q += blockDim.x) {
+      const int hx = ax == 0 ? q % EH : q % ET + 2;
+      const int hy = ax == 0 ? q / EH + 2 : q / ET;
+      double Uq[NM];
 #pragma unroll
-    for (int r = 0; r < NM; ++r) {
-      if (ax == 0) {
-        Wx[0][r][hy - 2][hx] = Wp[r];
-        Wx[1][r][hy - 2][hx] = Wm[r];
-      } else {
-        Wy[0][r][hy][hx - 2] = Wp[r];
-        Wy[1][r][hy][hx - 2] = Wm[r];
+      for (int r = 0; r < NM; ++r) Uq[r] = Ut[r][hy][hx];
+      double Wp[NM], Wm[NM];
+      phys &= split_flux<2>(Uq, ax, alpha[ax], G.gam, Wp, Wm);
+#pragma unroll
+      for (int r = 0; r < NM; ++r) {
+        Wb[0][r][q] = Wp[r];
+        Wb[1][r][q] = Wm[r];
+      }
+    }
+    __syncthreads();
+    if (own) {
+#pragma unroll
+      for (int r = 0; r < NM; ++r) {
+        // cells l-2 .. l+2 along ax: x -> entries ly*EH + lx + k, y -> (ly + k)*ET + lx
+        double wp[5], wm[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const int e = ax == 0 ? ly * EH + lx + k : (ly + k) * ET + lx;
+          wp[k] = Wb[0][r][e];
+          wm[k] = Wb[1][r][e];
+        }
+        const double spl = vl_slope(wp[1] - wp[0], wp[2] - wp[1], a.unlimited);
+        const double sml = vl_slope(wm[2] - wm[1], wm[3] - wm[2], a.unlimited);
+        const double spr = vl_slope(wp[2] - wp[1], wp[3] - wp[2], a.unlimited);
+        const double smr = vl_slope(wm[3] - wm[2], wm[4] - wm[3], a.unlimited);
+        const double psil = 0.5 * (wp[1] + wm[2]) + 0.25 * (spl - sml);
+        const double psir = 0.5 * (wp[2] + wm[3]) + 0.25 * (spr - smr);
+        div[r] += psir - psil;
       }
     }
   }
-  __syncthreads();
-  const int lx = t % ET, ly = t / ET;
-  const int gx = X0 + lx, gy = Y0 + ly;
   double mx[2] = {0.0, 0.0};
-  if (gx < Nx && gy < Ny) {
-    double div[NM];
-#pragma unroll
-    for (int r = 0; r < NM; ++r) {
-      // along x: cells lx-2 .. lx+2 are entries lx .. lx+4 of row ly
-      const double* wp = &Wx[0][r][ly][lx];
-      const double* wm = &Wx[1][r][ly][lx];
-      double spl = vl_slope(wp[1] - wp[0], wp[2] - wp[1], a.unlimited);
-      double sml = vl_slope(wm[2] - wm[1], wm[3] - wm[2], a.unlimited);
-      double spr = vl_slope(wp[2] - wp[1], wp[3] - wp[2], a.unlimited);
-      double smr = vl_slope(wm[3] - wm[2], wm[4] - wm[3], a.unlimited);
-      double psil = 0.5 * (wp[1] + wm[2]) + 0.25 * (spl - sml);
-      double psir = 0.5 * (wp[2] + wm[3]) + 0.25 * (spr - smr);
-      div[r] = psir - psil;
-      // along y: cells ly-2 .. ly+2 are rows ly .. ly+4 of column lx
-      double yp[5], ym[5];
-#pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        yp[k] = Wy[0][r][ly + k][lx];
-        ym[k] = Wy[1][r][ly + k][lx];
-      }
-      spl = vl_slope(yp[1] - yp[0], yp[2] - yp[1], a.unlimited);
-      sml = vl_slope(ym[2] - ym[1], ym[3] - ym[2], a.unlimited);
-      spr = vl_slope(yp[2] - yp[1], yp[3] - yp[2], a.unlimited);
-      smr = vl_slope(ym[3] - ym[2], ym[4] - ym[3], a.unlimited);
-      psil = 0.5 * (yp[1] + ym[2]) + 0.25 * (spl - sml);
-      psir = 0.5 * (yp[2] + ym[3]) + 0.25 * (spr - smr);
-      div[r] += psir - psil;
-    }
+  if (own) {
     double Un[NM];
 #pragma unroll
     for (int r = 0; r < NM; ++r) Un[r] = Ut[r][ly + 2][lx + 2] - dts_dx * div[r];

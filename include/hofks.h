@@ -157,7 +157,8 @@ hofks_status hofks_batch_tube_flags(hofks_ctx *ctx, int *flags);
  * the current state, which is advanced (set the state again afterwards), and
  * keeps the fastest:
  *   single grid: wavefronts per kinetic block and piece loads issued ahead,
- *                choice = (wavefronts, loads);
+ *                choice = (wavefronts, loads); 3D grids use blocks of four
+ *                y rows (four wavefronts) and tune the loads only;
  *   batch:       cells per kinetic item and persistent grid size,
  *                choice = (cells, blocks).
  * cache_path (may be NULL) is a JSON-lines file of earlier choices keyed by

@@ -25,6 +25,7 @@
 #include "closure.hpp"
 #include "euler2d.hpp"
 #include "kernels.hpp"
+#include "kinetic3d.hpp"
 #include "mlp.hpp"
 
 using namespace hofks;
@@ -261,6 +262,7 @@ struct hofks_ctx {
   long steps;
   bool ready;
   int kng, kunr;  // kinetic kernel: wavefronts per block, loads issued ahead
+  int kring;      // 3D steps with an Euler solve: k_kinetic3 (blocks of RY rows)
   // optional per-kernel timing: hipEvents around each launch group
   bool timing;
   std::vector<hipEvent_t> ev_pool;
@@ -361,10 +363,45 @@ int kin_unroll(const Plan& P, int ng, int unr) {
   return (even && per % unr == 0) ? unr : 1;
 }
 
+// 3D steps with an Euler solve: blocks of RY y rows sharing a ring of
+// staged upstream rows (k_kinetic3)
+#ifndef HOFKS_KRING
+#define HOFKS_KRING 1
+#endif
+size_t kin3_lds(const Plan& P) {
+  const int fc = P.tsize == 4 ? fold3_chunks<float>() : fold3_chunks<double>();
+  return (size_t)(RY + 1) * (64 + P.G.nv1 - 1) * fc * 16;
+}
+
+template <typename T>
+void dispatch_kin3(hofks_ctx* c, const StepArgs<T>& a) {
+  constexpr bool CP = sizeof(T) == 4;
+  const Plan& P = c->P;
+  const int nyb = (P.G.n[1] + RY - 1) / RY;
+  const dim3 grid((unsigned)((long)P.nseg * nyb * P.G.n[2]));
+  const size_t lds = kin3_lds(P);
+  const int nv = P.G.nv1;
+  const int unr = nv % c->kunr == 0 ? c->kunr : nv % 12 == 0 ? 12 : nv % 8 == 0 ? 8 : 1;
+#define K(BCX, U)                                                                 \
+  hipLaunchKernelGGL((k_kinetic3<T, CP, BCX, U>), grid, dim3(64 * RY), lds, c->stream, a, \
+                     P.G, nyb)
+#define KB(U) \
+  if (P.G.bc[0] == 0) K(0, U); else K(1, U);
+  if (unr == 16) { KB(16) } else if (unr == 12) { KB(12) } else if (unr == 8) { KB(8) } else { KB(1) }
+#undef KB
+#undef K
+}
+
 template <int D, typename T, bool FT, bool EUL>
 void dispatch_kin(hofks_ctx* c, const StepArgs<T>& a, dim3 grid) {
   constexpr bool CP = sizeof(T) == 4;  // compensated sums in the FP32 form
   const Plan& P = c->P;
+  if constexpr (D == 3 && EUL && !FT) {
+    if (c->kring) {
+      dispatch_kin3<T>(c, a);
+      return;
+    }
+  }
   const int bcx = P.G.bc[0];
   int ng = c->kng, unr = kin_unroll(P, c->kng, c->kunr);
   if (FT || !EUL) {  // free transport and FKS steps: one configuration
@@ -768,6 +805,7 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
   c->kng = (P.d == 2 && !P.prec) ? 2 : 4;
   c->kunr = P.d >= 2 ? 16 : 8;
   if (kin_lds(P, c->kng) > 65536) c->kng = 2;
+  c->kring = HOFKS_KRING && P.d == 3 && kin3_lds(P) <= 65536;
   // velocity node table of one axis (the lattice, used by every kernel)
   std::vector<VelNode> tab(P.G.nv1);
   for (int i = 0; i < P.G.nv1; ++i) {
@@ -1501,6 +1539,7 @@ hofks_status grid_autotune(hofks_ctx* c, int steps, const char* cache_path, int*
     const int cand[6][2] = {{4, 8}, {2, 16}, {4, 16}, {2, 8}, {8, 16}, {8, 8}};
     for (const auto& cd : cand) {
       if (kin_lds(P, cd[0]) > 65536 || (cd[0] == 8 && P.d < 2)) continue;
+      if (c->kring && cd[0] != RY) continue;  // 3D: blocks of RY rows, only the unroll varies
       c->kng = cd[0];
       c->kunr = cd[1];
       hofks_status st = hofks_step(c, 1);

@@ -114,6 +114,28 @@ def test_3d_fp64():
 
 
 @gpu
+@pytest.mark.parametrize("n,nv,bc,tau,prec", [
+    ((70, 10, 6), 10, (1, 1, 1), 5e-3, 0),   # two x segments, ragged y blocks, outflow
+    ((40, 7, 9), 16, (0, 0, 1), 1e-2, 0),    # periodic y shorter than the largest shift
+    ((30, 5, 4), 24, (0, 1, 0), 2e-3, 0),    # the 24-node lattice of the 3D workload
+    ((66, 9, 5), 16, (1, 0, 0), 1e-3, 1),    # FP32 form, ragged x and y
+])
+def test_3d_row_blocks(n, nv, bc, tau, prec):
+    """3D steps with an Euler solve (blocks of four y rows sharing staged
+    upstream rows): every block shape, ragged tail and boundary"""
+    announce("3d row blocks", n, nv, bc, tau, prec)
+    rng = np.random.default_rng(37)
+    nc = int(np.prod(n))
+    rho = 1.0 + 0.2 * rng.uniform(-1, 1, nc)
+    th = 1.0 + 0.2 * rng.uniform(-1, 1, nc)
+    u = 0.2 * rng.uniform(-1, 1, (3, nc))
+    o, s = run_pair(3, n, 1.0 / n[0], nv, 0.5, bc, tau, 3, (rho, u, th), precision=prec)
+    tol = TOL64 if prec == 0 else TOL32
+    assert moment_errors(s.read_moments(), o.U, 3).max() < tol
+    assert rel_inf(s.read_f(), o.f) < tol
+
+
+@gpu
 def test_gas2d_full_size_three_steps():
     """the 256^2 x 32^2 perturbed-gas workload at full size, 3 steps"""
     wl = W.GAS_2D

@@ -93,7 +93,8 @@ int fmt_err(char* buf, const char* f, ...) {
 // the partial sums of the extra wavefronts
 size_t kin_lds(const Plan& P, int ng) {
   const size_t sw = 64 + P.G.nv1 - 1;
-  const size_t stage = (P.d >= 2 ? ng : 1) * sw * P.RS * P.tsize;
+  const size_t fs = P.tsize == 8 ? row_rec_stride<double>() : row_rec_stride<float>();
+  const size_t stage = (P.d >= 2 ? ng : 1) * sw * fs * P.tsize;
   const size_t red = (size_t)(ng - 1) * 64 * 2 * P.nm * sizeof(double);
   return std::max(stage, red);
 }
@@ -810,7 +811,7 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
   std::vector<VelNode> tab(P.G.nv1);
   for (int i = 0; i < P.G.nv1; ++i) {
     const double v = (i - P.G.kofs) * P.G.dv;
-    tab[i] = VelNode{v, v * v, (float)v, (float)(0.5 * v * v), 0.0f, 0.0f};
+    tab[i] = VelNode{v, v * v, (float)v, (float)(0.5 * v * v), 0.5 * v * v};
   }
   if (reset_counters(c) != HOFKS_OK ||
       hipMemcpyAsync(c->vt, tab.data(), tab.size() * sizeof(VelNode), hipMemcpyHostToDevice,
@@ -1653,7 +1654,7 @@ hofks_status hofks_batch_create(const hofks_grid_desc* descs, const double* taus
   for (const TubeDev& T : B->tubes)
     for (int i = 0; i < T.nv1; ++i) {
       const double v = (i - T.kofs) * T.dv;
-      tab.push_back(VelNode{v, v * v, (float)v, (float)(0.5 * v * v), 0.0f, 0.0f});
+      tab.push_back(VelNode{v, v * v, (float)v, (float)(0.5 * v * v), 0.5 * v * v});
     }
   if (hipMemcpyAsync(B->vtar, tab.data(), sizeof(VelNode) * tab.size(), hipMemcpyHostToDevice,
                      c->stream) != hipSuccess ||

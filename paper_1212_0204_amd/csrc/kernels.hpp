@@ -196,7 +196,7 @@ struct Vec16<float> {
 struct VelNode {
   double v, v2;
   float vf, v2hf;  // (float)v, (float)(v^2 / 2)
-  float pad0, pad1;
+  double v2h;      // v^2 / 2
 };
 
 // bounded wait: gives up (and flags) after SPIN_CAP sleeps, or at once when
@@ -724,24 +724,82 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Record of one upstream cell as the piece loop reads it: the terms of the
+// transverse velocities (v_y, v_z: fixed over a velocity row) folded in,
+//   [a0, u_x, beta | P0, p_1, p_{d+1} | E0, e_1, e_{d+1}],
+//   log M = a0 - |beta| (v_x - u_x)^2,   p . m(v) = P0 + p_1 v_x + p_{d+1} v_x^2 / 2,
+// with a0 = lp - |beta| sum_{a>1} (v_a - u_a)^2 and
+// P0 = p_0 + sum_{a>1} p_a v_a + p_{d+1} sum_{a>1} v_a^2 / 2 (the same for e).
+// In 1D it is the record itself.  Nine values padded to an odd number of
+// 16-byte chunks.  A staged row segment holds its cells in reverse order, so
+// that the pieces of increasing k_x read increasing addresses (constant
+// offsets in the LDS reads).
+template <typename T>
+__host__ __device__ constexpr int row_rec_stride() {
+  return rec_stride<1, T>();
+}
+
+// read the nine values of a row record from LDS (16-byte chunks, the last
+// partial chunk as single values)
+template <typename T>
+__device__ __forceinline__ void read_row_rec(const T* p, T (&r)[9]) {
+  using V = typename Vec16<T>::type;
+  const V* q = reinterpret_cast<const V*>(p);
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const V t = q[c];
+      r[2 * c] = t.x;
+      r[2 * c + 1] = t.y;
+    }
+    r[8] = p[8];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const V t = q[c];
+      r[4 * c] = t.x;
+      r[4 * c + 1] = t.y;
+      r[4 * c + 2] = t.z;
+      r[4 * c + 3] = t.w;
+    }
+    r[8] = p[8];
+  }
+}
+
+// velocity node i through the scalar cache (the table is written only when
+// a context is created)
+__device__ __forceinline__ VelNode vel_node(const VelNode* vt, int i) {
+  using CVN = const __attribute__((address_space(4))) VelNode;
+  CVN* p = (CVN*)vt + i;
+  VelNode r;
+  r.v = p->v;
+  r.v2 = p->v2;
+  r.vf = p->vf;
+  r.v2hf = p->v2hf;
+  r.v2h = p->v2h;
+  return r;
+}
+
 // Kinetic kernel.  One block = 64 consecutive x cells of one row (one lane
 // per cell) and NG wavefronts, each taking 1/NG of the velocities (of the
-// velocity rows (k_y, k_z) in 2D/3D, of k_x in 1D).  Per
-// velocity row a wavefront stages the records of the upstream row segment in
-// its own LDS slice; its k_x loop issues UNR piece loads g(j - k, k) (coalesced
+// velocity rows (k_y, k_z) in 2D/3D, of k_x in 1D).  Per velocity row a
+// wavefront stages the row records of the upstream row segment in its own
+// LDS slice; its k_x loop issues UNR piece loads g(j - k, k) (coalesced
 // along x) before using them, relaxes each piece, writes it to cell j of the
-// new buffer and sums the moments of f* and of E.  The four partial sums are
-// combined in LDS and the first wavefront forms delta, U^{n+1}, cf and the
-// next record of its 64 cells; the Euler kernel of the step has finished.
-// (NG, UNR) is chosen per grid by the autotuner.
+// new buffer and sums the moments of f* and of E.  The partial sums are
+// combined in LDS and written for the per-cell update (k_cell_update; the
+// Euler solve runs on another stream meanwhile), or, for steps without an
+// Euler solve, the first wavefront forms U^{n+1}, cf and the next record of
+// its 64 cells.  (NG, UNR) is chosen per grid by the autotuner.
 template <int D, typename T, bool FT, bool COMP, int BCX, int UNR, bool EUL, int NG,
           bool CLOS = false>
 __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat A) {
   constexpr int NM = D + 2;
   constexpr int RS = rec_stride<D, T>();
   constexpr int PER16 = 16 / (int)sizeof(T);
-  constexpr int NCH = (rec_values<D, T>() + PER16 - 1) / PER16;  // chunks read per piece
+  constexpr int NCH = (rec_values<D, T>() + PER16 - 1) / PER16;  // chunks of a record
   constexpr int C16 = RS / PER16;
+  constexpr int FS = row_rec_stride<T>();
   using V = typename Vec16<T>::type;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
@@ -750,13 +808,15 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int seg = tile % a.nseg;
   const int row = tile / a.nseg;
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int Nx = G.n[0];
   const int x0 = seg * 64;
   const int x = x0 + lane;
   const bool active = x < Nx;
   const int jy = row % G.n[1], jz = row / G.n[1];
   const int dest = row * Nx + x;
+  const unsigned dboff = (unsigned)dest * (unsigned)sizeof(T);
   const int xN = x + Nx;
   const int lofs = G.nv1 - 1 - G.kofs;
   const int xlo = x0 - lofs;
@@ -771,7 +831,7 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
   const int vr1 = (D >= 2) ? (grp + 1) * nvr / NG : 1;
   const int ixa = (D >= 2) ? 0 : grp * G.nv1 / NG;
   const int ixb = (D >= 2) ? G.nv1 : (grp + 1) * G.nv1 / NG;
-  T* Lw = lds + (D >= 2 ? (size_t)grp * SW * RS : 0);
+  T* Lw = lds + (D >= 2 ? (size_t)grp * SW * FS : 0);
 
   double SK[NM], SE[NM], CK[NM], CE[NM];
 #pragma unroll
@@ -781,30 +841,70 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
     const int iy = (D >= 2) ? vr % G.nv1 : 0;
     const int iz = (D >= 3) ? vr / G.nv1 : 0;
     const int ky = iy - G.kofs, kz = iz - G.kofs;
-    const double vy = (D >= 2) ? a.vt[iy].v : 0.0;
-    const double vz = (D >= 3) ? a.vt[iz].v : 0.0;
-    const double hrow = (D >= 2 ? 0.5 * a.vt[iy].v2 : 0.0) + (D >= 3 ? 0.5 * a.vt[iz].v2 : 0.0);
+    const double vy = (D >= 2) ? vel_node(a.vt, iy).v : 0.0;
+    const double vz = (D >= 3) ? vel_node(a.vt, iz).v : 0.0;
+    const double hrow = (D >= 2 ? 0.5 * vel_node(a.vt, iy).v2 : 0.0) +
+                        (D >= 3 ? 0.5 * vel_node(a.vt, iz).v2 : 0.0);
     const int uy = (D >= 2) ? map_axis(jy - ky, G.n[1], G.bc[1]) : 0;
     const int uz = (D >= 3) ? map_axis(jz - kz, G.n[2], G.bc[2]) : 0;
     const int ubase = (uz * G.n[1] + uy) * Nx;
 
-    // stage the records of the upstream row segment (16-byte chunks)
+    // stage the row records of the upstream row segment
     {
-      V* ldsv = reinterpret_cast<V*>(Lw);
       const V* recv = reinterpret_cast<const V*>(a.rec_in);
       if (D >= 2) {
+        const T vyT = (T)vy, vzT = (T)vz, hT = (T)hrow;
         wave_lds_sync();
-        for (int idx = lane; idx < SW * C16; idx += 64) {
-          const int c = idx % C16, i = idx / C16;
-          const int ux = map_axis(xlo + i, Nx, G.bc[0]);
-          ldsv[idx] = recv[(size_t)(ubase + ux) * C16 + c];
+        for (int i = lane; i < SW; i += 64) {
+          const V* src = recv + (size_t)(ubase + map_axis(xlo + i, Nx, G.bc[0])) * C16;
+          T rv[NCH * PER16];
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            const V t = src[c];
+            if constexpr (sizeof(T) == 8) {
+              rv[2 * c] = t.x;
+              rv[2 * c + 1] = t.y;
+            } else {
+              rv[4 * c] = t.x;
+              rv[4 * c + 1] = t.y;
+              rv[4 * c + 2] = t.z;
+              rv[4 * c + 3] = t.w;
+            }
+          }
+          // record: [lp, u_1..u_D, beta | p_0..p_{D+1} | e_0..e_{D+1}]
+          const T beta = rv[D + 1];
+          const T bq = CLOS ? fabs(beta) : beta;
+          T q = (vyT - rv[2]) * (vyT - rv[2]);
+          T P0 = rv[NM] + rv[NM + 2] * vyT;
+          T E0 = rv[2 * NM] + rv[2 * NM + 2] * vyT;
+          if (D >= 3) {
+            q += (vzT - rv[3]) * (vzT - rv[3]);
+            P0 += rv[NM + 3] * vzT;
+            E0 += rv[2 * NM + 3] * vzT;
+          }
+          P0 += rv[2 * NM - 1] * hT;
+          E0 += rv[3 * NM - 1] * hT;
+          T* o = Lw + (size_t)(SW - 1 - i) * FS;
+          const T f[9] = {rv[0] - bq * q, rv[1], beta, P0, rv[NM + 1], rv[2 * NM - 1],
+                          E0, rv[2 * NM + 1], rv[3 * NM - 1]};
+          if constexpr (sizeof(T) == 8) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) reinterpret_cast<V*>(o)[c] = V{f[2 * c], f[2 * c + 1]};
+          } else {
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+              reinterpret_cast<V*>(o)[c] = V{f[4 * c], f[4 * c + 1], f[4 * c + 2], f[4 * c + 3]};
+          }
+          o[8] = f[8];
         }
         wave_lds_sync();
       } else {
+        // 1D: the record is the row record
+        V* ldsv = reinterpret_cast<V*>(Lw);
         for (int idx = threadIdx.x; idx < SW * C16; idx += blockDim.x) {
           const int c = idx % C16, i = idx / C16;
           const int ux = map_axis(xlo + i, Nx, G.bc[0]);
-          ldsv[idx] = recv[(size_t)ux * C16 + c];
+          ldsv[(SW - 1 - i) * C16 + c] = recv[(size_t)ux * C16 + c];
         }
         __syncthreads();
       }
@@ -812,29 +912,26 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
     if (!active) continue;
 
     const size_t kbase = (size_t)vr * G.nv1;
-    const T vyT = (T)vy, vzT = (T)vz;
-    const T hrowT = (T)hrow;
     double aK0 = 0.0, aK1 = 0.0, aK2 = 0.0, aE0 = 0.0, aE1 = 0.0, aE2 = 0.0;
 
     if constexpr (CLOS) {
       if (!tile_kin) {
         // closure tile: every piece is the equilibrium of its upstream cell,
-        // so only E is evaluated (record chunks without p) and summed once;
-        // the sums of f* equal those of E
+        // so only E is evaluated and summed once; the sums of f* equal those
+        // of E
         for (int ix = ixa; ix < ixb; ++ix) {
           const int kx = ix - G.kofs;
-          const VelNode vn = a.vt[ix];
+          const VelNode vn = vel_node(a.vt, ix);
           const T vxT = (sizeof(T) == 4) ? (T)vn.vf : (T)vn.v;
-          const T vhT = (sizeof(T) == 4) ? (T)(hrowT + (T)vn.v2hf) : (T)(hrow + 0.5 * vn.v2);
-          // record: [lp, u_x, u_y, beta | p_0..p_3 | e_0..e_3]
-          const T* rr = Lw + (lane - kx + lofs) * RS;
-          const T dx_ = vxT - rr[1], dy_ = vyT - rr[2];
-          const T M = fast_exp<T>(rr[0] - fabs(rr[3]) * (dx_ * dx_ + dy_ * dy_));
-          const T E = M + (rr[8] + rr[9] * vxT + rr[10] * vyT + rr[11] * vhT);
+          const T vhT = (sizeof(T) == 4) ? (T)vn.v2hf : (T)vn.v2h;
+          const T* rr = Lw + (SW - 1 - lane + kx - lofs) * FS;
+          const T dx_ = vxT - rr[1];
+          const T M = fast_exp<T>(rr[0] - fabs(rr[2]) * (dx_ * dx_));
+          const T E = M + (rr[6] + rr[7] * vxT + rr[8] * vhT);
           const double Ed = (double)E;
           aE0 += Ed;
           aE1 += vn.v * Ed;
-          aE2 += vn.v2 * Ed;
+          aE2 += vn.v2h * Ed;
         }
         aK0 = aE0;
         aK1 = aE1;
@@ -848,83 +945,60 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
       for (int u = 0; u < UNR; ++u) {
         const int ix = ix0 + u;
         const int kx = ix - G.kofs;
-        const T* gp = a.g_in + (kbase + ix) * (size_t)G.nc;
+        // plane base (uniform) + 32-bit byte offset of the upstream cell
+        const char* gp = reinterpret_cast<const char*>(a.g_in + (kbase + ix) * (size_t)G.nc);
+        const T* src = reinterpret_cast<const T*>(
+            gp + (unsigned)(ubase + map_x<BCX>(xN, kx, Nx)) * (unsigned)sizeof(T));
         if (CLOS && !tile_kin)
           gv[u] = (T)0;
         else if (HOFKS_NT)
-          gv[u] = __builtin_nontemporal_load(gp + ubase + map_x<BCX>(xN, kx, Nx));
+          gv[u] = __builtin_nontemporal_load(src);
         else
-          gv[u] = gp[ubase + map_x<BCX>(xN, kx, Nx)];
+          gv[u] = *src;
       }
+      // row records of the pieces of this group: cell lane - kx + lofs, at
+      // position SW - 1 - lane + kx - lofs, for kx = ix0 + u - kofs
+      const T* Lb = Lw + (SW - 1 - lane - lofs - G.kofs + ix0) * FS;
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const int ix = ix0 + u;
-        const int kx = ix - G.kofs;
-        const VelNode vn = a.vt[ix];
+        const VelNode vn = vel_node(a.vt, ix);
         const double vx = vn.v;
         const T vxT = (sizeof(T) == 4) ? (T)vn.vf : (T)vn.v;
-        const T vhT = (sizeof(T) == 4) ? (T)(hrowT + (T)vn.v2hf) : (T)(hrow + 0.5 * vn.v2);
-        const V* rp = reinterpret_cast<const V*>(Lw + (lane - kx + lofs) * RS);
-        T rv[NCH * PER16];
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          const V t = rp[c];
-          if constexpr (sizeof(T) == 8) {
-            rv[2 * c] = t.x;
-            rv[2 * c + 1] = t.y;
-          } else {
-            rv[4 * c] = t.x;
-            rv[4 * c + 1] = t.y;
-            rv[4 * c + 2] = t.z;
-            rv[4 * c + 3] = t.w;
-          }
-        }
-        // record: [lp, u_1..u_D, beta | p_0..p_{D+1} | e_0..e_{D+1}]
-        T pp = rv[NM + 0] + rv[NM + 1] * vxT;
-        if (D >= 2) pp += rv[NM + 2] * vyT;
-        if (D >= 3) pp += rv[NM + 3] * vzT;
-        pp += rv[2 * NM - 1] * vhT;
+        const T vhT = (sizeof(T) == 4) ? (T)vn.v2hf : (T)vn.v2h;
+        T rv[9];
+        read_row_rec<T>(Lb + u * FS, rv);
+        // row record: [a0, u_x, beta | P0, p_1, p_{d+1} | E0, e_1, e_{d+1}]
+        const T pp = rv[3] + rv[4] * vxT + rv[5] * vhT;
         const T g = gv[u];
         T fs;
         if (FT) {
           fs = g + pp;
         } else {
           const T dx_ = vxT - rv[1];
-          T q = dx_ * dx_;
-          if (D >= 2) {
-            const T dy_ = vyT - rv[2];
-            q += dy_ * dy_;
-          }
-          if (D >= 3) {
-            const T dz_ = vzT - rv[3];
-            q += dz_ * dz_;
-          }
-          const T M = fast_exp<T>(rv[0] - (CLOS ? fabs(rv[D + 1]) : rv[D + 1]) * q);
-          T pe = rv[2 * NM + 0] + rv[2 * NM + 1] * vxT;
-          if (D >= 2) pe += rv[2 * NM + 2] * vyT;
-          if (D >= 3) pe += rv[2 * NM + 3] * vzT;
-          pe += rv[3 * NM - 1] * vhT;
-          const T E = M + pe;
+          const T M = fast_exp<T>(rv[0] - (CLOS ? fabs(rv[2]) : rv[2]) * (dx_ * dx_));
+          const T E = M + (rv[6] + rv[7] * vxT + rv[8] * vhT);
           fs = lam * g + (mu * M + pp);
           // closure form: closure cells, and upstream cells without pieces,
           // take the equilibrium
-          if (CLOS) fs = (kin && rv[D + 1] > (T)0) ? fs : E;
+          if (CLOS) fs = (kin && rv[2] > (T)0) ? fs : E;
           const double Ed = (double)E;
           aE0 += Ed;
           aE1 += vx * Ed;
-          aE2 += vn.v2 * Ed;
+          aE2 += vn.v2h * Ed;
         }
-        T* op = a.g_out + (kbase + ix) * (size_t)G.nc;
+        T* op = reinterpret_cast<T*>(reinterpret_cast<char*>(a.g_out + (kbase + ix) * (size_t)G.nc) +
+                                     dboff);
         if (CLOS && !kin) {
         } else if (HOFKS_NT) {
-          __builtin_nontemporal_store(fs, op + dest);
+          __builtin_nontemporal_store(fs, op);
         } else {
-          op[dest] = fs;
+          *op = fs;
         }
         const double fd = (double)fs;
         aK0 += fd;
         aK1 += vx * fd;
-        aK2 += vn.v2 * fd;
+        aK2 += vn.v2h * fd;
       }
     }
   row_done:
@@ -942,8 +1016,8 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
       rk[3] = vz * aK0;
       re[3] = vz * aE0;
     }
-    rk[NM - 1] = 0.5 * aK2 + hrow * aK0;
-    re[NM - 1] = 0.5 * aE2 + hrow * aE0;
+    rk[NM - 1] = aK2 + hrow * aK0;
+    re[NM - 1] = aE2 + hrow * aE0;
 #pragma unroll
     for (int r = 0; r < NM; ++r) {
       if (COMP) {

@@ -46,11 +46,13 @@ __global__ __launch_bounds__(64 * RY) void k_kinetic3(StepArgs<T> a, Geom G, int
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int seg = tile % nseg;
   const int yb = (tile / nseg) % nyb, z = tile / nseg / nyb;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int Nx = G.n[0], Ny = G.n[1], Nz = G.n[2];
   const int x0 = seg * 64, x = x0 + lane, y = yb * RY + w;
   const bool active = x < Nx && y < Ny;
   const int dest = (z * Ny + (y < Ny ? y : Ny - 1)) * Nx + x;
+  const unsigned dboff = (unsigned)dest * (unsigned)sizeof(T);
   const int xN = x + Nx;
   const int lofs = G.nv1 - 1 - G.kofs;
   const int xlo = x0 - lofs;
@@ -59,7 +61,8 @@ __global__ __launch_bounds__(64 * RY) void k_kinetic3(StepArgs<T> a, Geom G, int
   const int nslot = RY + 1;
 
   // stage the folded records of upstream row r (unwrapped) at plane uz into
-  // its slot, one record per thread
+  // its slot, one record per thread, cells in reverse order (the pieces of
+  // increasing k_x then read increasing addresses)
   auto stage = [&](int r, int uz, T vzT, T vz2hT) {
     const int slot = ((r % nslot) + nslot) % nslot;
     V* dst = reinterpret_cast<V*>(lds + (size_t)slot * SW * FS);
@@ -108,7 +111,7 @@ __global__ __launch_bounds__(64 * RY) void k_kinetic3(StepArgs<T> a, Geom G, int
           t.z = o[4 * c + 2];
           t.w = o[4 * c + 3];
         }
-        dst[(size_t)i * FC + c] = t;
+        dst[(size_t)(SW - 1 - i) * FC + c] = t;
       }
     }
   };
@@ -120,8 +123,8 @@ __global__ __launch_bounds__(64 * RY) void k_kinetic3(StepArgs<T> a, Geom G, int
   for (int iz = 0; iz < G.nv1; ++iz) {
     const int kz = iz - G.kofs;
     const int uz = map_axis(z - kz, Nz, G.bc[2]);
-    const double vz = a.vt[iz].v;
-    const T vzT = (T)vz, vz2hT = (T)(0.5 * a.vt[iz].v2);
+    const double vz = vel_node(a.vt, iz).v;
+    const T vzT = (T)vz, vz2hT = (T)vel_node(a.vt, iz).v2h;
     // rows of the first k_y step: yb RY - ky .. + RY - 1 with ky = -kofs
     __syncthreads();  // the previous k_z's slots are no longer read
     for (int q = 0; q < RY; ++q) stage(yb * RY + G.kofs + q, uz, vzT, vz2hT);
@@ -135,10 +138,10 @@ __global__ __launch_bounds__(64 * RY) void k_kinetic3(StepArgs<T> a, Geom G, int
       const T* Lw = lds + (size_t)slot * SW * FS;
       const int uy = map_axis(r, Ny, G.bc[1]);
       const int ubase = (uz * Ny + uy) * Nx;
-      const double vy = a.vt[iy].v;
-      const double hrow = 0.5 * a.vt[iy].v2 + 0.5 * a.vt[iz].v2;
+      const double vy = vel_node(a.vt, iy).v;
+      const double hrow = vel_node(a.vt, iy).v2h + vel_node(a.vt, iz).v2h;
       const size_t kbase = ((size_t)iz * G.nv1 + iy) * G.nv1;
-      const T vyT = (T)vy, vy2hT = (T)(0.5 * a.vt[iy].v2);
+      const T vyT = (T)vy, vy2hT = (T)vel_node(a.vt, iy).v2h;
       double aK0 = 0.0, aK1 = 0.0, aK2 = 0.0, aE0 = 0.0, aE1 = 0.0, aE2 = 0.0;
       if (active) {
 #pragma unroll 1
@@ -147,21 +150,20 @@ __global__ __launch_bounds__(64 * RY) void k_kinetic3(StepArgs<T> a, Geom G, int
 #pragma unroll
           for (int u = 0; u < UNR; ++u) {
             const int ix = ix0 + u;
-            const T* gp = a.g_in + (kbase + ix) * (size_t)G.nc;
-            if (HOFKS_NT)
-              gv[u] = __builtin_nontemporal_load(gp + ubase + map_x<BCX>(xN, ix - G.kofs, Nx));
-            else
-              gv[u] = gp[ubase + map_x<BCX>(xN, ix - G.kofs, Nx)];
+            const char* gp = reinterpret_cast<const char*>(a.g_in + (kbase + ix) * (size_t)G.nc);
+            const T* src = reinterpret_cast<const T*>(
+                gp + (unsigned)(ubase + map_x<BCX>(xN, ix - G.kofs, Nx)) * (unsigned)sizeof(T));
+            gv[u] = HOFKS_NT ? __builtin_nontemporal_load(src) : *src;
           }
+          const T* Lb = Lw + (SW - 1 - lane - lofs - G.kofs + ix0) * FS;
 #pragma unroll
           for (int u = 0; u < UNR; ++u) {
             const int ix = ix0 + u;
-            const int kx = ix - G.kofs;
-            const VelNode vn = a.vt[ix];
+            const VelNode vn = vel_node(a.vt, ix);
             const double vx = vn.v;
             const T vxT = (sizeof(T) == 4) ? (T)vn.vf : (T)vn.v;
-            const T vhT = (sizeof(T) == 4) ? (T)(vy2hT + (T)vn.v2hf) : (T)(vy2hT + 0.5 * vn.v2);
-            const V* rp = reinterpret_cast<const V*>(Lw + (lane - kx + lofs) * FS);
+            const T vhT = (sizeof(T) == 4) ? (T)(vy2hT + (T)vn.v2hf) : (T)(vy2hT + vn.v2h);
+            const V* rp = reinterpret_cast<const V*>(Lb + u * FS);
             T rv[12];
 #pragma unroll
             for (int c = 0; c < NF; ++c) {
@@ -183,23 +185,24 @@ __global__ __launch_bounds__(64 * RY) void k_kinetic3(StepArgs<T> a, Geom G, int
             const T pe = rv[8] + rv[9] * vxT + rv[10] * vyT + rv[11] * vhT;
             const T E = M + pe;
             const T fs = lam * gv[u] + (mu * M + pp);
-            T* op = a.g_out + (kbase + ix) * (size_t)G.nc;
+            T* op = reinterpret_cast<T*>(
+                reinterpret_cast<char*>(a.g_out + (kbase + ix) * (size_t)G.nc) + dboff);
             if (HOFKS_NT)
-              __builtin_nontemporal_store(fs, op + dest);
+              __builtin_nontemporal_store(fs, op);
             else
-              op[dest] = fs;
+              *op = fs;
             const double fd = (double)fs, Ed = (double)E;
             aK0 += fd;
             aK1 += vx * fd;
-            aK2 += vn.v2 * fd;
+            aK2 += vn.v2h * fd;
             aE0 += Ed;
             aE1 += vx * Ed;
-            aE2 += vn.v2 * Ed;
+            aE2 += vn.v2h * Ed;
           }
         }
         // fold the row: m = (1, v_x, v_y, v_z, |v|^2/2)
-        const double rk[NM] = {aK0, aK1, vy * aK0, vz * aK0, 0.5 * aK2 + hrow * aK0};
-        const double re[NM] = {aE0, aE1, vy * aE0, vz * aE0, 0.5 * aE2 + hrow * aE0};
+        const double rk[NM] = {aK0, aK1, vy * aK0, vz * aK0, aK2 + hrow * aK0};
+        const double re[NM] = {aE0, aE1, vy * aE0, vz * aE0, aE2 + hrow * aE0};
 #pragma unroll
         for (int q = 0; q < NM; ++q) {
           if (COMP) {

@@ -306,7 +306,7 @@ __device__ void batch_update_item(const BatchArgs& a, int it) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) A.a[q] = T.A[q];
     float* recout = a.rar + (p ? T.rec[0] : T.rec[1]);
-    phys = cell_record<1, float>(Un, cfv, G, A, a.vtar + T.vt, recout + (size_t)x * RS, &speed);
+    phys = cell_record<1, float>(Un, cfv, G, A, recout + (size_t)x * RS, &speed);
     double* Uo = a.dar + (p ? T.U[0] : T.U[1]);
     double* cf = a.dar + T.cf;
 #pragma unroll

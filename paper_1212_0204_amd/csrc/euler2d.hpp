@@ -21,6 +21,34 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_euler_sub_tile(StepArgs<T> a, Geom G, int i, int ntx) {
   constexpr int NM = 4;
   double* S = a.set_r;
+  const int Nx = G.n[0], Ny = G.n[1];
+  const int X0 = (int)(blockIdx.x % ntx) * ET, Y0 = (int)(blockIdx.x / ntx) * ET;
+  const int t = threadIdx.x;
+  const double* in = (i == 0) ? a.U_in : ((i & 1) ? a.UE1 : a.UE0);
+  double* out = ((i + 1) & 1) ? a.UE1 : a.UE0;
+
+  __shared__ double Ut[NM][EH][EH];
+  // split fluxes along one axis at a time (x, then y) in one buffer:
+  // x: [+/-][r][y][x + 2] over 16 x 20 cells; y: [+/-][r][y + 2][x] over 20 x 16
+  __shared__ double Wb[2][NM][ET * EH];
+
+  // tile + halo (periodic wrap or outflow clamp, as the per-cell form),
+  // loaded before the speeds of the sub-step are read so that the two
+  // memory round trips overlap (both buffers exist whatever s is)
+  constexpr int NQ = (EH * EH + 255) / 256;
+  double Uload[NQ][NM];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = t + k * 256;
+    if (q < EH * EH) {
+      const int hx = q % EH, hy = q / EH;
+      const int gx = map_axis(X0 + hx - 2, Nx, G.bc[0]);
+      const int gy = map_axis(Y0 + hy - 2, Ny, G.bc[1]);
+      const size_t j = (size_t)gy * Nx + gx;
+#pragma unroll
+      for (int r = 0; r < NM; ++r) Uload[k][r] = in[(size_t)r * G.nc + j];
+    }
+  }
   bool over;
   const int s = substeps<2>(S, G, a.s_cap, &over);
   if (i == 0) {
@@ -35,25 +63,13 @@ __global__ __launch_bounds__(256) void k_euler_sub_tile(StepArgs<T> a, Geom G, i
   double alpha[3];
   row_speeds<2>(S, i, alpha);
   const double dts_dx = (G.dt / s) / G.dx;
-  const double* in = (i == 0) ? a.U_in : ((i & 1) ? a.UE1 : a.UE0);
-  double* out = ((i + 1) & 1) ? a.UE1 : a.UE0;
-  const int Nx = G.n[0], Ny = G.n[1];
-  const int X0 = (int)(blockIdx.x % ntx) * ET, Y0 = (int)(blockIdx.x / ntx) * ET;
-  const int t = threadIdx.x;
-
-  __shared__ double Ut[NM][EH][EH];
-  // split fluxes along one axis at a time (x, then y) in one buffer:
-  // x: [+/-][r][y][x + 2] over 16 x 20 cells; y: [+/-][r][y + 2][x] over 20 x 16
-  __shared__ double Wb[2][NM][ET * EH];
-
-  // tile + halo (periodic wrap or outflow clamp, as the per-cell form)
-  for (int q = t; q < EH * EH; q += blockDim.x) {
-    const int hx = q % EH, hy = q / EH;
-    const int gx = map_axis(X0 + hx - 2, Nx, G.bc[0]);
-    const int gy = map_axis(Y0 + hy - 2, Ny, G.bc[1]);
-    const size_t j = (size_t)gy * Nx + gx;
 #pragma unroll
-    for (int r = 0; r < NM; ++r) Ut[r][hy][hx] = in[(size_t)r * G.nc + j];
+  for (int k = 0; k < NQ; ++k) {
+    const int q = t + k * 256;
+    if (q < EH * EH) {
+#pragma unroll
+      for (int r = 0; r < NM; ++r) Ut[r][q / EH][q % EH] = Uload[k][r];
+    }
   }
   __syncthreads();
   bool phys = true;

@@ -349,8 +349,7 @@ __device__ __forceinline__ bool euler_cell(const double* __restrict__ in, int j,
 // record; speeds |u_a| + c for the next Euler solve.  Returns physicality.
 template <int D, typename T>
 __device__ __forceinline__ bool cell_record(const double* Un, const double* cfv, const Geom& G,
-                                            const Mat& A, const VelNode* __restrict__ vt,
-                                            T* __restrict__ rec_j, double* speed,
+                                            const Mat& A, T* __restrict__ rec_j, double* speed,
                                             bool valid = true) {
   constexpr int NM = D + 2;
   const double rho = Un[0];
@@ -376,21 +375,23 @@ __device__ __forceinline__ bool cell_record(const double* Un, const double* cfv,
     // that itself changes by the constant factor exp(-2 beta dv^2); both are
     // recomputed every 16 nodes so that rounding stays within ~16 ulp.
     // Values only decrease away from the peak, so an underflow to zero is
-    // where the true value is below the FP64 range.
+    // where the true value is below the FP64 range.  Nodes v_i = (i - kofs) dv
+    // are formed in place (the same rounding as the node table).
     double G0[3], G1[3], G2[3];
     const double dv = G.dv;
+    auto vnode = [&](int i) { return (double)(i - G.kofs) * dv; };
     const double qf = exp(-2.0 * beta * dv * dv);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       int ip = (int)rint(u[a] / dv) + G.kofs;
       ip = ip < 0 ? 0 : (ip >= G.nv1 ? G.nv1 - 1 : ip);
-      const double dp = vt[ip].v - u[a];
+      const double dp = vnode(ip) - u[a];
       const double ep = exp(-beta * dp * dp);
-      double s0 = ep, s1 = vt[ip].v * ep, s2 = vt[ip].v2 * ep;
+      double s0 = ep, s1 = vnode(ip) * ep, s2 = (vnode(ip) * vnode(ip)) * ep;
       double e = ep, r = exp(-beta * (2.0 * dp * dv + dv * dv));
       for (int i = ip + 1; i < G.nv1; ++i) {
         if (((i - ip) & 15) == 0) {
-          const double d = vt[i].v - u[a];
+          const double d = vnode(i) - u[a];
           e = exp(-beta * d * d);
           r = exp(-beta * (2.0 * d * dv + dv * dv));
         } else {
@@ -398,14 +399,14 @@ __device__ __forceinline__ bool cell_record(const double* Un, const double* cfv,
           r *= qf;
         }
         s0 += e;
-        s1 += vt[i].v * e;
-        s2 += vt[i].v2 * e;
+        s1 += vnode(i) * e;
+        s2 += (vnode(i) * vnode(i)) * e;
       }
       e = ep;
       r = exp(-beta * (dv * dv - 2.0 * dp * dv));
       for (int i = ip - 1; i >= 0; --i) {
         if (((ip - i) & 15) == 0) {
-          const double d = vt[i].v - u[a];
+          const double d = vnode(i) - u[a];
           e = exp(-beta * d * d);
           r = exp(-beta * (dv * dv - 2.0 * d * dv));
         } else {
@@ -413,8 +414,8 @@ __device__ __forceinline__ bool cell_record(const double* Un, const double* cfv,
           r *= qf;
         }
         s0 += e;
-        s1 += vt[i].v * e;
-        s2 += vt[i].v2 * e;
+        s1 += vnode(i) * e;
+        s2 += (vnode(i) * vnode(i)) * e;
       }
       G0[a] = s0;
       G1[a] = s1;
@@ -1108,7 +1109,7 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
       for (int s2 = 0; s2 < NM; ++s2) acc += A.a[r * NM + s2] * delta[s2];
       cfv[r] = acc;
     }
-    phys = cell_record<D, T>(Un, cfv, G, A, a.vt, a.rec_out + (size_t)dest * RS, speed, kin);
+    phys = cell_record<D, T>(Un, cfv, G, A, a.rec_out + (size_t)dest * RS, speed, kin);
 #pragma unroll
     for (int r = 0; r < NM; ++r) {
       a.U_out[(size_t)r * G.nc + dest] = Un[r];
@@ -1170,7 +1171,7 @@ __global__ __launch_bounds__(256) void k_cell_update(StepArgs<T> a, Geom G, Mat 
       for (int s2 = 0; s2 < NM; ++s2) acc += A.a[r * NM + s2] * delta[s2];
       cfv[r] = acc;
     }
-    phys = cell_record<D, T>(Un, cfv, G, A, a.vt, a.rec_out + (size_t)j * RS, speed, kin);
+    phys = cell_record<D, T>(Un, cfv, G, A, a.rec_out + (size_t)j * RS, speed, kin);
 #pragma unroll
     for (int r = 0; r < NM; ++r) {
       a.U_out[(size_t)r * G.nc + j] = Un[r];
@@ -1183,10 +1184,19 @@ __global__ __launch_bounds__(256) void k_cell_update(StepArgs<T> a, Geom G, Mat 
     const unsigned long long bk = __ballot(kin);
     if (lane == 0 && bk) atomicAdd(a.kcount, (unsigned long long)__popcll(bk));
   }
+  // speeds of U^{n+1}: maximum over the block, then one atomic per axis (the
+  // atomics of all blocks go to the same address and are serialised there)
+  __shared__ double wm[4][ASTR];
 #pragma unroll
   for (int d2 = 0; d2 < D; ++d2) {
     const double m = wave_max(phys ? speed[d2] : 0.0);
-    if (lane == 0) atomic_max_pos(a.set_w + d2, m);
+    if (lane == 0) wm[threadIdx.x >> 6][d2] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x < D) {
+    double m = wm[0][threadIdx.x];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, wm[w][threadIdx.x]);
+    atomic_max_pos(a.set_w + threadIdx.x, m);
   }
 }
 
@@ -1233,7 +1243,7 @@ __global__ __launch_bounds__(256) void k_cell_init(double* __restrict__ U, doubl
       }
     }
     const bool valid = mode != MODE_RETAU || !(rec[(size_t)j * RS + D + 1] < (T)0);
-    phys = cell_record<D, T>(Un, cfv, G, A, vt, rec + (size_t)j * RS, speed, valid);
+    phys = cell_record<D, T>(Un, cfv, G, A, rec + (size_t)j * RS, speed, valid);
 #pragma unroll
     for (int r = 0; r < NM; ++r) {
       U[(size_t)r * G.nc + j] = Un[r];

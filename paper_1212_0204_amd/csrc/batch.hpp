@@ -1,8 +1,8 @@
 // batch.hpp -- batched persistent form: many independent 1D-1V tubes (each
 // with its own cells, velocity grid, dt and tau) advanced together.  A step is
 // two launches: a persistent grid pulls from one queue first the Euler solves
-// of the tubes (one 1024-thread block per tube, s MUSCL sub-steps, largest
-// first) and then the kinetic items (a CELLS-cell segment of one tube with
+// of the tubes (one 1024-thread block per tube, s MUSCL sub-steps with the
+// tube's moments in registers, largest first) and then the kinetic items (a CELLS-cell segment of one tube with
 // all its velocities split over 1024/CELLS groups of threads, writing the
 // moment sums of its cells), so the two run side by side; the update launch
 // then forms U^{n+1} and the next records cell by cell.
@@ -162,6 +162,125 @@ __device__ void batch_euler_seg(const BatchArgs& a, int t, double* L, double* re
   if (!phys) atomicOr(a.tflag + t, FLAG_NONPHYS);
 }
 
+// Euler solve of one tube of at most EUL_TPB * EUL_CPT cells with the
+// moments held in registers for all s sub-steps: thread t owns cells
+// t + k EUL_TPB (slab k).  Per sub-step and slab the owners write the split
+// fluxes W+- of their cells (and of the two cells beyond each end of the
+// slab, which they also own, or the boundary cell for the clamped outflow
+// entries) into LDS, the faces of the slab are formed once each, and every
+// owner updates its cell; memory is read once at the start and written once
+// at the end (UE[s % 2]).  Same arithmetic per flux and face as
+// `batch_euler_seg` and `euler_cell`.
+constexpr int EUL_CPT = 4;
+
+__device__ void batch_euler_reg(const BatchArgs& a, int t, double* L, double* red) {
+  t = __builtin_amdgcn_readfirstlane(t);
+  const TubeDev T = a.tubes[t];
+  const Geom G = tube_geom(T);
+  const int p = a.parity;
+  double* alpha_r = a.alpha + ((size_t)t * 2 + p) * ASTR;
+  double* alpha_w = a.alpha + ((size_t)t * 2 + (p ^ 1)) * ASTR;
+  double alpha = __hip_atomic_load(alpha_r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  bool over;
+  const int s = substeps<1>(&alpha, G, a.s_cap, &over);
+  if (threadIdx.x == 0) {
+    alpha_w[0] = 0.0;  // the kinetic launch reduces the speeds of U^{n+1} here
+    a.tube_s[t] = s;
+    if (over) atomicOr(a.tflag + t, FLAG_SUBSTEP);
+  }
+  if (G.mu == 0.0) return;
+  const int Nx = G.nc;
+  const int nslab = (Nx + EUL_TPB - 1) / EUL_TPB;
+  double* Wl = L;                      // [EUL_TPB + 4][6]: W+ (3), W- (3)
+  double* Pl = L + (EUL_TPB + 4) * 6;  // [EUL_TPB + 1][3]: face fluxes
+  const int tid = threadIdx.x;
+  const double* U0 = a.dar + (p ? T.U[1] : T.U[0]);
+  double Ur[EUL_CPT][3], Un[EUL_CPT][3];
+#pragma unroll
+  for (int k = 0; k < EUL_CPT; ++k) {
+    const int c = k * EUL_TPB + tid;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      Ur[k][r] = c < Nx ? U0[(size_t)r * Nx + c] : 0.0;
+      Un[k][r] = Ur[k][r];
+    }
+  }
+  const double dts_dx = (G.dt / s) / G.dx;
+  bool phys = true;
+  for (int i = 0; i < s; ++i) {
+    double mx = 0.0;
+#pragma unroll
+    for (int k = 0; k < EUL_CPT; ++k) {
+      if (k >= nslab) break;
+      const int x0 = k * EUL_TPB;
+      const int end = min(x0 + EUL_TPB, Nx);
+      const int nent = end - x0 + 4;  // flux entries of cells x0-2 .. end+1
+      // entries written by this thread: those whose (clamped) cell it owns,
+      // among its cells of slabs k-1, k and k+1
+#pragma unroll
+      for (int dk = -1; dk <= 1; ++dk) {
+        const int kk = k + dk;
+        if (kk < 0 || kk >= EUL_CPT) continue;
+        const int c = kk * EUL_TPB + tid;
+        if (c >= Nx) continue;
+        int qlo = c - x0 + 2, qhi = qlo;
+        if (c == 0) qlo = 0;
+        if (c == Nx - 1) qhi = nent - 1;
+        qlo = max(qlo, 0);
+        qhi = min(qhi, nent - 1);
+        if (qlo > qhi) continue;
+        double Wp[3], Wm[3];
+        phys &= split_flux<1>(Ur[kk], 0, alpha, G.gam, Wp, Wm);
+        for (int q = qlo; q <= qhi; ++q) {
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            Wl[q * 6 + r] = Wp[r];
+            Wl[q * 6 + 3 + r] = Wm[r];
+          }
+        }
+      }
+      __syncthreads();
+      // face f between cells x0+f-1 and x0+f uses entries f .. f+3
+      for (int f = tid; f <= end - x0; f += blockDim.x) {
+        const double* w = Wl + f * 6;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const double spl = vl_slope(w[6 + r] - w[r], w[12 + r] - w[6 + r], 0);
+          const double sml = vl_slope(w[15 + r] - w[9 + r], w[21 + r] - w[15 + r], 0);
+          Pl[f * 3 + r] = 0.5 * (w[6 + r] + w[15 + r]) + 0.25 * (spl - sml);
+        }
+      }
+      __syncthreads();
+      if (x0 + tid < Nx) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          Un[k][r] = Ur[k][r] - dts_dx * (Pl[(tid + 1) * 3 + r] - Pl[tid * 3 + r]);
+        if (i + 1 < s) {
+          double sp;
+          phys &= lf_speeds<1>(Un[k], G.gam, &sp);
+          mx = fmax(mx, sp);
+        }
+      }
+      __syncthreads();  // the next slab overwrites the LDS entries
+    }
+#pragma unroll
+    for (int k = 0; k < EUL_CPT; ++k)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) Ur[k][r] = Un[k][r];
+    if (i + 1 < s) alpha = block_max_1024(mx, red);
+  }
+  double* out = a.dar + ((s & 1) ? T.UE[1] : T.UE[0]);
+#pragma unroll
+  for (int k = 0; k < EUL_CPT; ++k) {
+    const int c = k * EUL_TPB + tid;
+    if (c < Nx) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) out[(size_t)r * Nx + c] = Ur[k][r];
+    }
+  }
+  if (!phys) atomicOr(a.tflag + t, FLAG_NONPHYS);
+}
+
 template <int CELLS, int UNR>
 __device__ void batch_kinetic_item(const BatchArgs& a, int it, unsigned char* lds_raw) {
   constexpr int VG = 1024 / CELLS;
@@ -213,13 +332,15 @@ __device__ void batch_kinetic_item(const BatchArgs& a, int it, unsigned char* ld
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const int ix = ix0 + u;
-        gv[u] = gin[(size_t)ix * Nx + map_x<1>(xN, ix - G.kofs, Nx)];
+        const char* gp = reinterpret_cast<const char*>(gin + (size_t)ix * Nx);
+        gv[u] = *reinterpret_cast<const float*>(
+            gp + (unsigned)map_x<1>(xN, ix - G.kofs, Nx) * (unsigned)sizeof(float));
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const int ix = ix0 + u;
         const int kx = ix - G.kofs;
-        const VelNode vn = vt[ix];
+        const VelNode vn = vel_node(vt, ix);
         const float vxT = vn.vf, vhT = vn.v2hf;
         const float4* rp = reinterpret_cast<const float4*>(lds + (cl - kx + lofs) * RS);
         const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
@@ -230,7 +351,8 @@ __device__ void batch_kinetic_item(const BatchArgs& a, int it, unsigned char* ld
         const float pe = r1.z + r1.w * vxT + r2.x * vhT;
         const float E = M + pe;
         const float fs = lam * gv[u] + (mu * M + pp);
-        gout[(size_t)ix * Nx + x] = fs;
+        *reinterpret_cast<float*>(reinterpret_cast<char*>(gout + (size_t)ix * Nx) +
+                                  (unsigned)x * (unsigned)sizeof(float)) = fs;
         const double fd = (double)fs, Ed = (double)E;
         aK0 += fd;
         aK1 += vn.v * fd;
@@ -337,9 +459,13 @@ __global__ __launch_bounds__(1024, 4) void k_batch_step(BatchArgs a) {
     if (threadIdx.x == 0) s_item = atomicAdd(a.queue + p, 1);
     __syncthreads();
     const int w = s_item;
-    if (w < a.ntubes)
-      batch_euler_seg(a, a.euler_order[w], reinterpret_cast<double*>(lds_raw), red);
-    else if (w < a.ntubes + a.nitems)
+    if (w < a.ntubes) {
+      const int tb = a.euler_order[w];
+      if (a.tubes[tb].Nx <= EUL_TPB * EUL_CPT)
+        batch_euler_reg(a, tb, reinterpret_cast<double*>(lds_raw), red);
+      else
+        batch_euler_seg(a, tb, reinterpret_cast<double*>(lds_raw), red);
+    } else if (w < a.ntubes + a.nitems)
       batch_kinetic_item<CELLS, UNR>(a, w - a.ntubes, lds_raw);
     else
       break;

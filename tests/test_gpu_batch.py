@@ -119,3 +119,28 @@ def test_full_batch_sampled_tubes():
             continue
         err = moment_errors(Us[i], o.U, 1)
         assert err.max() < TOL32, (i, tubes[i], err)
+
+
+@gpu
+def test_long_tubes_match_oracle():
+    """long tubes: up to 4096 cells the Euler solve keeps four cells per
+    thread in registers (slabs of 1024 cells, ragged last slab), beyond it
+    runs by segments through memory; all of them, and a short tube beside
+    them, against the oracle after 12 single steps"""
+    rng = np.random.default_rng(11)
+    tubes = []
+    for nx in (2049, 3001, 4096, 5000, 8192, 9000, 300):
+        nv = 32
+        tau = float(10.0 ** rng.uniform(-3, -1))
+        rl, pl, rr, pr = rng.uniform(0.5, 1.0, 4)
+        th_max = max(pl / rl, pr / rr)
+        dv = 2.0 ** np.ceil(np.log2(6.0 * np.sqrt(th_max) / (nv / 2)))
+        tubes.append(W.Tube(nx, nv, float(dv), tau, (rl, 0.0, pl), (rr, 0.0, pr)))
+    announce("long tubes", [t.nx for t in tubes])
+    b = make_batch(tubes)
+    b.set_state_macro(*tube_fields(tubes))
+    b.step(12)
+    assert (b.tube_flags() == 0).all()
+    for t, U in zip(tubes, b.read_moments()):
+        err = moment_errors(U, oracle_tube(t, 12).U, 1)
+        assert err.max() < TOL32, (t.nx, err)

@@ -186,7 +186,10 @@ hofks_status hofks_autotune(hofks_ctx *ctx, int steps, const char *cache_path,
 
 /* Network: device pointer to hofks_mlp_packed_bytes() bytes (16-byte
  * aligned) written by hofks_mlp_pack; owned by the caller and read by every
- * following step until hofks_closure_disable.  sigma scales the output;
+ * following step until hofks_closure_disable.  The output on the uniform
+ * stencil (y0) is evaluated at the first closure step after this call and
+ * again when tau changes: weights rewritten in place take effect after
+ * calling hofks_closure_enable again.  sigma scales the output;
  * threshold < 0 makes every cell kinetic, +INF every cell a closure cell
  * (up to the delta marks, also compared with it). */
 hofks_status hofks_closure_enable(hofks_ctx *ctx, const void *packed_weights,

@@ -162,8 +162,10 @@ __global__ __launch_bounds__(256) void k_dilate(const unsigned char* __restrict_
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= G.nc) return;
   const int x = j % G.n[0], y = j / G.n[0];
+  // every load of the window is issued (no early exit), so they overlap
   unsigned char any = 0;
-  for (int d = -h; d <= h && !any; ++d) {
+#pragma unroll 8
+  for (int d = -h; d <= h; ++d) {
     const int jj = AXIS == 0 ? y * G.n[0] + map_axis(x + d, G.n[0], G.bc[0])
                              : map_axis(y + d, G.n[1], G.bc[1]) * G.n[0] + x;
     any |= in[jj];

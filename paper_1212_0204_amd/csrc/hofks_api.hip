@@ -39,6 +39,7 @@ struct Plan {
   int prec;
   size_t tsize;  // bytes per stored piece
   int TX, TR, nseg, nrowgrp, nchunk, nvr, GE, ETPB;
+  int ncu;  // compute units of the device
   size_t lds;
   int RS;  // record stride (values)
   // workspace offsets (bytes)
@@ -191,6 +192,7 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
     ncu = 256;
   // threads per Euler block: up to one cell per thread when the grid is
   // large enough to fill every compute unit with wider blocks
+  P->ncu = ncu;
   const int ge = std::min(256, ncu);
   P->ETPB = 256;
   for (int tpb = HOFKS_EULER_TPB_MAX; tpb > 256; tpb /= 2)
@@ -288,6 +290,8 @@ struct hofks_ctx {
   unsigned char *cflag, *ctmp, *cmode, *cdfl;
   unsigned long long* kcount;
   float* clos_y0;
+  float clos_y0_ftau;  // log10(tau/dt) input of the stored y0
+  bool clos_y0_ok;     // y0 holds the network's output on the uniform stencil
   long clos_steps;
   char err[512];
 };
@@ -586,10 +590,17 @@ hofks_status launch_closure_step(hofks_ctx* c, StepArgs<T>& a, float* snap_x, fl
     ca.lam = P.G.lam;
     ca.sigma = c->clos_sigma;
     ca.thr = c->clos_thr;
-    hipLaunchKernelGGL(k_closure_center, dim3(1), dim3(64), 0, c->stream, c->clos_w, c->clos_y0,
-                       ftau);
+    if (!c->clos_y0_ok || c->clos_y0_ftau != ftau) {  // once per network and tau
+      hipLaunchKernelGGL(k_closure_center, dim3(1), dim3(64), 0, c->stream, c->clos_w,
+                         c->clos_y0, ftau);
+      c->clos_y0_ok = true;
+      c->clos_y0_ftau = ftau;
+    }
+    // one resident round of blocks (two per compute unit at this kernel's
+    // register use), each wavefront looping over 16-cell tiles, so that the
+    // network weights are loaded into registers once per wavefront
     const unsigned tiles = (unsigned)((nc + 15) / 16);
-    const unsigned grid = std::min(2048u, (tiles + 3) / 4);
+    const unsigned grid = std::min(2u * (unsigned)P.ncu, (tiles + 3) / 4);
     hipLaunchKernelGGL(k_closure_mlp, dim3(grid), dim3(256), 0, c->stream, ca, P.G);
     const int h = P.G.nv1 / 2;
     hipLaunchKernelGGL((k_dilate<0>), dim3(nblk(nc)), dim3(256), 0, c->stream,
@@ -1843,6 +1854,7 @@ hofks_status hofks_closure_enable(hofks_ctx* c, const void* packed, double sigma
   c->clos_sigma = sigma;
   c->clos_thr = threshold;
   c->clos_on = true;
+  c->clos_y0_ok = false;
   return HOFKS_OK;
 }
 

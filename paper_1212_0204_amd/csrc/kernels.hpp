@@ -920,19 +920,23 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
         // closure tile: every piece is the equilibrium of its upstream cell,
         // so only E is evaluated and summed once; the sums of f* equal those
         // of E
-        for (int ix = ixa; ix < ixb; ++ix) {
-          const int kx = ix - G.kofs;
-          const VelNode vn = vel_node(a.vt, ix);
-          const T vxT = (sizeof(T) == 4) ? (T)vn.vf : (T)vn.v;
-          const T vhT = (sizeof(T) == 4) ? (T)vn.v2hf : (T)vn.v2h;
-          const T* rr = Lw + (SW - 1 - lane + kx - lofs) * FS;
-          const T dx_ = vxT - rr[1];
-          const T M = fast_exp<T>(rr[0] - fabs(rr[2]) * (dx_ * dx_));
-          const T E = M + (rr[6] + rr[7] * vxT + rr[8] * vhT);
-          const double Ed = (double)E;
-          aE0 += Ed;
-          aE1 += vn.v * Ed;
-          aE2 += vn.v2h * Ed;
+        for (int ix0 = ixa; ix0 < ixb; ix0 += UNR) {
+          const T* Lb = Lw + (SW - 1 - lane - lofs - G.kofs + ix0) * FS;
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) {
+            const VelNode vn = vel_node(a.vt, ix0 + u);
+            const T vxT = (sizeof(T) == 4) ? (T)vn.vf : (T)vn.v;
+            const T vhT = (sizeof(T) == 4) ? (T)vn.v2hf : (T)vn.v2h;
+            T rr[9];
+            read_row_rec<T>(Lb + u * FS, rr);
+            const T dx_ = vxT - rr[1];
+            const T M = fast_exp<T>(rr[0] - fabs(rr[2]) * (dx_ * dx_));
+            const T E = M + (rr[6] + rr[7] * vxT + rr[8] * vhT);
+            const double Ed = (double)E;
+            aE0 += Ed;
+            aE1 += vn.v * Ed;
+            aE2 += vn.v2h * Ed;
+          }
         }
         aK0 = aE0;
         aK1 = aE1;

@@ -25,6 +25,7 @@
 #include "closure.hpp"
 #include "euler2d.hpp"
 #include "kernels.hpp"
+#include "kinetic2w.hpp"
 #include "kinetic3d.hpp"
 #include "mlp.hpp"
 
@@ -266,6 +267,7 @@ struct hofks_ctx {
   bool ready;
   int kng, kunr;  // kinetic kernel: wavefronts per block, loads issued ahead
   int kring;      // 3D steps with an Euler solve: k_kinetic3 (blocks of RY rows)
+  int kwide;      // 2D FP64 steps with an Euler solve: k_kinetic2w (two cells per lane)
   // optional per-kernel timing: hipEvents around each launch group
   bool timing;
   std::vector<hipEvent_t> ev_pool;
@@ -397,6 +399,34 @@ void dispatch_kin3(hofks_ctx* c, const StepArgs<T>& a) {
 #undef K
 }
 
+// 2D FP64 steps with an Euler solve: two cells per lane (k_kinetic2w)
+size_t kin2w_lds(const Plan& P, int ng) {
+  const size_t sp = (W2_CELLS + P.G.nv1) / 2;  // records per parity half
+  const size_t stage = (size_t)ng * 2 * sp * row_rec_stride<double>() * sizeof(double);
+  const size_t red = (size_t)(ng - 1) * 64 * 16 * sizeof(double);
+  return std::max(stage, red);
+}
+
+void dispatch_kin2w(hofks_ctx* c, const StepArgs<double>& a) {
+  const Plan& P = c->P;
+  const int nsegw = (P.G.n[0] + W2_CELLS - 1) / W2_CELLS;
+  const dim3 grid((unsigned)((long)nsegw * P.G.n[1]));
+  const int ng = c->kng == 2 ? 2 : 4, unr = P.G.nv1 % 8 == 0 && c->kunr == 8 ? 8 : 4;
+  const size_t lds = kin2w_lds(P, ng);
+#define K(BCX, NG, U)                                                                    \
+  hipLaunchKernelGGL((k_kinetic2w<BCX, U, NG>), grid, dim3(64 * NG), lds, c->stream, a, \
+                     P.G, nsegw)
+#define KB(NG, U) \
+  if (P.G.bc[0] == 0) K(0, NG, U); else K(1, NG, U);
+  if (ng == 2) {
+    if (unr == 8) { KB(2, 8) } else { KB(2, 4) }
+  } else {
+    if (unr == 8) { KB(4, 8) } else { KB(4, 4) }
+  }
+#undef KB
+#undef K
+}
+
 template <int D, typename T, bool FT, bool EUL>
 void dispatch_kin(hofks_ctx* c, const StepArgs<T>& a, dim3 grid) {
   constexpr bool CP = sizeof(T) == 4;  // compensated sums in the FP32 form
@@ -404,6 +434,12 @@ void dispatch_kin(hofks_ctx* c, const StepArgs<T>& a, dim3 grid) {
   if constexpr (D == 3 && EUL && !FT) {
     if (c->kring) {
       dispatch_kin3<T>(c, a);
+      return;
+    }
+  }
+  if constexpr (D == 2 && EUL && !FT && sizeof(T) == 8) {
+    if (c->kwide) {
+      dispatch_kin2w(c, a);
       return;
     }
   }
@@ -818,6 +854,11 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
   c->kunr = P.d >= 2 ? 16 : 8;
   if (kin_lds(P, c->kng) > 65536) c->kng = 2;
   c->kring = HOFKS_KRING && P.d == 3 && kin3_lds(P) <= 65536;
+  c->kwide = P.d == 2 && !P.prec && P.G.nv1 % 4 == 0 && kin2w_lds(P, 4) <= 65536;
+  if (c->kwide) {
+    c->kng = 4;
+    c->kunr = 4;
+  }
   // velocity node table of one axis (the lattice, used by every kernel)
   std::vector<VelNode> tab(P.G.nv1);
   for (int i = 0; i < P.G.nv1; ++i) {
@@ -1537,7 +1578,8 @@ hofks_status grid_autotune(hofks_ctx* c, int steps, const char* cache_path, int*
       const size_t pn = line.find("\"ng\": "), pu = line.find("\"unr\": ");
       if (pn == std::string::npos || pu == std::string::npos) continue;
       const int ng = std::atoi(line.c_str() + pn + 6), unr = std::atoi(line.c_str() + pu + 7);
-      if ((ng == 2 || ng == 4 || (ng == 8 && P.d >= 2)) && (unr == 8 || unr == 16)) {
+      if ((ng == 2 || ng == 4 || (ng == 8 && P.d >= 2)) &&
+          (unr == 8 || unr == 16 || (unr == 4 && c->kwide))) {
         best_ng = ng;
         best_unr = unr;
       }
@@ -1548,9 +1590,14 @@ hofks_status grid_autotune(hofks_ctx* c, int steps, const char* cache_path, int*
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    const int cand[6][2] = {{4, 8}, {2, 16}, {4, 16}, {2, 8}, {8, 16}, {8, 8}};
-    for (const auto& cd : cand) {
-      if (kin_lds(P, cd[0]) > 65536 || (cd[0] == 8 && P.d < 2)) continue;
+    // two cells per lane (2D FP64): loads ahead 4 or 8, at most four wavefronts
+    const int cand_w[4][2] = {{4, 4}, {2, 4}, {4, 8}, {2, 8}};
+    const int cand_n[6][2] = {{4, 8}, {2, 16}, {4, 16}, {2, 8}, {8, 16}, {8, 8}};
+    const int ncand = c->kwide ? 4 : 6;
+    for (int k = 0; k < ncand; ++k) {
+      const int* cd = c->kwide ? cand_w[k] : cand_n[k];
+      if (c->kwide && kin2w_lds(P, cd[0]) > 65536) continue;
+      if (!c->kwide && (kin_lds(P, cd[0]) > 65536 || (cd[0] == 8 && P.d < 2))) continue;
       if (c->kring && cd[0] != RY) continue;  // 3D: blocks of RY rows, only the unroll varies
       c->kng = cd[0];
       c->kunr = cd[1];

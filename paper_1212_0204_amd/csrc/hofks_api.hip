@@ -513,6 +513,12 @@ void launch_euler(hofks_ctx* c, const StepArgs<T>& a, hipStream_t st) {
     const int ntx = (P.G.n[0] + ET - 1) / ET, nty = (P.G.n[1] + ET - 1) / ET;
     for (int i = 0; i < K; ++i)
       hipLaunchKernelGGL((k_euler_sub_tile<T>), dim3(ntx * nty), dim3(256), 0, st, a, P.G, i, ntx);
+  } else if constexpr (D == 3) {  // 8 x 4 x 4 LDS tiles
+    const int ntx = (P.G.n[0] + E3X - 1) / E3X, nty = (P.G.n[1] + E3Y - 1) / E3Y;
+    const int ntz = (P.G.n[2] + E3Z - 1) / E3Z;
+    for (int i = 0; i < K; ++i)
+      hipLaunchKernelGGL((k_euler_sub_tile3<T>), dim3(ntx * nty * ntz), dim3(256), 0, st, a, P.G,
+                         i, ntx, nty);
   } else {
     for (int i = 0; i < K; ++i)
       hipLaunchKernelGGL((k_euler_sub<D, T>), dim3(nblk(P.G.nc)), dim3(256), 0, st, a, P.G, i);

@@ -268,6 +268,8 @@ struct hofks_ctx {
   int kng, kunr;  // kinetic kernel: wavefronts per block, loads issued ahead
   int kring;      // 3D steps with an Euler solve: k_kinetic3 (blocks of RY rows)
   int kwide;      // 2D FP64 steps with an Euler solve: k_kinetic2w (two cells per lane)
+  bool fork_next;     // the current step is followed by another in this call
+  bool fork_pending;  // ev_fork already marks the next step's fork point
   // optional per-kernel timing: hipEvents around each launch group
   bool timing;
   std::vector<hipEvent_t> ev_pool;
@@ -478,7 +480,12 @@ void launch_euler(hofks_ctx* c, const StepArgs<T>& a, hipStream_t st);
 // already queued on the caller's stream
 template <int D, typename T>
 hofks_status fork_euler(hofks_ctx* c, const StepArgs<T>& a) {
-  HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+  // within one hofks_step call the previous step recorded the fork point
+  // right after U^{n+1} was formed, before its records
+  if (c->fork_pending)
+    c->fork_pending = false;
+  else
+    HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
   HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
   {
     Mark m0(c, 0, 1, c->aux);
@@ -495,8 +502,21 @@ hofks_status join_update(hofks_ctx* c, const StepArgs<T>& a) {
   const Plan& P = c->P;
   HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
   Mark m(c, 2);
-  hipLaunchKernelGGL((k_cell_update<D, T, CLOS>), dim3(nblk(P.G.nc)), dim3(256), 0, c->stream, a,
-                     P.G, P.A);
+  if constexpr (CLOS) {
+    hipLaunchKernelGGL((k_cell_update<D, T, CLOS>), dim3(nblk(P.G.nc)), dim3(256), 0, c->stream,
+                       a, P.G, P.A);
+  } else {
+    // U^{n+1}, cf and speeds; the fork point of the next step of this call;
+    // then the records, beside the next step's Euler solve
+    hipLaunchKernelGGL((k_cell_update_u<D, T>), dim3(nblk(P.G.nc)), dim3(256), 0, c->stream, a,
+                       P.G, P.A);
+    if (c->fork_next) {
+      HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+      c->fork_pending = true;
+    }
+    hipLaunchKernelGGL((k_cell_record<D, T>), dim3(nblk(P.G.nc)), dim3(256), 0, c->stream, a,
+                       P.G, P.A);
+  }
   HIPCHK(c, hipGetLastError());
   return HOFKS_OK;
 }
@@ -681,13 +701,17 @@ hofks_status launch_closure_step(hofks_ctx* c, StepArgs<T>& a, float* snap_x, fl
 
 template <int D, typename T>
 hofks_status step_impl(hofks_ctx* c, int nsteps) {
-  for (int it = 0; it < nsteps; ++it) {
-    hofks_status st = launch_step<D, T>(c);
-    if (st) return st;
+  c->fork_pending = false;
+  hofks_status st = HOFKS_OK;
+  for (int it = 0; it < nsteps && !st; ++it) {
+    c->fork_next = it + 1 < nsteps;
+    st = launch_step<D, T>(c);
+    if (st) break;
     c->cur ^= 1;
     c->steps++;
   }
-  return HOFKS_OK;
+  c->fork_next = c->fork_pending = false;
+  return st;
 }
 
 template <typename F>

@@ -1204,6 +1204,78 @@ __global__ __launch_bounds__(256) void k_cell_update(StepArgs<T> a, Geom G, Mat 
   }
 }
 
+// The per-cell update in two launches, so that the Euler solve of the next
+// step (which needs U^{n+1} and its speeds only) can start while the next
+// records are formed.  First: delta, U^{n+1}, cf and the speeds of U^{n+1}
+// (the same formulas as `k_cell_update`; |u_a| + c as in `lf_speeds`).
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_cell_update_u(StepArgs<T> a, Geom G, Mat A) {
+  constexpr int NM = D + 2;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = j < G.nc;
+  bool phys = true;
+  double speed[3] = {0.0, 0.0, 0.0};
+  if (active) {
+    double SK[NM], SE[NM];
+#pragma unroll
+    for (int r = 0; r < NM; ++r) {
+      SK[r] = a.sums[(size_t)r * G.nc + j];
+      SE[r] = a.sums[(size_t)(NM + r) * G.nc + j];
+    }
+    bool over;
+    const int s = substeps<D>(a.set_r, G, a.s_cap, &over);
+    const double* UEs = (s & 1) ? a.UE1 : a.UE0;
+    double delta[NM], Un[NM];
+#pragma unroll
+    for (int r = 0; r < NM; ++r) {
+      const double UM = G.mu * (G.w * SE[r]);
+      const double UEv = G.mu * UEs[(size_t)r * G.nc + j];
+      delta[r] = UEv - UM;
+    }
+#pragma unroll
+    for (int r = 0; r < NM; ++r) Un[r] = G.w * SK[r] + delta[r];
+#pragma unroll
+    for (int r = 0; r < NM; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int s2 = 0; s2 < NM; ++s2) acc += A.a[r * NM + s2] * delta[s2];
+      a.U_out[(size_t)r * G.nc + j] = Un[r];
+      a.cf[(size_t)r * G.nc + j] = acc;
+    }
+    phys = lf_speeds<D>(Un, G.gam, speed);
+  }
+  if (active && G.mu != 0.0 && !phys) atomicOr(a.flag, FLAG_NONPHYS);
+  const int lane = threadIdx.x & 63;
+  __shared__ double wm[4][ASTR];
+#pragma unroll
+  for (int d2 = 0; d2 < D; ++d2) {
+    const double m = wave_max(phys ? speed[d2] : 0.0);
+    if (lane == 0) wm[threadIdx.x >> 6][d2] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x < D) {
+    double m = wm[0][threadIdx.x];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, wm[w][threadIdx.x]);
+    atomic_max_pos(a.set_w + threadIdx.x, m);
+  }
+}
+
+// Second: the next record of every cell from U^{n+1} and cf.
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_cell_record(StepArgs<T> a, Geom G, Mat A) {
+  constexpr int NM = D + 2;
+  constexpr int RS = rec_stride<D, T>();
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= G.nc) return;
+  double Un[NM], cfv[NM], speed[3];
+#pragma unroll
+  for (int r = 0; r < NM; ++r) {
+    Un[r] = a.U_out[(size_t)r * G.nc + j];
+    cfv[r] = a.cf[(size_t)r * G.nc + j];
+  }
+  (void)cell_record<D, T>(Un, cfv, G, A, a.rec_out + (size_t)j * RS, speed, true);
+}
+
 // ======================================================= set-up / refresh
 // MODE_INIT: U given, the pieces g hold sampled values with sums S (chunk 0
 // of part): project onto U as in eq. (minim1), cf = A (U - w S).

@@ -84,6 +84,8 @@ def test_free_transport_bit_exact(d, n, nv):
     ((64, 32), (0, 1), 0.0, 0),      # tau = 0: Euler only
     ((64, 32), (0, 0), 1e-2, 1),     # FKS
     ((64, 32), (0, 0), 1e-2, 2),     # unlimited
+    ((67, 9), (0, 0), 1e-3, 0),      # odd x: a lane with one cell, pairs across the seam
+    ((129, 5), (1, 0), 2e-3, 0),     # odd x over two 128-cell segments, outflow clamps
 ])
 def test_2d_fp64(n, bc, tau, scheme):
     announce("2d fp64", n, bc, tau, scheme)

@@ -85,6 +85,7 @@ __device__ __forceinline__ double block_max_1024(double v, double* red) {
 // face as `euler_cell`; the result is UE[s % 2].
 constexpr int EUL_TPB = 1024;
 constexpr size_t EUL_LDS = (size_t)((EUL_TPB + 4) * 6 + (EUL_TPB + 1) * 3) * sizeof(double);
+constexpr size_t EUL_REG_LDS = 2 * EUL_LDS;  // the register form alternates two sets
 
 __device__ void batch_euler_seg(const BatchArgs& a, int t, double* L, double* red) {
   t = __builtin_amdgcn_readfirstlane(t);
@@ -191,8 +192,13 @@ __device__ void batch_euler_reg(const BatchArgs& a, int t, double* L, double* re
   if (G.mu == 0.0) return;
   const int Nx = G.nc;
   const int nslab = (Nx + EUL_TPB - 1) / EUL_TPB;
-  double* Wl = L;                      // [EUL_TPB + 4][6]: W+ (3), W- (3)
-  double* Pl = L + (EUL_TPB + 4) * 6;  // [EUL_TPB + 1][3]: face fluxes
+  // two sets of LDS entries, alternating between slabs, so that a slab's
+  // writes need no barrier after the previous slab's reads (the barriers
+  // inside each slab already separate slab k's reads from slab k+2's writes)
+  double* Wl0 = L;                       // [EUL_TPB + 4][6]: W+ (3), W- (3)
+  double* Pl0 = L + (EUL_TPB + 4) * 6;   // [EUL_TPB + 1][3]: face fluxes
+  double* Wl1 = L + EUL_LDS / sizeof(double);
+  double* Pl1 = Wl1 + (EUL_TPB + 4) * 6;
   const int tid = threadIdx.x;
   const double* U0 = a.dar + (p ? T.U[1] : T.U[0]);
   double Ur[EUL_CPT][3], Un[EUL_CPT][3];
@@ -212,6 +218,8 @@ __device__ void batch_euler_reg(const BatchArgs& a, int t, double* L, double* re
 #pragma unroll
     for (int k = 0; k < EUL_CPT; ++k) {
       if (k >= nslab) break;
+      double* Wl = (k & 1) ? Wl1 : Wl0;
+      double* Pl = (k & 1) ? Pl1 : Pl0;
       const int x0 = k * EUL_TPB;
       const int end = min(x0 + EUL_TPB, Nx);
       const int nent = end - x0 + 4;  // flux entries of cells x0-2 .. end+1
@@ -261,7 +269,6 @@ __device__ void batch_euler_reg(const BatchArgs& a, int t, double* L, double* re
           mx = fmax(mx, sp);
         }
       }
-      __syncthreads();  // the next slab overwrites the LDS entries
     }
 #pragma unroll
     for (int k = 0; k < EUL_CPT; ++k)

@@ -1426,7 +1426,7 @@ hofks_status batch_launch(hofks_ctx* c, hipStream_t stream, int parity) {
   Batch* B = c->batch;
   const BatchArgs a = batch_args(c, parity);
   const dim3 grid(B->grid), block(1024);
-  const size_t lds = std::max(EUL_LDS, B->lds);
+  const size_t lds = std::max(EUL_REG_LDS, B->lds);
 #define BL(CELLS, UNR) \
   hipLaunchKernelGGL((k_batch_step<CELLS, UNR>), grid, block, lds, stream, a)
   const int u = B->unr;

@@ -301,3 +301,29 @@ def test_checkpoint_resume_is_exact(d, n, nv, prec, bc):
     s3 = Solver(d, n, dx, nv + 2, 0.5, bc=bc, precision=prec, tau=2e-2)
     with pytest.raises(HofksError):
         s3.write_state(img)
+
+
+@gpu
+@pytest.mark.parametrize("d,n,nv,prec", [(2, (70, 37), 16, 0), (3, (20, 12, 10), 8, 1)])
+def test_steps_in_one_call_equal_single_steps(d, n, nv, prec):
+    """within one step call the next step's Euler solve forks before the
+    records of the current step are formed; the results are bit for bit
+    those of single-step calls"""
+    announce("one call vs single steps", d, n, nv, prec)
+    from paper_1212_0204_amd import Solver
+    nc = int(np.prod(n))
+    rng = np.random.default_rng(19)
+    fields = (1.0 + 0.2 * rng.uniform(-1, 1, nc), 0.1 * rng.uniform(-1, 1, (d, nc)),
+              1.0 + 0.2 * rng.uniform(-1, 1, nc))
+    runs = []
+    for split in (False, True):
+        s = Solver(d, n, 1.0 / n[0], nv, 0.5, bc=(0,) * d, precision=prec, tau=1e-3)
+        s.set_state_macro(*fields)
+        if split:
+            for _ in range(6):
+                s.step(1)
+        else:
+            s.step(6)
+        runs.append((s.read_moments(), s.read_f()))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])

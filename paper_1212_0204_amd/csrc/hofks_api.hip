@@ -374,9 +374,6 @@ int kin_unroll(const Plan& P, int ng, int unr) {
 
 // 3D steps with an Euler solve: blocks of RY y rows sharing a ring of
 // staged upstream rows (k_kinetic3)
-#ifndef HOFKS_KRING
-#define HOFKS_KRING 1
-#endif
 size_t kin3_lds(const Plan& P) {
   const int fc = P.tsize == 4 ? fold3_chunks<float>() : fold3_chunks<double>();
   return (size_t)(RY + 1) * (64 + P.G.nv1 - 1) * fc * 16;
@@ -883,7 +880,7 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
   c->kng = (P.d == 2 && !P.prec) ? 2 : 4;
   c->kunr = P.d >= 2 ? 16 : 8;
   if (kin_lds(P, c->kng) > 65536) c->kng = 2;
-  c->kring = HOFKS_KRING && P.d == 3 && kin3_lds(P) <= 65536;
+  c->kring = P.d == 3 && kin3_lds(P) <= 65536;
   c->kwide = P.d == 2 && !P.prec && P.G.nv1 % 4 == 0 && kin2w_lds(P, 4) <= 65536;
   if (c->kwide) {
     c->kng = 4;

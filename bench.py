@@ -147,7 +147,13 @@ def run_batch(steps, warmup):
            "steps": steps, "cv_per_s": cv / (ms * 1e-3), "ms_per_step": ms / steps,
            "hbm_frac": 8 * cv / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
            "tuned": {"cells_per_item": tuned[0], "blocks": tuned[1]},
-           "flagged_tubes": flagged}
+           "flagged_tubes": flagged,
+           # cold-side velocity resolution of each tube: dv / sqrt(theta_min)
+           "dv_over_cold_thermal_speed": dict(zip(
+               ("min", "median", "max"),
+               (float(x) for x in np.percentile(
+                   [t.dv / math.sqrt(min(t.left[2] / t.left[0], t.right[2] / t.right[0]))
+                    for t in tubes], [0, 50, 100]))))}
     del b
     torch.cuda.empty_cache()
     return out

@@ -246,10 +246,19 @@ __device__ void batch_euler_reg(const BatchArgs& a, int t, double* L, double* re
             Wl[q * 6 + 3 + r] = Wm[r];
           }
         }
+        if (k == 0 && c == 0) {
+          // the tube's left face: entries 0..2 all hold cell 0, so both
+          // limited slopes vanish and the flux is the mean of W+ and W- of
+          // cell 0 (the value the face loop below would give)
+#pragma unroll
+          for (int r = 0; r < 3; ++r) Pl[r] = 0.5 * (Wp[r] + Wm[r]) + 0.25 * (0.0 - 0.0);
+        }
       }
       __syncthreads();
-      // face f between cells x0+f-1 and x0+f uses entries f .. f+3
-      for (int f = tid; f <= end - x0; f += blockDim.x) {
+      // face f between cells x0+f-1 and x0+f uses entries f .. f+3; face 0
+      // of a later slab is the previous slab's last face, kept in the other
+      // set, so the 1024 threads form the at most 1024 remaining faces at once
+      for (int f = tid + 1; f <= end - x0; f += blockDim.x) {
         const double* w = Wl + f * 6;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
@@ -260,9 +269,10 @@ __device__ void batch_euler_reg(const BatchArgs& a, int t, double* L, double* re
       }
       __syncthreads();
       if (x0 + tid < Nx) {
+        const double* Pleft = (tid == 0 && k > 0) ? ((k & 1) ? Pl0 : Pl1) + EUL_TPB * 3 : Pl + tid * 3;
 #pragma unroll
         for (int r = 0; r < 3; ++r)
-          Un[k][r] = Ur[k][r] - dts_dx * (Pl[(tid + 1) * 3 + r] - Pl[tid * 3 + r]);
+          Un[k][r] = Ur[k][r] - dts_dx * (Pl[(tid + 1) * 3 + r] - Pleft[r]);
         if (i + 1 < s) {
           double sp;
           phys &= lf_speeds<1>(Un[k], G.gam, &sp);

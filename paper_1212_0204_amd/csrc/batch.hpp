@@ -238,7 +238,18 @@ __device__ void batch_euler_reg(const BatchArgs& a, int t, double* L, double* re
         qhi = min(qhi, nent - 1);
         if (qlo > qhi) continue;
         double Wp[3], Wm[3];
-        phys &= split_flux<1>(Ur[kk], 0, alpha, G.gam, Wp, Wm);
+        if (k > 0 && (dk < 0 || (dk == 0 && tid < 2))) {
+          // cells x0-2, x0-1, x0 and x0+1: this thread formed their split
+          // fluxes in the previous slab's pass, in the other set of entries
+          const double* Wq = ((k & 1) ? Wl0 : Wl1) + (c - x0 + EUL_TPB + 2) * 6;
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            Wp[r] = Wq[r];
+            Wm[r] = Wq[3 + r];
+          }
+        } else {
+          phys &= split_flux<1>(Ur[kk], 0, alpha, G.gam, Wp, Wm);
+        }
         for (int q = qlo; q <= qhi; ++q) {
 #pragma unroll
           for (int r = 0; r < 3; ++r) {

@@ -866,9 +866,12 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
     c->kcount = (unsigned long long*)b;
     c->clos_y0 = (float*)(b + 16);
   }
+  // the fork and join events order the two streams of this device only, so
+  // they need no system-scope fence (no host or peer reads between them)
+  constexpr unsigned evf = hipEventDisableTiming | hipEventDisableSystemFence;
   if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ev_fork, evf) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, evf) != hipSuccess) {
     delete c;
     return HOFKS_EDEVICE;
   }

@@ -519,13 +519,15 @@ hofks_status join_update(hofks_ctx* c, const StepArgs<T>& a) {
 }
 
 // Euler solve of a step: one launch per sub-step for the first K = (last
-// known count + 2) sub-steps (the kernel boundary is the grid-wide barrier),
+// known count + 1) sub-steps (the kernel boundary is the grid-wide barrier),
 // then a persistent tail that runs any further sub-steps with an in-kernel
-// barrier (it returns at once when K >= s)
+// barrier (it returns at once when K >= s).  One spare launch absorbs a count
+// that grows by one within a call; each launch with i >= s still costs a
+// kernel boundary on the solve's critical path, so there is only one.
 template <int D, typename T>
 void launch_euler(hofks_ctx* c, const StepArgs<T>& a, hipStream_t st) {
   const Plan& P = c->P;
-  const int K = std::max(1, std::min(c->s_cap, c->s_known + 2));
+  const int K = std::max(1, std::min(c->s_cap, c->s_known + 1));
   if constexpr (D == 2) {  // 16 x 16 LDS tiles
     const int ntx = (P.G.n[0] + ET - 1) / ET, nty = (P.G.n[1] + ET - 1) / ET;
     for (int i = 0; i < K; ++i)

@@ -35,7 +35,6 @@ struct BatchArgs {
   int ntubes, nitems;
   int* queue;             // work counters by step parity
   double* alpha;          // [tube][parity][ASTR]: speeds of U^n / U^{n+1}
-  int* done;              // unused
   int* tube_s;            // sub-steps of the current step, per tube
   int* tflag;             // per-tube error bits
   int* flag;              // launch-wide bits (bounded waits)

@@ -319,8 +319,8 @@ double* slot_set(hofks_ctx* c, int set) { return c->slots + (size_t)set * SET_D;
 int rpar(const hofks_ctx* c) { return (int)(c->steps & 1); }   // buffer holding U^n, rec^n
 int rset(const hofks_ctx* c) { return (int)(c->steps % 3); }   // speeds of U^n
 
-// timing groups: 0 Euler sub-steps (not separable in the fused step), 1 the
-// fused step kernel, 2 unused
+// timing groups: 0 the Euler sub-steps (auxiliary stream), 1 the kinetic
+// kernel, 2 the per-cell update, 3 the closure network and its indicator
 hipEvent_t next_event(hofks_ctx* c) {
   if (c->ev_next == c->ev_pool.size()) {
     hipEvent_t e;
@@ -1216,14 +1216,14 @@ struct Batch {
   int nvt = 0, items_max = 0;
   long long total_cells = 0, total_cv = 0;
   size_t off_gar = 0, off_rar = 0, off_dar = 0, off_vt = 0, off_tubes = 0, off_order = 0,
-         off_items = 0, off_queue = 0, off_alpha = 0, off_done = 0, off_s = 0, off_tflag = 0,
+         off_items = 0, off_queue = 0, off_alpha = 0, off_s = 0, off_tflag = 0,
          off_flag = 0, total = 0;
   // device pointers
   float *gar = nullptr, *rar = nullptr;
   double *dar = nullptr, *alpha = nullptr;
   VelNode* vtar = nullptr;
   TubeDev* tubes_d = nullptr;
-  int *order = nullptr, *queue = nullptr, *done = nullptr, *tube_s = nullptr, *tflag = nullptr,
+  int *order = nullptr, *queue = nullptr, *tube_s = nullptr, *tflag = nullptr,
       *flag = nullptr;
   int2* items = nullptr;
   // launch configuration
@@ -1322,7 +1322,6 @@ hofks_status batch_plan(const hofks_grid_desc* descs, const double* taus, int n,
   B->off_items = take(sizeof(int2) * nitems);
   B->off_queue = take(64);
   B->off_alpha = take(sizeof(double) * n * 2 * ASTR);
-  B->off_done = take(sizeof(int) * n * 2);
   B->off_s = take(sizeof(int) * n);
   B->off_tflag = take(sizeof(int) * n);
   B->off_flag = take(64);
@@ -1415,7 +1414,6 @@ BatchArgs batch_args(hofks_ctx* c, int parity) {
   a.nitems = B->nitems;
   a.queue = B->queue;
   a.alpha = B->alpha;
-  a.done = B->done;
   a.tube_s = B->tube_s;
   a.tflag = B->tflag;
   a.flag = B->flag;
@@ -1545,8 +1543,6 @@ hofks_status batch_set_state(hofks_ctx* c, const double* rho, const double* u,
   hofks_status st = zero_ints(c, B->flag, 16);
   if (st) return st;
   st = zero_ints(c, B->tflag, B->n);
-  if (st) return st;
-  st = zero_ints(c, B->done, 2 * B->n);
   if (st) return st;
   st = zero_ints(c, B->queue, 16);
   if (st) return st;
@@ -1714,7 +1710,6 @@ hofks_status hofks_batch_create(const hofks_grid_desc* descs, const double* taus
   B->items = (int2*)(c->ws + B->off_items);
   B->queue = (int*)(c->ws + B->off_queue);
   B->alpha = (double*)(c->ws + B->off_alpha);
-  B->done = (int*)(c->ws + B->off_done);
   B->tube_s = (int*)(c->ws + B->off_s);
   B->tflag = (int*)(c->ws + B->off_tflag);
   B->flag = (int*)(c->ws + B->off_flag);

@@ -144,3 +144,29 @@ def test_long_tubes_match_oracle():
     for t, U in zip(tubes, b.read_moments()):
         err = moment_errors(U, oracle_tube(t, 12).U, 1)
         assert err.max() < TOL32, (t.nx, err)
+
+
+@gpu
+def test_slab_edge_tubes_match_oracle():
+    """tube lengths at the edges of the 1024-cell slabs of the register form
+    of the Euler solve (one cell short of, exactly at and one cell past a
+    slab end): a slab's first face is carried over from the previous slab
+    and the split fluxes of the two cells on each side of a seam are reused,
+    so these lengths exercise every seam case"""
+    rng = np.random.default_rng(23)
+    tubes = []
+    for nx in (1023, 1024, 1025, 2047, 2048, 3072, 4095):
+        nv = 32
+        tau = float(10.0 ** rng.uniform(-3, -1))
+        rl, pl, rr, pr = rng.uniform(0.5, 1.0, 4)
+        th_max = max(pl / rl, pr / rr)
+        dv = 2.0 ** np.ceil(np.log2(6.0 * np.sqrt(th_max) / (nv / 2)))
+        tubes.append(W.Tube(nx, nv, float(dv), tau, (rl, 0.0, pl), (rr, 0.0, pr)))
+    announce("slab edge tubes", [t.nx for t in tubes])
+    b = make_batch(tubes)
+    b.set_state_macro(*tube_fields(tubes))
+    b.step(12)
+    assert (b.tube_flags() == 0).all()
+    for t, U in zip(tubes, b.read_moments()):
+        err = moment_errors(U, oracle_tube(t, 12).U, 1)
+        assert err.max() < TOL32, (t.nx, err)

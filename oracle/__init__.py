@@ -60,6 +60,7 @@ def _lib():
         lib.or_maxwellian.argtypes = [vp, dp, dp]
         lib.or_equilibrium.argtypes = [vp, dp, dp]
         lib.or_muscl.argtypes = [vp, dp, d, P(i)]
+        lib.or_muscl_substep.argtypes = [vp, dp, d]
         lib.mlp_nparam.restype = i
         lib.mlp_forward.argtypes = [dp, dp, dp, i]
         lib.mlp_loss_grad.argtypes = [dp, dp, dp, i, dp]
@@ -189,6 +190,14 @@ class Oracle:
         if st:
             raise OracleError(st, "muscl")
         return U, ns.value
+
+    def muscl_substep(self, U, h):
+        """one sub-step of length h with the speeds of U (no sub-cycling)"""
+        U = np.array(U, dtype=np.float64).reshape(self.nm, self.nc).copy()
+        st = _lib().or_muscl_substep(self._h, _dp(U), float(h))
+        if st:
+            raise OracleError(st, "muscl_substep")
+        return U
 
 
 # ------------------------------------------------------ closure network (FP64)

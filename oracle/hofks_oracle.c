@@ -298,6 +298,29 @@ static int muscl_flux(const or_state *S, const double *U, int j, int a,
   return OR_OK;
 }
 
+/* one forward-Euler sub-step of eq. (discmom) of length dts with the speeds
+ * alpha; U (nm x nc) is read, Unew written */
+static int muscl_substep(const or_state *S, const double *U, double *Unew,
+                         const double *alpha, double dts) {
+  int nm = S->nm, nc = S->nc, d = S->d, st = OR_OK;
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < nc; ++j) {
+    double div[5] = {0, 0, 0, 0, 0}, pr[5], pl[5];
+    for (int a = 0; a < d; ++a) {
+      int l1 = muscl_flux(S, U, j, a, 0, alpha[a], pr);
+      int l2 = muscl_flux(S, U, j, a, -1, alpha[a], pl);
+      if (l1 || l2) {
+#pragma omp atomic write
+        st = OR_ENONPHYS;
+      }
+      for (int r = 0; r < nm; ++r) div[r] += pr[r] - pl[r];
+    }
+    for (int r = 0; r < nm; ++r)
+      Unew[r * nc + j] = U[r * nc + j] - dts / S->dx * div[r];
+  }
+  return st;
+}
+
 /* eq. (discmom) applied with s sub-steps over dt; U is nm x nc, updated */
 static int muscl_solve(const or_state *S, double *U, double dt, int *nsub) {
   int nm = S->nm, nc = S->nc, d = S->d;
@@ -315,21 +338,7 @@ static int muscl_solve(const or_state *S, double *U, double dt, int *nsub) {
   for (int it = 0; it < s && st == OR_OK; ++it) {
     if (it > 0) st = lf_speeds(S, U, alpha);
     if (st) break;
-#pragma omp parallel for schedule(static)
-    for (int j = 0; j < nc; ++j) {
-      double div[5] = {0, 0, 0, 0, 0}, pr[5], pl[5];
-      for (int a = 0; a < d; ++a) {
-        int l1 = muscl_flux(S, U, j, a, 0, alpha[a], pr);
-        int l2 = muscl_flux(S, U, j, a, -1, alpha[a], pl);
-        if (l1 || l2) {
-#pragma omp atomic write
-          st = OR_ENONPHYS;
-        }
-        for (int r = 0; r < nm; ++r) div[r] += pr[r] - pl[r];
-      }
-      for (int r = 0; r < nm; ++r)
-        Unew[r * nc + j] = U[r * nc + j] - dts / S->dx * div[r];
-    }
+    st = muscl_substep(S, U, Unew, alpha, dts);
     memcpy(U, Unew, sizeof(double) * nm * nc);
   }
   free(Unew);
@@ -651,4 +660,16 @@ int or_equilibrium(const or_state *S, const double *U, double *E) {
 }
 int or_muscl(const or_state *S, double *U, double dt, int *nsub) {
   return muscl_solve(S, U, dt, nsub);
+}
+/* a single sub-step of length h with the speeds of U (no sub-cycling) */
+int or_muscl_substep(const or_state *S, double *U, double h) {
+  double alpha[3];
+  int st = lf_speeds(S, U, alpha);
+  if (st) return st;
+  double *Unew = (double *)malloc(sizeof(double) * S->nm * S->nc);
+  if (!Unew) return OR_EINVAL;
+  st = muscl_substep(S, U, Unew, alpha, h);
+  memcpy(U, Unew, sizeof(double) * S->nm * S->nc);
+  free(Unew);
+  return st;
 }

@@ -374,3 +374,122 @@ def test_mlp_zero_weights_give_bias_and_adam_descends():
         _, g = mlp_loss_grad(p, x, t)
         mlp_adam(p, g, m, v, 1e-3, k)
     assert mlp_loss_grad(p, x, t)[0] < 0.7 * l0
+
+
+def _torch_net(p):
+    """the closure network as a float64 torch.nn composition, with its
+    parameters taken from the documented flat layout (W row-major (out, in),
+    then b, for 37 -> 64 -> 64 -> 64 -> 4)"""
+    import torch
+    sizes = [(37, 64), (64, 64), (64, 64), (64, 4)]
+    layers, o = [], 0
+    for li, (nin, nout) in enumerate(sizes):
+        lin = torch.nn.Linear(nin, nout, dtype=torch.float64)
+        with torch.no_grad():
+            lin.weight.copy_(torch.from_numpy(p[o:o + nin * nout].reshape(nout, nin)))
+            o += nin * nout
+            lin.bias.copy_(torch.from_numpy(p[o:o + nout]))
+            o += nout
+        layers.append(lin)
+        if li < 3:
+            layers.append(torch.nn.Tanh())
+    assert o == p.size
+    return torch.nn.Sequential(*layers)
+
+
+def _torch_flat_grad(net):
+    import torch
+    return torch.cat([torch.cat([l.weight.grad.reshape(-1), l.bias.grad])
+                      for l in net if isinstance(l, torch.nn.Linear)]).numpy()
+
+
+def test_mlp_forward_and_gradient_match_torch_float64():
+    """forward pass, MSE loss and its gradient against torch.nn (Linear, Tanh)
+    in float64 with autograd: a transposed weight layout, a wrong activation
+    derivative or a wrong loss scale fails here"""
+    import torch
+    from oracle import mlp_forward, mlp_loss_grad, mlp_nparam
+    rng = np.random.default_rng(21)
+    p = 0.25 * rng.standard_normal(mlp_nparam())
+    x = rng.standard_normal((33, 37))
+    t = rng.standard_normal((33, 4))
+    net = _torch_net(p)
+    xt = torch.from_numpy(x)
+    y = net(xt)
+    np.testing.assert_allclose(mlp_forward(p, x), y.detach().numpy(), rtol=1e-12, atol=1e-13)
+    loss_t = torch.nn.functional.mse_loss(y, torch.from_numpy(t))
+    loss_t.backward()
+    loss, g = mlp_loss_grad(p, x, t)
+    assert abs(loss - loss_t.item()) <= 1e-13 * abs(loss_t.item())
+    gt = _torch_flat_grad(net)
+    np.testing.assert_allclose(g, gt, rtol=1e-11, atol=1e-14 * np.abs(gt).max())
+
+
+def test_mlp_adam_matches_torch_optim_adam():
+    """five Adam steps (bias-corrected, Kingma & Ba) against torch.optim.Adam
+    in float64 on the same gradients"""
+    import torch
+    from oracle import mlp_adam, mlp_loss_grad, mlp_nparam
+    rng = np.random.default_rng(22)
+    n = mlp_nparam()
+    p = 0.3 * rng.standard_normal(n)
+    x = rng.standard_normal((40, 37))
+    t = rng.standard_normal((40, 4))
+    pt = torch.from_numpy(p.copy()).requires_grad_(True)
+    opt = torch.optim.Adam([pt], lr=3e-3, betas=(0.85, 0.995), eps=1e-7)
+    m, v = np.zeros(n), np.zeros(n)
+    po = p.copy()
+    for k in range(1, 6):
+        _, g = mlp_loss_grad(po, x, t)
+        mlp_adam(po, g, m, v, 3e-3, k, b1=0.85, b2=0.995, eps=1e-7)
+        opt.zero_grad()
+        pt.grad = torch.from_numpy(mlp_loss_grad(pt.detach().numpy().copy(), x, t)[1])
+        opt.step()
+        np.testing.assert_allclose(po, pt.detach().numpy(), rtol=1e-13, atol=1e-15)
+
+
+# ---------------------------------------------- sub-steps and eq. (Time2)
+def _lf_speeds(U, d):
+    """global Lax-Friedrichs speeds max_j |u_a| + c, c = sqrt(gamma p / rho)"""
+    rho = U[0]
+    u = U[1:1 + d] / rho
+    p = (2.0 * U[d + 1] - rho * (u ** 2).sum(0)) / d
+    c = np.sqrt((d + 2.0) / d * p / rho)
+    return np.array([(np.abs(u[a]) + c).max() for a in range(d)])
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_substeps_meet_time2_at_tn_and_reevaluate_speeds(d):
+    """eq. (Time2): the MUSCL solve is stable for dt_s sum_a alpha_a <= dx / 2.
+    The lattice dt = dx/dv is larger, so the oracle sub-cycles (reading R11):
+    s is the smallest count that meets the bound with the speeds of U^n
+    (computed here independently), the sub-steps are equal, and each takes
+    the Lax-Friedrichs speeds of its own state -- replayed here one sub-step
+    at a time, the solve must equal the s-step solve bit for bit.  The bound
+    is met at the first sub-step only; the largest ratio reached at a later
+    sub-step is printed (R11 fixes s from U^n)."""
+    if d == 1:
+        nx, dv = 200, 0.25
+        rho, u, th = W.sod_tube(nx)
+        o = Oracle(1, (nx,), 1.0 / nx, 64, dv, bc=(1,), tau=0.0)
+    else:
+        nx, dv = 48, 0.5
+        rho, u, th = W.perturbed_gas(nx, 2, 0.2, 0.1, 4, (61, 62))
+        u = 0.2 * np.stack([np.sin(np.arange(nx * nx) * 0.07), np.cos(np.arange(nx * nx) * 0.05)])
+        o = Oracle(2, (nx, nx), 1.0 / nx, 16, dv, tau=0.0)
+    o.init_macro(rho, u, th)
+    U0 = o.U
+    dt, dx = o.dt, o.dx
+    Us, s = o.muscl(U0, dt)
+    a0 = _lf_speeds(U0, d).sum()
+    assert s > 1
+    assert (dt / s) * a0 <= 0.5 * dx * (1 + 1e-15)
+    assert (dt / (s - 1)) * a0 > 0.5 * dx
+    U = U0.copy()
+    cfl = []
+    for i in range(s):
+        cfl.append((dt / s) * _lf_speeds(U, d).sum() / dx)
+        U = o.muscl_substep(U, dt / s)
+    np.testing.assert_array_equal(U, Us)
+    print(f"d={d}: s={s}, dt_s sum alpha / dx at the sub-steps: first {cfl[0]:.4f}, "
+          f"largest {max(cfl):.4f}")

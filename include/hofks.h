@@ -116,6 +116,21 @@ hofks_status hofks_write_state(hofks_ctx *ctx, const void *host, size_t bytes);
  * the steps taken so far.  Synchronous. */
 hofks_status hofks_read_counters(hofks_ctx *ctx, int *substeps, long *steps);
 
+/* Euler sub-steps run so far by the persistent tail of the Euler solve (the
+ * sub-steps beyond the per-sub-step launches of a step; see
+ * hofks_set_euler_launches), counted since the state was set.  Synchronous.
+ * Always 0 for a batch. */
+hofks_status hofks_read_tail_substeps(hofks_ctx *ctx, long *n);
+
+/* The Euler solve of a step (section 4.3.2, sub-cycled) is launched as k
+ * single-sub-step kernels followed by a persistent kernel that runs any
+ * further sub-steps with an in-kernel barrier between them.  k = 0 (the
+ * default) takes k = (sub-steps of the last step seen at a synchronising
+ * call) + 1; k >= 1 fixes it, so that k = 1 runs every sub-step after the
+ * first in the persistent kernel.  Results do not depend on k.  HOFKS_EINVAL
+ * for k < 0 or a batch. */
+hofks_status hofks_set_euler_launches(hofks_ctx *ctx, int k);
+
 /* Per-kernel timing with hipEvents recorded around each launch group of
  * hofks_step: group 0 = the Euler sub-steps (on the library's auxiliary
  * stream, beside group 1), 1 = the kinetic kernel (relaxation, shift, moment

@@ -22,6 +22,7 @@ SYMBOLS = [
     "hofks_closure_enable", "hofks_closure_disable", "hofks_closure_snapshot", "hofks_closure_stats",
     "hofks_mlp_nparam", "hofks_mlp_packed_bytes", "hofks_mlp_pack", "hofks_mlp_forward",
     "hofks_mlp_grad", "hofks_mlp_adam", "hofks_state_bytes", "hofks_read_state", "hofks_write_state",
+    "hofks_read_tail_substeps", "hofks_set_euler_launches",
 ]
 
 
@@ -57,6 +58,8 @@ def lib():
     L.hofks_read_f.argtypes = [vp, dp, sz]
     L.hofks_read_counters.argtypes = [vp, P(i), P(ctypes.c_long)]
     L.hofks_kernel_timing.argtypes = [vp, i, dp, P(i)]
+    L.hofks_read_tail_substeps.argtypes = [vp, P(ctypes.c_long)]
+    L.hofks_set_euler_launches.argtypes = [vp, i]
     L.hofks_batch_workspace_size.argtypes = [P(GridDesc), i, P(sz)]
     L.hofks_batch_create.argtypes = [P(GridDesc), dp, i, vp, sz, vp, P(vp)]
     L.hofks_batch_tube_flags.argtypes = [vp, P(i)]

@@ -263,6 +263,7 @@ struct hofks_ctx {
   double tau;
   int s_cap;
   int s_known;  // Euler sub-steps of the last step seen by the host
+  int euler_k;  // > 0: per-sub-step Euler launches before the tail (0: s_known + 1)
   long steps;
   bool ready;
   int kng, kunr;  // kinetic kernel: wavefronts per block, loads issued ahead
@@ -527,7 +528,7 @@ hofks_status join_update(hofks_ctx* c, const StepArgs<T>& a) {
 template <int D, typename T>
 void launch_euler(hofks_ctx* c, const StepArgs<T>& a, hipStream_t st) {
   const Plan& P = c->P;
-  const int K = std::max(1, std::min(c->s_cap, c->s_known + 1));
+  const int K = std::max(1, std::min(c->s_cap, c->euler_k > 0 ? c->euler_k : c->s_known + 1));
   if constexpr (D == 2) {  // 16 x 16 LDS tiles
     const int ntx = (P.G.n[0] + ET - 1) / ET, nty = (P.G.n[1] + ET - 1) / ET;
     for (int i = 0; i < K; ++i)
@@ -1190,6 +1191,26 @@ hofks_status hofks_kernel_timing(hofks_ctx* c, int enable, double* ms, int* laun
   c->ev_marks.clear();
   c->ev_next = 0;
   c->timing = enable != 0;
+  return HOFKS_OK;
+}
+
+hofks_status hofks_read_tail_substeps(hofks_ctx* c, long* n) {
+  if (!c || !n) return HOFKS_EINVAL;
+  if (c->batch) {
+    *n = 0;
+    return HOFKS_OK;
+  }
+  int h[3] = {0, 0, 0};
+  HIPCHK(c, hipMemcpyAsync(h, c->flag, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *n = h[2];
+  return HOFKS_OK;
+}
+
+hofks_status hofks_set_euler_launches(hofks_ctx* c, int k) {
+  if (!c || k < 0) return HOFKS_EINVAL;
+  if (c->batch) return fmt_err(c->err, "not available for batches"), HOFKS_EINVAL;
+  c->euler_k = k;
   return HOFKS_OK;
 }
 

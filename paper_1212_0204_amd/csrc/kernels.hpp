@@ -566,6 +566,7 @@ __global__ __launch_bounds__(TPB) void k_euler(StepArgs<T> a, Geom G, int K) {
   bool over;
   const int s = substeps<D>(S, G, a.s_cap, &over);
   if (K >= s) return;  // the sub-step launches covered every sub-step
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.flag + 2, s - K);  // tail sub-steps run
   const double dts_dx = (G.dt / s) / G.dx;
   __shared__ double wmax[TPB / 64][ASTR];
   double alpha[3];

@@ -127,6 +127,18 @@ class Solver:
                     "read_counters")
         return s.value, n.value
 
+    def tail_substeps(self):
+        """Euler sub-steps run by the persistent tail since the state was set"""
+        n = ctypes.c_long(0)
+        self._check(_lib.lib().hofks_read_tail_substeps(self._h, ctypes.byref(n)),
+                    "read_tail_substeps")
+        return n.value
+
+    def set_euler_launches(self, k):
+        """single-sub-step Euler launches per step before the persistent tail
+        (0: automatic)"""
+        self._check(_lib.lib().hofks_set_euler_launches(self._h, int(k)), "set_euler_launches")
+
     def kernel_timing(self, enable=True):
         """(ms[4], launches[4]) of the Euler, kinetic, per-cell update and
         closure-network groups since the previous call; keeps recording

@@ -170,3 +170,60 @@ def test_slab_edge_tubes_match_oracle():
     for t, U in zip(tubes, b.read_moments()):
         err = moment_errors(U, oracle_tube(t, 12).U, 1)
         assert err.max() < TOL32, (t.nx, err)
+
+
+@gpu
+def test_full_batch_every_tube_8_steps():
+    """the 512-tube batch at full size: every tube against the oracle after 8
+    steps (1e-5 per moment); a tube may be left out only when both sides
+    find it non-physical"""
+    from tests.oracle_pool import run_tubes
+    tubes = W.batched_tubes()
+    announce("full batch, every tube", len(tubes), "tubes, 8 steps")
+    ref = run_tubes(tubes, 8)
+    b = make_batch(tubes)
+    b.set_state_macro(*tube_fields(tubes))
+    b.step(8)
+    flags = b.tube_flags()
+    Us = b.read_moments()
+    worst = 0.0
+    for i, (t, (Uo, bad)) in enumerate(zip(tubes, ref)):
+        assert bool(flags[i] & 1) == bool(bad), (i, t, int(flags[i]), bad)
+        if bad:
+            continue
+        err = moment_errors(Us[i], Uo, 1)
+        worst = max(worst, err.max())
+        assert err.max() < TOL32, (i, t, err)
+    print(f"worst moment error over {len(tubes)} tubes: {worst:.3e}; "
+          f"both sides non-physical: {int(sum(1 for r in ref if r[1]))}", flush=True)
+
+
+@gpu
+def test_full_batch_flags_agree_with_oracle():
+    """the non-physical tubes of the batch over the first 60 steps: for each
+    tube, the step at which the GPU flags it equals the step at which the
+    oracle first meets a non-physical state (raised during the step or left
+    in the moments it produces); a difference is reported with the tube's
+    cold-side resolution dv / sqrt(theta_min)"""
+    from tests.oracle_pool import run_tubes
+    steps = 60
+    tubes = W.batched_tubes()
+    announce("batch flags", len(tubes), "tubes,", steps, "steps")
+    ref = run_tubes(tubes, steps)
+    b = make_batch(tubes)
+    b.set_state_macro(*tube_fields(tubes))
+    first = np.zeros(len(tubes), dtype=int)
+    for n in range(1, steps + 1):
+        b.step(1)
+        fl = b.tube_flags()
+        new = (fl & 1).astype(bool) & (first == 0)
+        first[new] = n
+    oracle_first = np.array([r[1] for r in ref])
+    print("flagged (gpu, oracle):", int((first > 0).sum()), int((oracle_first > 0).sum()), flush=True)
+    diff = np.nonzero(first != oracle_first)[0]
+    for i in diff:
+        t = tubes[i]
+        res = t.dv / np.sqrt(min(t.left[2] / t.left[0], t.right[2] / t.right[0]))
+        print(f"tube {i}: gpu step {first[i]}, oracle step {oracle_first[i]}, nx {t.nx}, "
+              f"nv {t.nv}, tau {t.tau:.2e}, dv/sqrt(theta_min) {res:.2f}", flush=True)
+    assert len(diff) == 0

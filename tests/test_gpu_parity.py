@@ -327,3 +327,136 @@ def test_steps_in_one_call_equal_single_steps(d, n, nv, prec):
         runs.append((s.read_moments(), s.read_f()))
     assert np.array_equal(runs[0][0], runs[1][0])
     assert np.array_equal(runs[0][1], runs[1][1])
+
+
+# ------------------------------------------- relaxation weight lambda = 1/2
+def _lam_half_tau(dx, dv):
+    """tau with lambda = exp(-dt/tau) = 1/2 on the lattice dt = dx/dv, so that
+    the relaxed pieces carry half of U^{n+1}"""
+    return (dx / dv) / math.log(2.0)
+
+
+def _random_fields(d, nc, seed, amp=0.2):
+    rng = np.random.default_rng(seed)
+    return (1.0 + amp * rng.uniform(-1, 1, nc), 0.1 * rng.uniform(-1, 1, (d, nc)),
+            1.0 + amp * rng.uniform(-1, 1, nc))
+
+
+@gpu
+@pytest.mark.parametrize("d,n,nv,bc", [
+    (2, (70, 37), 16, (0, 0)),        # ragged x tile, several rows
+    (2, (131, 19), 12, (1, 0)),       # three x segments, outflow x
+    (3, (66, 9, 5), 12, (0, 1, 0)),   # ragged x and y row blocks
+    (3, (20, 12, 10), 8, (1, 1, 1)),
+])
+def test_precision_form_at_lambda_half(d, n, nv, bc):
+    """FP32 pieces where they carry half of U^{n+1} (lambda = 1/2): the FP32
+    relaxation and shift of the 2D and 3D kinetic kernels reach the moments;
+    1e-5 per moment and on f after 6 steps"""
+    dv = 0.5
+    dx = 1.0 / n[0]
+    tau = _lam_half_tau(dx, dv)
+    announce("fp32 lambda 1/2", d, n, nv, bc, f"tau={tau:.4g}")
+    nc = int(np.prod(n))
+    o, s = run_pair(d, n, dx, nv, dv, bc, tau, 6, _random_fields(d, nc, 43), precision=1)
+    assert abs(o.lam - 0.5) < 1e-12
+    err = moment_errors(s.read_moments(), o.U, d)
+    ef = rel_inf(s.read_f(), o.f)
+    print("fp32 lambda=1/2 moment errors", err, "f", ef)
+    assert err.max() < TOL32, err
+    assert ef < TOL32, ef
+
+
+@gpu
+@pytest.mark.parametrize("n,nv,bc", [((70, 10, 6), 10, (1, 1, 1)), ((30, 5, 4), 24, (0, 1, 0))])
+def test_3d_fp64_at_lambda_half(n, nv, bc):
+    """the 3D kinetic kernel (blocks of four y rows) in FP64 where the
+    relaxed pieces carry half of U^{n+1}: 1e-12"""
+    dv, dx = 0.5, 1.0 / n[0]
+    tau = _lam_half_tau(dx, dv)
+    announce("3d fp64 lambda 1/2", n, nv, bc)
+    o, s = run_pair(3, n, dx, nv, dv, bc, tau, 4, _random_fields(3, int(np.prod(n)), 47))
+    err = moment_errors(s.read_moments(), o.U, 3)
+    print("3d fp64 lambda=1/2 moment errors", err)
+    assert err.max() < TOL64, err
+    assert rel_inf(s.read_f(), o.f) < TOL64
+
+
+@gpu
+@pytest.mark.parametrize("lam", [0.0, 0.5])
+def test_gas3d_reduced_grid_fp32(lam):
+    """the 3D FP32 workload's velocity grid (24^3, dv = 1/2) and field recipe
+    on a 32^3 grid, 3 steps, against the oracle: with the workload's tau
+    (lambda ~ 1e-14, the Euler part dominates) and with lambda = 1/2"""
+    wl = W.GAS_3D
+    n = (32, 32, 32)
+    dx = 1.0 / 32
+    rho, u, th = W.perturbed_gas(32, 3, 0.1, 0.1, 4, (3, 33))
+    tau = _lam_half_tau(dx, wl.dv) if lam else wl.tau
+    announce("gas3d reduced 32^3 x 24^3 fp32", f"tau={tau:.4g}")
+    o, s = run_pair(3, n, dx, wl.nv, wl.dv, wl.bc, tau, 3, (rho, u, th), precision=1)
+    err = moment_errors(s.read_moments(), o.U, 3)
+    ef = rel_inf(s.read_f(), o.f)
+    print(f"gas3d 32^3 fp32 lambda={o.lam:.3g} moment errors", err, "f", ef)
+    assert err.max() < TOL32, err
+    assert ef < TOL32, ef
+
+
+# ------------------------------------------------ persistent Euler tail
+@gpu
+@pytest.mark.parametrize("d,n,nv,bc,tau", [
+    (1, (130,), 24, (1,), 1e-2),
+    (2, (70, 37), 16, (0, 0), 1e-3),
+    (2, (48, 40), 16, (1, 1), 5e-3),
+    (3, (23, 9, 11), 8, (0, 1, 0), 1e-2),
+])
+def test_euler_tail_every_substep(d, n, nv, bc, tau):
+    """one single-sub-step Euler launch per step: every further sub-step runs
+    in the persistent kernel (grid barrier, per-block speed maxima); the
+    library's tail counter shows that it ran; 1e-12 against the oracle"""
+    announce("euler tail", d, n, nv, bc, tau)
+    from paper_1212_0204_amd import Solver
+    nc = int(np.prod(n))
+    fields = W.sod_tube(n[0]) if d == 1 else _random_fields(d, nc, 53)
+    dx = 1.0 / n[0]
+    o = Oracle(d, n, dx, nv, 0.5, bc=bc, tau=tau)
+    s = Solver(d, n, dx, nv, 0.5, bc=bc, tau=tau)
+    s.set_euler_launches(1)
+    o.init_macro(*fields)
+    s.set_state_macro(*fields)
+    expect = 0
+    for _ in range(5):  # the tail runs every sub-step after the first
+        o.step(1)
+        expect += o.substeps - 1
+    s.step(5)
+    tail = s.tail_substeps()
+    assert tail == expect and tail > 0, (tail, expect)
+    err = moment_errors(s.read_moments(), o.U, d)
+    assert err.max() < TOL64, err
+    assert rel_inf(s.read_f(), o.f) < TOL64
+    assert s.counters()[0] == o.substeps
+
+
+@gpu
+def test_disk_substeps_grow_within_one_call():
+    """a disk-shaped Riemann problem (section 5, 2D Sod geometry) on a 40^2
+    periodic grid, lambda ~ 0.29: the sub-step count jumps from 12 to 18
+    at the second step, inside one step call, beyond the one spare launch,
+    so the persistent tail runs the extra sub-steps; 1e-12 after 8 steps"""
+    n = (40, 40)
+    dx = 2.0 / 40
+    rho, u, th = W.disk_2d(40, 2.0, (1.0, 1.0), 0.3)
+    announce("disk 40^2 substep growth")
+    from paper_1212_0204_amd import Solver
+    o = Oracle(2, n, dx, 16, 0.5, bc=(0, 0), tau=0.08)
+    s = Solver(2, n, dx, 16, 0.5, bc=(0, 0), tau=0.08)
+    o.init_macro(rho, u, th)
+    s.set_state_macro(rho, u, th)
+    o.step(8)
+    s.step(8)
+    tail = s.tail_substeps()
+    print("tail sub-steps", tail)
+    assert tail >= 5
+    err = moment_errors(s.read_moments(), o.U, 2)
+    assert err.max() < TOL64, err
+    assert rel_inf(s.read_f(), o.f) < TOL64

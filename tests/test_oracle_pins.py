@@ -493,3 +493,18 @@ def test_substeps_meet_time2_at_tn_and_reevaluate_speeds(d):
     np.testing.assert_array_equal(U, Us)
     print(f"d={d}: s={s}, dt_s sum alpha / dx at the sub-steps: first {cfl[0]:.4f}, "
           f"largest {max(cfl):.4f}")
+
+
+def test_tube_pool_matches_in_process_oracle():
+    """the worker pool the batch tests use gives the in-process oracle's
+    moments bit for bit (one thread per tube either way)"""
+    from oracle import set_threads
+    from tests.oracle_pool import run_tube, run_tubes
+    tubes = W.batched_tubes(count=6, seed=99, nx_range=(200, 400))
+    res = run_tubes(tubes, 3, workers=2)
+    for t, (U, bad) in zip(tubes, res):
+        U1, bad1 = run_tube((t, 3))
+        assert bad == bad1
+        if not bad:
+            np.testing.assert_array_equal(U, U1)
+    set_threads(os.cpu_count() or 1)

@@ -61,6 +61,7 @@ def _lib():
         lib.or_equilibrium.argtypes = [vp, dp, dp]
         lib.or_muscl.argtypes = [vp, dp, d, P(i)]
         lib.or_muscl_substep.argtypes = [vp, dp, d]
+        lib.or_weno.argtypes = [vp, dp, d, P(i)]
         lib.mlp_nparam.restype = i
         lib.mlp_forward.argtypes = [dp, dp, dp, i]
         lib.mlp_loss_grad.argtypes = [dp, dp, dp, i, dp]
@@ -78,7 +79,8 @@ class Oracle:
     """One grid + velocity set + tau, stepped with the plain FP64 scheme.
 
     ``scheme``: 0 HOFKS (section 4.3), 1 FKS with the Euler coupling removed
-    (U_E := U_M), 2 HOFKS with the Van Leer limiter replaced by phi == 1.
+    (U_E := U_M), 2 HOFKS with the Van Leer limiter replaced by phi == 1,
+    3 HOFKS with the WENO Euler solve (section 4.3.3).
     ``bc`` per axis: 0 periodic, 1 outflow (zero gradient).
     """
 
@@ -189,6 +191,15 @@ class Oracle:
         st = _lib().or_muscl(self._h, _dp(U), float(dt), ctypes.byref(ns))
         if st:
             raise OracleError(st, "muscl")
+        return U, ns.value
+
+    def weno(self, U, dt):
+        """the WENO solve of scheme 3 over dt: (U after dt, sub-steps)"""
+        U = np.array(U, dtype=np.float64).reshape(self.nm, self.nc).copy()
+        ns = ctypes.c_int(0)
+        st = _lib().or_weno(self._h, _dp(U), float(dt), ctypes.byref(ns))
+        if st:
+            raise OracleError(st, "weno")
         return U, ns.value
 
     def muscl_substep(self, U, h):

@@ -39,8 +39,81 @@ def _cell_tuples(n):
     return out
 
 
+def _cell_average_quadratic(offsets):
+    """coefficients (a, b, c) of p(xi) = a + b xi + c xi^2 as linear maps of
+    the cell averages of p over the cells at `offsets` (xi in cell widths,
+    cell m = [m - 1/2, m + 1/2]): the 3 x 3 inverse of the averaging map"""
+    A = mp.matrix(3, 3)
+    for row, m in enumerate(offsets):
+        A[row, 0] = 1
+        A[row, 1] = mp.mpf(m)
+        A[row, 2] = mp.mpf(m) ** 2 + mp.mpf(1) / 12
+    return A ** -1
+
+
+def _reconstruction_at(xi, offsets):
+    """row vector giving p(xi) from the averages of a polynomial of degree
+    len(offsets) - 1 over the cells at `offsets`"""
+    k = len(offsets)
+    A = mp.matrix(k, k)
+    for row, m in enumerate(offsets):
+        for pw in range(k):
+            # average of xi^pw over [m - 1/2, m + 1/2]
+            A[row, pw] = ((m + mp.mpf(1) / 2) ** (pw + 1) - (m - mp.mpf(1) / 2) ** (pw + 1)) / (pw + 1)
+    Ainv = A ** -1
+    return [sum(xi ** pw * Ainv[pw, col] for pw in range(k)) for col in range(k)]
+
+
+class Weno5:
+    """fifth-order WENO (Jiang and Shu) from its definitions: three quadratic
+    candidates matching cell averages on the stencils {-2..0}, {-1..1},
+    {0..2} around a cell, linear weights that recombine them into the quartic
+    through all five averages, and smoothness indicators
+    sum_l int (d^l p / dxi^l)^2 over the cell (l = 1, 2), eps = 1e-6"""
+
+    STENCILS = [(-2, -1, 0), (-1, 0, 1), (0, 1, 2)]
+
+    def __init__(self):
+        self.eps = mp.mpf("1e-6")
+        self.coef = [_cell_average_quadratic(st) for st in self.STENCILS]
+        self.cand = {}
+        self.lin = {}
+        for side in (1, -1):
+            xi = mp.mpf(side) / 2
+            rows = [_reconstruction_at(xi, st) for st in self.STENCILS]
+            big = _reconstruction_at(xi, (-2, -1, 0, 1, 2))
+            # d with sum_r d_r rows_r == big on the five cells (the first,
+            # third and fifth columns determine d; the others must agree)
+            M = mp.matrix(5, 3)
+            for r, st in enumerate(self.STENCILS):
+                for c, m in enumerate(st):
+                    M[m + 2, r] = rows[r][c]
+            Msub = mp.matrix(3, 3)
+            for i, row in enumerate((0, 2, 4)):
+                for c in range(3):
+                    Msub[i, c] = M[row, c]
+            d = mp.lu_solve(Msub, mp.matrix([big[0], big[2], big[4]]))
+            assert max(abs((M * d)[i] - big[i]) for i in range(5)) < mp.mpf("1e-40")
+            self.cand[side] = rows
+            self.lin[side] = [d[i] for i in range(3)]
+
+    def face(self, v, side):
+        """value at the face (side +1: right, -1: left) of the middle cell of
+        v = averages of cells -2..2"""
+        q, w = [], []
+        for r, st in enumerate(self.STENCILS):
+            vals = [v[m + 2] for m in st]
+            q.append(sum(c * x for c, x in zip(self.cand[side][r], vals)))
+            ab = self.coef[r] * mp.matrix(vals)
+            b, c = ab[1], ab[2]
+            beta = b * b + c * c / 3 + 4 * c * c  # int p'^2 + int p''^2 over the cell
+            w.append(self.lin[side][r] / (self.eps + beta) ** 2)
+        return sum(wi * qi for wi, qi in zip(w, q)) / sum(w)
+
+
 class Brute:
-    """scheme 0 HOFKS, 1 FKS (U_E := U_M), 2 HOFKS with phi == 1"""
+    """scheme 0 HOFKS, 1 FKS (U_E := U_M), 2 HOFKS with phi == 1, 3 HOFKS
+    with the WENO Euler solve (three-stage SSP Runge-Kutta, CFL 0.4)"""
 
     def __init__(self, d, n, dx, nv, dv, bc, tau, scheme=0):
         self.d, self.n, self.bc, self.scheme = d, tuple(n), tuple(bc), scheme
@@ -61,6 +134,7 @@ class Brute:
         self.set_tau(tau)
         self.f = None
         self.U = None
+        self.weno = Weno5() if scheme == 3 else None
 
     # --------------------------------------------------------------- set-up
     def set_tau(self, tau):
@@ -172,7 +246,53 @@ class Brute:
                        (sp - sm) / 4)
         return psi
 
+    def weno_rhs(self, Us, alpha):
+        """L(U) = -(1/dx) sum_a (fh_{j+1/2} - fh_{j-1/2}); fh = WENO value of
+        (F + alpha U)/2 from the left of the face + WENO value of
+        (F - alpha U)/2 from the right of the face"""
+        nm = self.d + 2
+        out = []
+        for cell in self.cells:
+            div = [mp.mpf(0)] * nm
+            for a in range(self.d):
+                idx = {o: self._shifted(cell, a, o) for o in range(-3, 4)}
+                F = {o: self.flux(Us[i], a)[0] for o, i in idx.items()}
+                for r in range(nm):
+                    fp = {o: (F[o][r] + alpha[a] * Us[idx[o]][r]) / 2 for o in idx}
+                    fm = {o: (F[o][r] - alpha[a] * Us[idx[o]][r]) / 2 for o in idx}
+                    right = self.weno.face([fp[o] for o in range(-2, 3)], 1) + \
+                        self.weno.face([fm[o] for o in range(-1, 4)], -1)
+                    left = self.weno.face([fp[o] for o in range(-3, 2)], 1) + \
+                        self.weno.face([fm[o] for o in range(-2, 3)], -1)
+                    div[r] += right - left
+            out.append([-x / self.dx for x in div])
+        return out
+
     def euler(self, Us, dt):
+        if self.scheme == 3:
+            return self.euler_weno(Us, dt)
+        return self.euler_muscl(Us, dt)
+
+    def euler_weno(self, Us, dt):
+        """s = max(1, ceil(dt sum alpha / (0.4 dx))) sub-steps, each by the
+        Shu-Osher three-stage SSP Runge-Kutta method with the speeds of the
+        sub-step's initial state"""
+        alpha = self.speeds(Us)
+        s = max(1, int(mp.ceil(dt * sum(alpha) / (mp.mpf(2) / 5 * self.dx))))
+        h = dt / s
+        nm = self.d + 2
+        for it in range(s):
+            if it:
+                alpha = self.speeds(Us)
+            L0 = self.weno_rhs(Us, alpha)
+            U1 = [[u[r] + h * l[r] for r in range(nm)] for u, l in zip(Us, L0)]
+            L1 = self.weno_rhs(U1, alpha)
+            U2 = [[(3 * u[r] + u1[r] + h * l[r]) / 4 for r in range(nm)] for u, u1, l in zip(Us, U1, L1)]
+            L2 = self.weno_rhs(U2, alpha)
+            Us = [[(u[r] + 2 * (u2[r] + h * l[r])) / 3 for r in range(nm)] for u, u2, l in zip(Us, U2, L2)]
+        return Us, s
+
+    def euler_muscl(self, Us, dt):
         """eq. (discmom) over dt in s equal sub-steps"""
         alpha = self.speeds(Us)
         s = max(1, int(mp.ceil(2 * dt * sum(alpha) / self.dx)))

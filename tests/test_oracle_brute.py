@@ -8,7 +8,11 @@ it solves the normal equations of eq. (minimMax) and (minim_full) by LU in
 1D 5 cells x 5 velocities and 2D 3 x 3 cells x 3^2 velocities, three steps
 from a non-equilibrium start, every scheme, tau and boundary, the oracle must
 agree to 1e-13 normwise on U and on f.  A dropped term, a wrong sign or
-index, or a transposed operand in the oracle fails here.
+index, or a transposed operand in the oracle fails here.  For the WENO
+solve (scheme 3) the brute force derives the candidate reconstructions, the
+linear weights and the smoothness indicators from their definitions (cell
+averages of quadratics, the quartic through five averages, integrals of the
+squared derivatives) instead of typing their coefficients.
 """
 import math
 
@@ -54,7 +58,7 @@ def _compare(o, b, d):
     return max(errU), errf
 
 
-@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
 @pytest.mark.parametrize("tau", [0.0, 1e-2, 1.0, math.inf])
 @pytest.mark.parametrize("n,bc", CASES_1D + CASES_2D)
 def test_oracle_matches_brute_force(n, bc, tau, scheme):

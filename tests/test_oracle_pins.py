@@ -266,6 +266,87 @@ def test_tau_zero_sod_converges_to_exact_riemann():
     assert errs[2] < 6e-3
 
 
+# --------------------------------------- section 4.3.3: a WENO Euler solve
+def test_weno_uniform_state_is_steady():
+    o = Oracle(2, (7, 5), 0.1, 8, 0.5, scheme=3)
+    U = np.tile(np.array([[1.3], [0.2], [-0.4], [2.0]]), (1, 35))
+    Un, ns = o.weno(U, 0.05)
+    assert ns >= 1
+    np.testing.assert_allclose(Un, U, rtol=1e-15, atol=1e-15)
+
+
+def _weno_advection_errors(sizes, dt_of):
+    errs = []
+    for nx in sizes:
+        x = (np.arange(nx) + 0.5) / nx
+        rho = 1.0 + 0.2 * np.sin(2 * np.pi * x)
+        o = Oracle(1, (nx,), 1.0 / nx, 8, 0.5, scheme=3)
+        U = np.stack([rho, rho, 0.5 * rho + 0.5])  # u = 1, p = 1, gamma = 3
+        t, T = 0.0, 0.25
+        h = dt_of(nx)
+        while t < T - 1e-15:
+            step = min(h, T - t) if h else T - t
+            U, _ = o.weno(U, step)
+            t += step
+        errs.append(np.abs(U[0] - (1.0 + 0.2 * np.sin(2 * np.pi * (x - T)))).mean())
+    return np.array(errs)
+
+
+def test_weno_smooth_advection_fifth_order_in_space():
+    """smooth density advected at uniform velocity and pressure: with
+    dt ~ dx^(5/3) the third-order Runge-Kutta error is O(dx^5), so the
+    fifth-order WENO reconstruction shows its spatial order (L1 rate > 4.5;
+    a wrong linear weight or candidate coefficient leaves <= 3)"""
+    errs = _weno_advection_errors((32, 64, 128), lambda nx: 0.4 * (1.0 / nx) ** (5.0 / 3.0))
+    rates = np.log2(errs[:-1] / errs[1:])
+    assert rates.min() > 4.5, (errs, rates)
+
+
+def test_weno_at_its_own_cfl_is_high_order():
+    """the same problem in one call (the solver's own sub-steps at CFL 0.4):
+    still well above MUSCL's second order (rate > 4)"""
+    errs = _weno_advection_errors((32, 64, 128), lambda nx: None)
+    rates = np.log2(errs[:-1] / errs[1:])
+    assert rates.min() > 4.0, (errs, rates)
+
+
+def test_weno_substeps_from_the_reduced_cfl():
+    """s is the smallest count with dt_s sum_a alpha_a <= 0.4 dx at t^n (a
+    CFL tighter than MUSCL's 1/2, section 4.3.3)"""
+    nx = 200
+    rho, u, th = W.sod_tube(nx)
+    o = Oracle(1, (nx,), 1.0 / nx, 64, 0.25, bc=(1,), tau=0.0, scheme=3)
+    o.init_macro(rho, u, th)
+    U0 = o.U
+    _, s = o.weno(U0, o.dt)
+    a0 = _lf_speeds(U0, 1).sum()
+    assert (o.dt / s) * a0 <= 0.4 * o.dx * (1 + 1e-15)
+    assert (o.dt / (s - 1)) * a0 > 0.4 * o.dx
+
+
+def test_tau_zero_sod_weno_converges_to_exact_riemann():
+    """tau = 0 with the WENO Euler solve: the L1 density error against the
+    exact Riemann solution (gamma = 3) decreases under refinement and stays
+    below the MUSCL scheme's on every grid"""
+    left, right = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    for nx in (100, 200, 400):
+        errs = {}
+        for scheme in (0, 3):
+            rho, u, th = W.sod_tube(nx)
+            o = Oracle(1, (nx,), 1.0 / nx, 16, 0.25 * 400 / nx, bc=(1,), tau=0.0, scheme=scheme)
+            o.init_macro(rho, u, th)
+            t_end = 0.16
+            o.step(int(round(t_end / o.dt)))
+            x = (np.arange(nx) + 0.5) / nx
+            rex, _, _ = XR.solution(left, right, 3.0, x, t_end)
+            errs[scheme] = np.abs(o.U[0] - rex).mean()
+        assert errs[3] < errs[0], (nx, errs)
+        if nx == 100:
+            e100 = errs[3]
+        if nx == 400:
+            assert errs[3] < 0.5 * e100 and errs[3] < 5e-3, (e100, errs)
+
+
 def test_exact_riemann_solver_textbook_sod():
     """the exact solver itself: Sod's problem at gamma = 1.4 against the
     textbook star state stored in tests/golden (5 digits)."""
@@ -279,15 +360,17 @@ def test_exact_riemann_solver_textbook_sod():
     assert abs(ps - vals["p_star"][0]) < 5e-6 and abs(us - vals["u_star"][0]) < 5e-6
 
 
-def test_mirror_symmetry_odd_velocity_set():
+@pytest.mark.parametrize("scheme", [0, 3])
+def test_mirror_symmetry_odd_velocity_set(scheme):
     """odd n_v gives a symmetric velocity set; mirrored data stay mirrored
-    (pins the orientation of the shift, fluxes and slopes)."""
+    (pins the orientation of the shift, fluxes and slopes; scheme 3: of the
+    upwind-biased WENO stencils)."""
     nx, nv = 60, 15
     x = (np.arange(nx) + 0.5) / nx
     rho = np.where(np.abs(x - 0.5) < 0.2, 1.0, 0.3) + 0.1 * x * (1 - x)
     u = (0.3 * np.sin(2 * np.pi * x))[None, :]  # odd about the centre
     th = np.where(np.abs(x - 0.5) < 0.2, 1.0, 0.7)
-    o = Oracle(1, (nx,), 1 / nx, nv, 8.0 / nv, bc=(1,), tau=3e-3)
+    o = Oracle(1, (nx,), 1 / nx, nv, 8.0 / nv, bc=(1,), tau=3e-3, scheme=scheme)
     o.init_macro(rho, u, th)
     o.step(5)
     U = o.U

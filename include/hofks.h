@@ -62,7 +62,11 @@ typedef struct {
   double dv;        /* velocity step; dt = dx / dv                            */
   int bc[3];        /* per axis: 0 periodic, 1 outflow (zero gradient)        */
   int precision;    /* 0: FP64 pieces; 1: FP32 pieces, FP64 compensated sums  */
-  int scheme;       /* 0 HOFKS; 1 FKS (U_E := U_M); 2 HOFKS with phi == 1     */
+  int scheme;       /* 0 HOFKS; 1 FKS (U_E := U_M); 2 HOFKS with phi == 1;
+                       3 HOFKS with the WENO Euler solve (section 4.3.3:
+                       WENO5 of the Lax-Friedrichs split flux, three-stage
+                       SSP Runge-Kutta, CFL 0.4 instead of eq. (Time2)'s 1/2;
+                       single grids only, not the closure form)              */
 } hofks_grid_desc;
 
 /* Bytes of device workspace a context with this descriptor needs. */

@@ -59,6 +59,7 @@ __device__ __forceinline__ Geom tube_geom(const TubeDev& T) {
   G.lam = T.lam;
   G.mu = T.mu;
   G.gam = T.gam;
+  G.sfac = 2.0;
   return G;
 }
 

@@ -28,6 +28,7 @@
 #include "kinetic2w.hpp"
 #include "kinetic3d.hpp"
 #include "mlp.hpp"
+#include "weno.hpp"
 
 using namespace hofks;
 
@@ -44,7 +45,7 @@ struct Plan {
   size_t lds;
   int RS;  // record stride (values)
   // workspace offsets (bytes)
-  size_t off_g[2], off_U[2], off_UE[2], off_rec[2], off_vt, off_cf, off_part, off_slots,
+  size_t off_g[2], off_U[2], off_UE[4], off_rec[2], off_vt, off_cf, off_part, off_slots,
       off_tiles, off_flag;
   size_t off_clos;  // closure form (2D): N^, indicator, dilation, mode, delta marks, count
   size_t off_sums;  // kinetic moment sums per cell, 2 (d+2) doubles
@@ -119,8 +120,8 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
     return fmt_err(err, "n_vel must be in [2, 256]"), HOFKS_EINVAL;
   if (desc->precision < 0 || desc->precision > 1)
     return fmt_err(err, "precision must be 0 or 1"), HOFKS_EINVAL;
-  if (desc->scheme < 0 || desc->scheme > 2)
-    return fmt_err(err, "scheme must be 0, 1 or 2"), HOFKS_EINVAL;
+  if (desc->scheme < 0 || desc->scheme > 3)
+    return fmt_err(err, "scheme must be 0, 1, 2 or 3"), HOFKS_EINVAL;
   Geom& G = P->G;
   G.nc = 1;
   for (int a = 0; a < 3; ++a) {
@@ -144,6 +145,7 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
   G.lam = 1.0;
   G.mu = 0.0;
   G.gam = (d + 2.0) / d;
+  G.sfac = desc->scheme == 3 ? 2.5 : 2.0;
   P->d = d;
   P->nm = d + 2;
   P->R = 3 * P->nm;
@@ -218,6 +220,12 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
   off = align256(off + ubytes);
   P->off_UE[1] = off;
   off = align256(off + ubytes);
+  if (desc->scheme == 3) {  // Runge-Kutta stage values of the WENO solve
+    P->off_UE[2] = off;
+    off = align256(off + ubytes);
+    P->off_UE[3] = off;
+    off = align256(off + ubytes);
+  }
   P->off_rec[0] = off;
   off = align256(off + (size_t)P->RS * G.nc * P->tsize);
   P->off_rec[1] = off;
@@ -255,7 +263,7 @@ struct hofks_ctx {
   unsigned char* ws;
   void* g[2];
   int cur;                 // piece buffer holding f^n
-  double *U[2], *UE[2], *cf, *part, *slots;
+  double *U[2], *UE[4], *cf, *part, *slots;
   void* rec[2];
   VelNode* vt;
   int* tiles;
@@ -529,6 +537,14 @@ template <int D, typename T>
 void launch_euler(hofks_ctx* c, const StepArgs<T>& a, hipStream_t st) {
   const Plan& P = c->P;
   const int K = std::max(1, std::min(c->s_cap, c->euler_k > 0 ? c->euler_k : c->s_known + 1));
+  if (c->desc.scheme == 3) {  // WENO: three Runge-Kutta stage launches per sub-step
+    for (int i = 0; i < K; ++i)
+      for (int stg = 0; stg < 3; ++stg)
+        hipLaunchKernelGGL((k_weno_stage<D, T>), dim3(nblk(P.G.nc)), dim3(256), 0, st, a, P.G, i,
+                           stg);
+    hipLaunchKernelGGL((k_weno_tail<D, T, 256>), dim3(P.GE), dim3(256), 0, st, a, P.G, K);
+    return;
+  }
   if constexpr (D == 2) {  // 16 x 16 LDS tiles
     const int ntx = (P.G.n[0] + ET - 1) / ET, nty = (P.G.n[1] + ET - 1) / ET;
     for (int i = 0; i < K; ++i)
@@ -566,6 +582,8 @@ hofks_status launch_step(hofks_ctx* c, float* snap_x = nullptr, float* snap_t = 
   a.U_out = c->U[rp ^ 1];
   a.UE0 = c->UE[0];
   a.UE1 = c->UE[1];
+  a.UE2 = c->UE[2];
+  a.UE3 = c->UE[3];
   a.cf = c->cf;
   a.set_r = slot_set(c, (int)(n % 3));
   a.set_w = slot_set(c, (int)((n + 1) % 3));
@@ -766,7 +784,7 @@ hofks_status plan_substeps(hofks_ctx* c) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   double sum = 0.0;
   for (int k = 0; k < c->P.d; ++k) sum += a[k];
-  const double sv = std::ceil(2.0 * c->P.G.dt * sum / c->P.G.dx);
+  const double sv = std::ceil(c->P.G.sfac * c->P.G.dt * sum / c->P.G.dx);
   const int s0 = (sv >= 1.0 && sv < SMAX) ? (int)sv : (sv >= SMAX ? SMAX : 1);
   c->s_cap = std::min(SMAX, std::max(2 * s0, s0 + 8));
   c->s_known = s0;
@@ -849,6 +867,8 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
     c->UE[i] = (double*)(c->ws + P.off_UE[i]);
     c->rec[i] = (void*)(c->ws + P.off_rec[i]);
   }
+  for (int i = 2; i < 4; ++i)
+    c->UE[i] = desc->scheme == 3 ? (double*)(c->ws + P.off_UE[i]) : nullptr;
   c->cur = 0;
   c->vt = (VelNode*)(c->ws + P.off_vt);
   c->cf = (double*)(c->ws + P.off_cf);

@@ -59,6 +59,7 @@ struct Geom {
   int nv1, kofs, nv;  // nodes per axis, k_a = i_a - kofs, total nodes
   int bc[3];          // 0 periodic, 1 outflow
   double dx, dv, dt, w, lam, mu, gam;
+  double sfac;        // sub-steps s = ceil(sfac dt sum_a alpha_a / dx): 2 MUSCL, 2.5 WENO
 };
 
 struct Mat {
@@ -106,13 +107,14 @@ __device__ __forceinline__ unsigned load_acquire(unsigned* p) {
 }
 
 // Euler sub-step count of a step, from the speeds of U^n (same rule as the
-// oracle: s = max(1, ceil(2 dt sum_a alpha_a / dx)))
+// oracle: s = max(1, ceil(c dt sum_a alpha_a / dx)), c = 2 for the MUSCL
+// bound dt_s sum alpha <= dx/2 of eq. (Time2), 2.5 for the WENO solve's 0.4)
 template <int D>
 __device__ __forceinline__ int substeps(const double* alpha0, const Geom& G, int s_cap,
                                         bool* over) {
   double sum = 0.0;
   for (int a = 0; a < D; ++a) sum += alpha0[a];
-  double sv = ceil(2.0 * G.dt * sum / G.dx);
+  double sv = ceil(G.sfac * G.dt * sum / G.dx);
   int s = (sv >= 1.0) ? (sv <= (double)s_cap ? (int)sv : s_cap + 1) : 1;
   *over = (s > s_cap);
   return s > s_cap ? s_cap : s;
@@ -479,6 +481,8 @@ struct StepArgs {
   double* U_out;
   double* UE0;
   double* UE1;
+  double* UE2;        // WENO solve: Runge-Kutta stage values (scheme 3 only)
+  double* UE3;
   double* cf;
   double* set_r;      // speeds of U^n (row 0) and of the sub-steps; control
   double* set_w;      // speeds of U^{n+1} (row 0), written by the kinetic epilogue

@@ -29,7 +29,8 @@ class Solver:
     nodes per axis spaced ``dv``; the time step is ``dx / dv``.
 
     precision: 0 FP64 pieces; 1 FP32 pieces with FP64 compensated moment sums.
-    scheme: 0 HOFKS; 1 FKS (no Euler coupling); 2 HOFKS with phi == 1.
+    scheme: 0 HOFKS; 1 FKS (no Euler coupling); 2 HOFKS with phi == 1;
+    3 HOFKS with the WENO Euler solve.
     bc per axis: 0 periodic, 1 outflow.
     """
 

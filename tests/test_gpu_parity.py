@@ -460,3 +460,44 @@ def test_disk_substeps_grow_within_one_call():
     err = moment_errors(s.read_moments(), o.U, 2)
     assert err.max() < TOL64, err
     assert rel_inf(s.read_f(), o.f) < TOL64
+
+
+# ------------------------------------------ WENO Euler solve (scheme 3)
+@gpu
+@pytest.mark.parametrize("d,n,nv,bc,tau,prec,launches", [
+    (1, (200,), 64, (1,), 1e-2, 0, 0),         # the Sod tube workload's lattice
+    (1, (130,), 24, (1,), 0.0, 0, 0),          # tau = 0: Euler only
+    (1, (97,), 16, (0,), 1.0, 0, 1),           # periodic; persistent tail for every later sub-step
+    (2, (70, 37), 16, (0, 0), 1e-3, 0, 0),     # ragged tiles
+    (2, (48, 40), 16, (1, 1), 5e-3, 0, 1),     # outflow both axes; tail
+    (2, (67, 9), 12, (0, 0), 2e-2, 1, 0),      # FP32 pieces
+    (3, (23, 9, 11), 8, (0, 1, 0), 1e-2, 0, 0),
+    (3, (20, 12, 10), 8, (1, 1, 1), 5e-3, 1, 1),
+])
+def test_weno_scheme_parity(d, n, nv, bc, tau, prec, launches):
+    """HOFKS with the WENO Euler solve (scheme 3) against the oracle: 1e-12
+    in FP64, 1e-5 with FP32 pieces, on U and f; sub-step counts equal; with
+    one single-sub-step launch per step the persistent tail runs the rest"""
+    announce("weno", d, n, nv, bc, tau, prec, launches)
+    from paper_1212_0204_amd import Solver
+    nc = int(np.prod(n))
+    fields = W.sod_tube(n[0]) if d == 1 else _random_fields(d, nc, 59)
+    dx = 1.0 / n[0]
+    dv = 0.25 if nv == 64 else 0.5
+    o = Oracle(d, n, dx, nv, dv, bc=bc, tau=tau, scheme=3)
+    s = Solver(d, n, dx, nv, dv, bc=bc, tau=tau, precision=prec, scheme=3)
+    if launches:
+        s.set_euler_launches(launches)
+    o.init_macro(*fields)
+    s.set_state_macro(*fields)
+    steps = 20 if d == 1 else 5
+    o.step(steps)
+    s.step(steps)
+    tol = TOL64 if prec == 0 else TOL32
+    err = moment_errors(s.read_moments(), o.U, d)
+    print("weno moment errors", err, "substeps", o.substeps, "tail", s.tail_substeps())
+    assert err.max() < tol, err
+    assert rel_inf(s.read_f(), o.f) < tol
+    assert s.counters()[0] == o.substeps
+    if launches:
+        assert s.tail_substeps() > 0

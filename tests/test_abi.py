@@ -50,7 +50,7 @@ def test_workspace_sizes_of_the_workloads():
 
 
 @pytest.mark.parametrize("kw", [dict(dim=0), dict(dim=4), dict(nv=1), dict(dv=0.0),
-                                dict(dx=-1.0), dict(precision=2), dict(scheme=3),
+                                dict(dx=-1.0), dict(precision=2), dict(scheme=4),
                                 dict(bc=(2, 0, 0)), dict(n=(0, 4, 1)),
                                 dict(n=(8, 8, 1), nv=32)])  # periodic x shorter than the shift
 def test_bad_descriptors_are_rejected(kw):

@@ -41,7 +41,9 @@ def _lib():
         d, i, vp = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
         dp = P(ctypes.c_double)
         lib.or_create.restype = vp
-        lib.or_create.argtypes = [i, P(i), d, i, d, P(i), i, d, P(i)]
+        lib.or_create.argtypes = [i, P(i), d, i, d, P(i), i, d, d, P(i)]
+        lib.or_nstep.argtypes = [vp]
+        lib.or_nstep.restype = ctypes.c_long
         lib.or_destroy.argtypes = [vp]
         lib.or_set_tau.argtypes = [vp, d]
         lib.or_init_macro.argtypes = [vp, dp, dp, dp]
@@ -82,9 +84,11 @@ class Oracle:
     (U_E := U_M), 2 HOFKS with the Van Leer limiter replaced by phi == 1,
     3 HOFKS with the WENO Euler solve (section 4.3.3).
     ``bc`` per axis: 0 periodic, 1 outflow (zero gradient).
+    ``dt``: None for the lattice dt = dx/dv; a smaller value for off-lattice
+    transport (pieces at accumulated offsets v_k n dt, section 4.2).
     """
 
-    def __init__(self, d, n, dx, nv, dv, bc=None, tau=math.inf, scheme=0):
+    def __init__(self, d, n, dx, nv, dv, bc=None, tau=math.inf, scheme=0, dt=None):
         n = (list(n) + [1, 1, 1])[:3]
         bc = (list(bc if bc is not None else [0] * 3) + [0, 0, 0])[:3]
         self.d, self.n, self.nv1, self.dx, self.dv = d, n[:d], nv, dx, dv
@@ -96,7 +100,7 @@ class Oracle:
         ia = (ctypes.c_int * 3)(*n)
         ba = (ctypes.c_int * 3)(*bc)
         self._h = _lib().or_create(d, ia, float(dx), nv, float(dv), ba,
-                                   scheme, float(tau), ctypes.byref(st))
+                                   scheme, float(tau), float(dt or 0.0), ctypes.byref(st))
         if not self._h:
             raise OracleError(st.value, "create")
 
@@ -163,6 +167,10 @@ class Oracle:
     @property
     def dt(self):
         return _lib().or_dt(self._h)
+
+    @property
+    def nstep(self):
+        return _lib().or_nstep(self._h)
 
     @property
     def lam(self):

@@ -67,6 +67,18 @@
  * initial state and kept for its three stages; outflow ghosts (three per
  * side) copy the boundary cell.
  *
+ * Off-lattice velocities (dt given, dt <= dx/dv): the transport of section
+ * 4.2 moves every piecewise-constant function f_k by v_k dt per step with no
+ * reconstruction, so after n steps the discontinuities of f_k sit at
+ * x_{p-1/2} + v_k n dt and the cell centre x_j lies in the piece that started
+ * in cell j - o_k(n), o_k(n) = ceil(c_k n - 1/2), c_k = v_k dt / dx (pieces
+ * are the half-open cells [x_{p-1/2}, x_{p+1/2})).  The value at the centre
+ * is what the relaxation and the moments see (section 4.2), so a step
+ * t^n -> t^{n+1} reads the upstream cell j - (o_k(n+1) - o_k(n)) per axis:
+ * an integer shift that is floor(c_k) or ceil(c_k) by step.  c_k n is formed
+ * as ((k dv) dt / dx) * n, each operation rounded (no contraction).  With
+ * dt = dx/dv this is the lattice shift k.
+ *
  * Layouts: U and u are component-major, U[r*Nc + j]; f is velocity-plane major,
  * f[k*Nc + j]; cells are x-fastest, j = (jz*Ny + jy)*Nx + jx; velocities are
  * x-fastest, k = (iz*n + iy)*n + ix with k_a = i_a - n/2 (integer division).
@@ -93,6 +105,10 @@ typedef struct or_state {
   int scheme;           /* 0 HOFKS, 1 FKS (U_E := U_M), 2 HOFKS unlimited,
                            3 HOFKS with the WENO Euler solve                 */
   double tau, lam, mu;  /* relaxation time, exp(-dt/tau), 1 - exp(-dt/tau)   */
+  int offl;             /* 1: dt given (off-lattice transport), 0: dt = dx/dv */
+  long nstep;           /* steps taken since the initial data (off-lattice)  */
+  double *cvel;         /* nv1: c = v dt / dx per node of one axis            */
+  int *shift;           /* nv1: cells moved by the current step, per node     */
   int *kint;            /* nv x d integer velocity indices k_a               */
   double *m;            /* nv x nm collision invariants m_k                  */
   double A[25];         /* (C C^T)^{-1}, nm x nm                             */
@@ -135,6 +151,7 @@ static int upstream(const or_state *S, int j, int k) {
   cell_coords(S, j, c);
   for (int a = 0; a < 3; ++a) {
     int ka = (a < S->d) ? S->kint[k * S->d + a] : 0;
+    if (S->offl && a < S->d) ka = S->shift[ka + S->nv1 / 2];
     s[a] = map_axis(S, a, c[a] - ka);
   }
   return cell_index(S, s);
@@ -588,6 +605,8 @@ static int step_once(or_state *S) {
 
 void or_destroy(or_state *S) {
   if (!S) return;
+  free(S->cvel);
+  free(S->shift);
   free(S->kint);
   free(S->m);
   free(S->f);
@@ -616,7 +635,7 @@ static int set_tau(or_state *S, double tau) {
 }
 
 or_state *or_create(int d, const int *n, double dx, int nv1, double dv,
-                    const int *bc, int scheme, double tau, int *status) {
+                    const int *bc, int scheme, double tau, double dt, int *status) {
   *status = OR_EINVAL;
   if (d < 1 || d > 3 || nv1 < 2 || !(dx > 0) || !(dv > 0) || scheme < 0 ||
       scheme > 3)
@@ -637,6 +656,14 @@ or_state *or_create(int d, const int *n, double dx, int nv1, double dv,
   S->dx = dx;
   S->dv = dv;
   S->dt = dx / dv; /* lattice: v_k dt = k dx */
+  if (dt != 0.0) { /* off-lattice: a free time step up to the lattice's */
+    if (!(dt > 0.0) || !(dt <= dx / dv)) {
+      free(S);
+      return NULL;
+    }
+    S->dt = dt;
+    S->offl = 1;
+  }
   S->w = pow(dv, d);
   S->nv1 = nv1;
   S->nv = 1;
@@ -647,6 +674,13 @@ or_state *or_create(int d, const int *n, double dx, int nv1, double dv,
     return NULL;
   }
   int nm = S->nm, nv = S->nv, nc = S->nc;
+  S->cvel = (double *)malloc(sizeof(double) * nv1);
+  S->shift = (int *)malloc(sizeof(int) * nv1);
+  for (int i = 0; i < nv1; ++i) {
+    double v = (double)(i - nv1 / 2) * dv;
+    S->cvel[i] = v * S->dt / dx;
+    S->shift[i] = i - nv1 / 2;
+  }
   S->kint = (int *)malloc(sizeof(int) * nv * d);
   S->m = (double *)malloc(sizeof(double) * nv * nm);
   for (int k = 0; k < nv; ++k) {
@@ -696,6 +730,7 @@ int or_set_tau(or_state *S, double tau) { return set_tau(S, tau); }
 /* initial data: U^0 from (rho, u, theta), f^0 = E[U^0] (section 4.2) */
 int or_init_macro(or_state *S, const double *rho, const double *u,
                   const double *theta) {
+  S->nstep = 0;
   int d = S->d, nm = S->nm, nc = S->nc, nv = S->nv, st = OR_OK;
   for (int j = 0; j < nc; ++j) {
     double usq = 0.0;
@@ -719,6 +754,7 @@ int or_init_macro(or_state *S, const double *rho, const double *u,
 
 /* arbitrary initial f; the carried moments become U = P(f), eq. (DM) */
 int or_set_f(or_state *S, const double *f) {
+  S->nstep = 0;
   int nm = S->nm, nc = S->nc, nv = S->nv;
   memcpy(S->f, f, sizeof(double) * nv * nc);
   for (int j = 0; j < nc; ++j)
@@ -730,8 +766,19 @@ int or_set_f(or_state *S, const double *f) {
   return OR_OK;
 }
 
+/* o(n) = ceil(c n - 1/2): the piece holding a cell centre after n steps */
+static long piece_offset(double c, long n) {
+  volatile double cn = c * (double)n; /* rounded product, no contraction */
+  return (long)ceil(cn - 0.5);
+}
+
 int or_step(or_state *S, int nsteps) {
   for (int i = 0; i < nsteps; ++i) {
+    if (S->offl)
+      for (int q = 0; q < S->nv1; ++q)
+        S->shift[q] = (int)(piece_offset(S->cvel[q], S->nstep + 1) -
+                            piece_offset(S->cvel[q], S->nstep));
+    S->nstep++;
     int st = step_once(S);
     if (st) return st;
   }
@@ -766,6 +813,7 @@ int or_max_threads(void) {
 #endif
 }
 double or_dt(const or_state *S) { return S->dt; }
+long or_nstep(const or_state *S) { return S->nstep; }
 double or_lambda(const or_state *S) { return S->lam; }
 void or_get_A(const or_state *S, double *A) {
   memcpy(A, S->A, sizeof(double) * S->nm * S->nm);

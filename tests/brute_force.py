@@ -115,10 +115,17 @@ class Brute:
     """scheme 0 HOFKS, 1 FKS (U_E := U_M), 2 HOFKS with phi == 1, 3 HOFKS
     with the WENO Euler solve (three-stage SSP Runge-Kutta, CFL 0.4)"""
 
-    def __init__(self, d, n, dx, nv, dv, bc, tau, scheme=0):
+    def __init__(self, d, n, dx, nv, dv, bc, tau, scheme=0, dt=None):
         self.d, self.n, self.bc, self.scheme = d, tuple(n), tuple(bc), scheme
         self.dx, self.dv = mp.mpf(dx), mp.mpf(dv)
         self.dt = self.dx / self.dv  # lattice: v_k dt = k dx
+        # off-lattice (section 4.2): a free dt; the pieces of f_k move by
+        # v_k dt per step and the centre x_j lies, after n steps, in the piece
+        # whose cell [x_p - dx/2, x_p + dx/2) contains x_j - v_k n dt
+        self.offl = dt is not None
+        if self.offl:
+            self.dt = mp.mpf(dt)
+        self.nstep = 0
         self.K = _velocity_tuples(d, nv)
         self.V = [tuple(k * self.dv for k in kk) for kk in self.K]
         self.cells = _cell_tuples(n)
@@ -171,6 +178,7 @@ class Brute:
 
     def init_macro(self, rho, u, theta):
         d = self.d
+        self.nstep = 0
         self.U, self.f = [], []
         for j in range(len(self.cells)):
             r = mp.mpf(float(rho[j]))
@@ -180,8 +188,16 @@ class Brute:
             self.U.append(U)
             self.f.append(self.equilibrium(U))
 
+    def _piece(self, k, n):
+        """cells between x_j and the piece holding it after n steps"""
+        if not self.offl:
+            return k * n
+        y = mp.mpf(1) / 2 - k * self.dv * n * self.dt / self.dx  # (x_j - v_k n dt)/dx - j + 1/2
+        return -int(mp.floor(y))
+
     def set_f(self, f):
         """f[k][j] (velocity-plane major); U = P(f)"""
+        self.nstep = 0
         self.f = [[mp.mpf(float(f[k][j])) for k in range(len(self.K))]
                   for j in range(len(self.cells))]
         self.U = [self.moments(fj) for fj in self.f]
@@ -322,10 +338,13 @@ class Brute:
         E = [self.equilibrium(U) for U in self.U] if lam != 1 else None
         fK = [[None] * len(self.K) for _ in range(ncell)]
         Ustar, UM = [], []
+        n = self.nstep
+        self.nstep += 1
         for j, cell in enumerate(self.cells):
             fs_parts, e_parts = [], []
             for q, kk in enumerate(self.K):
-                src = self._index([self._wrap(a, cell[a] - kk[a]) for a in range(d)])
+                sh = [self._piece(kk[a], n + 1) - self._piece(kk[a], n) for a in range(d)]
+                src = self._index([self._wrap(a, cell[a] - sh[a]) for a in range(d)])
                 fn = self.f[src][q]
                 if lam == 1:
                     fK[j][q] = fn

@@ -93,3 +93,26 @@ def test_oracle_matches_brute_force_from_equilibrium(n, bc):
     b.step(2)
     eU, ef = _compare(o, b, d)
     assert eU < TOL and ef < TOL, (eU, ef)
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 3])
+@pytest.mark.parametrize("tau", [0.0, 0.05, math.inf])
+@pytest.mark.parametrize("n,bc", [((5,), (0,)), ((5,), (1,)), ((3, 3), (0, 1))])
+def test_oracle_matches_brute_force_off_lattice(n, bc, tau, scheme):
+    """a free time step dt = 0.37 dx/dv (section 4.2 transport of the
+    piecewise-constant pieces at accumulated offsets v_k n dt): four steps,
+    so that the per-step shifts take both of their values"""
+    d = len(n)
+    nv = 5 if d == 1 else 3
+    dv = 1.25
+    dx = 1.0 / n[0]
+    dt = 0.37 * dx / dv
+    f0, _ = _start(d, n, nv, dv, seed=2000 + 10 * d + sum(bc))
+    o = Oracle(d, n, dx, nv, dv, bc=bc, tau=tau, scheme=scheme, dt=dt)
+    b = Brute(d, n, dx, nv, dv, bc, tau, scheme, dt=dt)
+    o.set_f(f0)
+    b.set_f(f0)
+    o.step(4)
+    b.step(4)
+    eU, ef = _compare(o, b, d)
+    assert eU < TOL and ef < TOL, (eU, ef)

@@ -591,3 +591,88 @@ def test_tube_pool_matches_in_process_oracle():
         if not bad:
             np.testing.assert_array_equal(U, U1)
     set_threads(os.cpu_count() or 1)
+
+
+# -------------------------------- section 4.2: transport off the lattice
+def _exact_piecewise_transport(f0, n, nv, dv, dt, dx, nsteps, d):
+    """f at the cell centres after nsteps free-transport steps: each f_k is
+    the piecewise-constant initial function (cells [p dx, (p+1) dx))
+    translated by v_k t, evaluated at x_j (periodic); computed here from the
+    positions, not from step-by-step offsets"""
+    ks = np.arange(nv) - nv // 2
+    t = nsteps * dt
+    out = np.empty_like(f0)
+    nc = int(np.prod(n))
+    cells = np.stack(np.unravel_index(np.arange(nc), tuple(reversed(n)))[::-1], 1)  # (nc, d) x first
+    for k in range(nv ** d):
+        idx = np.unravel_index(k, (nv,) * d)[::-1]  # x-fastest velocity index
+        src = np.empty_like(cells)
+        for a in range(d):
+            y = (cells[:, a] + 0.5) * dx - ks[idx[a]] * dv * t
+            src[:, a] = np.floor(y / dx).astype(int) % n[a]
+        j = np.ravel_multi_index(tuple(src[:, a] for a in reversed(range(d))), tuple(reversed(n)))
+        out[k] = f0[k, j]
+    return out
+
+
+@pytest.mark.parametrize("d,n,nv,frac", [(1, (41,), 12, 0.37), (2, (13, 9), 6, math.sqrt(2) / 3),
+                                         (3, (7, 5, 6), 4, 0.61)])
+def test_offlattice_free_transport_is_exact(d, n, nv, frac):
+    """tau = +inf with a free time step dt = frac dx/dv: f^n at every cell
+    centre is the initial piecewise-constant f_k translated by v_k n dt
+    (section 4.2, no reconstruction), bit for bit"""
+    dv = 0.5
+    dx = 1.0 / n[0]
+    dt = frac * dx / dv
+    rng = np.random.default_rng(5 + d)
+    f0 = rng.uniform(0.0, 1.0, (nv ** d, int(np.prod(n))))
+    o = Oracle(d, n, dx, nv, dv, tau=math.inf, dt=dt)
+    assert o.dt == dt
+    o.set_f(f0)
+    for steps in (1, 3, 7):
+        o.step(steps - o.nstep)
+        np.testing.assert_array_equal(o.f, _exact_piecewise_transport(f0, n, nv, dv, dt, dx, steps, d))
+
+
+@pytest.mark.parametrize("tau", [0.0, 1e-3, 1e-2, 1.0, math.inf])
+@pytest.mark.parametrize("scheme", [0, 1, 3])
+def test_offlattice_conservation_and_consistency(tau, scheme):
+    """off-lattice transport keeps every piece, so periodic totals are
+    conserved to rounding for every tau and scheme, and P(f^n) = U^n"""
+    n, nv, dv = (24, 20), 12, 0.5
+    dx = 1.0 / 24
+    rho, u, th = W.perturbed_gas(24, 2, 0.2, 0.1, 3, (71, 72))
+    rho = rho.reshape(24, 24)[:20].reshape(-1)
+    th = th.reshape(24, 24)[:20].reshape(-1)
+    u = 0.2 * np.stack([np.sin(np.arange(480) * 0.1), np.cos(np.arange(480) * 0.07)])
+    o = Oracle(2, n, dx, nv, dv, tau=tau, scheme=scheme, dt=0.43 * dx / dv)
+    o.init_macro(rho, u, th)
+    tot0 = o.U.sum(1)
+    o.step(6)
+    U = o.U
+    scale = np.abs(U[0]).sum()
+    assert (np.abs(U.sum(1) - tot0) / scale).max() < 1e-13
+    np.testing.assert_allclose(moment_matrix(o) @ o.f, U, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("tau", [0.0, 1e-2, math.inf])
+def test_offlattice_at_the_lattice_step_is_the_lattice_scheme(tau):
+    """dt = dx/dv given explicitly reproduces the lattice run bit for bit"""
+    n, nv, dv = (30, 11), 10, 0.5
+    dx = 1.0 / 30
+    rng = np.random.default_rng(8)
+    fields = (1.0 + 0.2 * rng.uniform(-1, 1, 330), 0.1 * rng.uniform(-1, 1, (2, 330)),
+              1.0 + 0.2 * rng.uniform(-1, 1, 330))
+    a = Oracle(2, n, dx, nv, dv, bc=(1, 0), tau=tau)
+    b = Oracle(2, n, dx, nv, dv, bc=(1, 0), tau=tau, dt=dx / dv)
+    a.init_macro(*fields)
+    b.init_macro(*fields)
+    a.step(5)
+    b.step(5)
+    np.testing.assert_array_equal(a.U, b.U)
+    np.testing.assert_array_equal(a.f, b.f)
+
+
+def test_offlattice_rejects_a_step_beyond_the_lattice():
+    with pytest.raises(OracleError):
+        Oracle(1, (10,), 0.1, 8, 0.5, dt=0.21)

@@ -13,8 +13,11 @@
  * E[U] is the conservative Maxwellian of eq. (minimMax).
  *
  * Lattice.  Velocity nodes v_k = k dv with k in {-n/2 .. n/2-1} per axis for
- * even n and {-(n-1)/2 .. (n-1)/2} for odd n; the library sets dt = dx / dv, so
- * v_k dt = k dx and transport moves every piece by exactly k cells.
+ * even n and {-(n-1)/2 .. (n-1)/2} for odd n; by default the library sets
+ * dt = dx / dv, so v_k dt = k dx and transport moves every piece by exactly k
+ * cells.  A smaller dt in the descriptor gives off-lattice transport (the
+ * pieces keep their shape and move continuously; each step shifts them by a
+ * whole number of cells that follows their accumulated offset).
  *
  * Layouts (host arrays).  Cells are x-fastest: j = (jz*Ny + jy)*Nx + jx.
  * Moments U are component-major, U[r*Nc + j] with r = 0 (rho), 1..d (rho u),
@@ -67,6 +70,13 @@ typedef struct {
                        WENO5 of the Lax-Friedrichs split flux, three-stage
                        SSP Runge-Kutta, CFL 0.4 instead of eq. (Time2)'s 1/2;
                        single grids only, not the closure form)              */
+  double dt;        /* 0: the lattice dt = dx/dv (every piece moves k cells);
+                       0 < dt <= dx/dv: off-lattice transport (section 4.2):
+                       the pieces of velocity v_k sit at the accumulated
+                       offset v_k n dt and a step moves them by
+                       ceil(c (n+1) - 1/2) - ceil(c n - 1/2) cells,
+                       c = v_k dt / dx; n_vel a multiple of 4 in 2D/3D;
+                       not for batches or the closure form                   */
 } hofks_grid_desc;
 
 /* Bytes of device workspace a context with this descriptor needs. */

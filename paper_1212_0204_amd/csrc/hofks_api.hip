@@ -141,6 +141,15 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
   G.dx = desc->dx;
   G.dv = desc->dv;
   G.dt = desc->dx / desc->dv;  // lattice: v_k dt = k dx
+  G.offl = 0;
+  if (desc->dt != 0.0) {  // a free time step: off-lattice transport (section 4.2)
+    if (!(desc->dt > 0.0) || !(desc->dt <= G.dt))
+      return fmt_err(err, "dt must lie in (0, dx/dv]"), HOFKS_EINVAL;
+    if (d >= 2 && G.nv1 % 4 != 0)
+      return fmt_err(err, "off-lattice transport in 2D/3D needs n_vel a multiple of 4"), HOFKS_EINVAL;
+    G.dt = desc->dt;
+    G.offl = 1;
+  }
   G.w = std::pow(desc->dv, d);
   G.lam = 1.0;
   G.mu = 0.0;
@@ -452,6 +461,19 @@ void dispatch_kin(hofks_ctx* c, const StepArgs<T>& a, dim3 grid) {
     }
   }
   const int bcx = P.G.bc[0];
+  if (P.G.offl) {  // four wavefronts; four loads ahead in 2D/3D (n_vel % 4 == 0)
+    const size_t lds0 = kin_lds(P, 4);
+#define KO(BCX, U)                                                                               \
+  hipLaunchKernelGGL((k_kinetic<D, T, FT, CP, BCX, U, EUL, 4, false, true>), grid, dim3(256), lds0, \
+                     c->stream, a, P.G, P.A)
+    if constexpr (D >= 2) {
+      if (bcx == 0) KO(0, 4); else KO(1, 4);
+    } else {
+      if (bcx == 0) KO(0, 1); else KO(1, 1);
+    }
+#undef KO
+    return;
+  }
   int ng = c->kng, unr = kin_unroll(P, c->kng, c->kunr);
   if (FT || !EUL) {  // free transport and FKS steps: one configuration
     ng = 4;
@@ -601,6 +623,7 @@ hofks_status launch_step(hofks_ctx* c, float* snap_x = nullptr, float* snap_t = 
   a.kcount = nullptr;
   a.thr = 0.0;
   a.sums = (double*)(c->ws + P.off_sums);
+  a.nstep = n;
   const bool ft = (P.G.mu == 0.0);
   const bool eul = !ft && c->desc.scheme != 1;
   if (c->clos_dirty && !eul) {
@@ -912,11 +935,15 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
     c->kng = 4;
     c->kunr = 4;
   }
+  if (P.G.offl) {  // off-lattice: the generic kinetic kernel with per-step shifts
+    c->kring = c->kwide = 0;
+    c->kng = 4;
+  }
   // velocity node table of one axis (the lattice, used by every kernel)
   std::vector<VelNode> tab(P.G.nv1);
   for (int i = 0; i < P.G.nv1; ++i) {
     const double v = (i - P.G.kofs) * P.G.dv;
-    tab[i] = VelNode{v, v * v, (float)v, (float)(0.5 * v * v), 0.5 * v * v};
+    tab[i] = VelNode{v, v * v, (float)v, (float)(0.5 * v * v), 0.5 * v * v, v * P.G.dt / P.G.dx};
   }
   if (reset_counters(c) != HOFKS_OK ||
       hipMemcpyAsync(c->vt, tab.data(), tab.size() * sizeof(VelNode), hipMemcpyHostToDevice,
@@ -1083,7 +1110,7 @@ hofks_status hofks_read_f(hofks_ctx* c, double* f, size_t bytes) {
 struct StateHeader {
   char magic[8];
   int version, dim, n[3], nv1, precision, scheme, bc[3];
-  double dx, dv, tau;
+  double dx, dv, tau, dt;
   long long steps;
   double speeds[ASTR];
 };
@@ -1114,7 +1141,7 @@ hofks_status hofks_read_state(hofks_ctx* c, void* host, size_t bytes) {
   StateHeader h;
   std::memset(&h, 0, sizeof(h));
   std::memcpy(h.magic, "HOFKSST1", 8);
-  h.version = 1;
+  h.version = 2;
   h.dim = P.d;
   for (int a = 0; a < 3; ++a) {
     h.n[a] = P.G.n[a];
@@ -1126,6 +1153,7 @@ hofks_status hofks_read_state(hofks_ctx* c, void* host, size_t bytes) {
   h.dx = P.G.dx;
   h.dv = P.G.dv;
   h.tau = c->tau;
+  h.dt = P.G.dt;
   h.steps = c->steps;
   HIPCHK(c, hipMemcpyAsync(h.speeds, slot_set(c, rset(c)), sizeof(h.speeds), hipMemcpyDeviceToHost,
                            c->stream));
@@ -1149,9 +1177,9 @@ hofks_status hofks_write_state(hofks_ctx* c, const void* host, size_t bytes) {
   if (bytes < state_bytes(P)) return HOFKS_ESIZE;
   StateHeader h;
   std::memcpy(&h, host, sizeof(h));
-  bool same = std::memcmp(h.magic, "HOFKSST1", 8) == 0 && h.version == 1 && h.dim == P.d &&
+  bool same = std::memcmp(h.magic, "HOFKSST1", 8) == 0 && h.version == 2 && h.dim == P.d &&
               h.nv1 == P.G.nv1 && h.precision == P.prec && h.scheme == c->desc.scheme &&
-              h.dx == P.G.dx && h.dv == P.G.dv && h.steps >= 0;
+              h.dx == P.G.dx && h.dv == P.G.dv && h.dt == P.G.dt && h.steps >= 0;
   for (int a = 0; a < 3; ++a) same = same && h.n[a] == P.G.n[a] && h.bc[a] == P.G.bc[a];
   if (!same) return fmt_err(c->err, "state image does not match this grid"), HOFKS_EINVAL;
   hofks_status st = hofks_set_tau(c, h.tau);  // lambda of the stored records
@@ -1294,7 +1322,7 @@ hofks_status batch_plan(const hofks_grid_desc* descs, const double* taus, int n,
   constexpr int RS = rec_stride<1, float>();
   for (int i = 0; i < n; ++i) {
     const hofks_grid_desc& d = descs[i];
-    if (d.dim != 1 || d.precision != 1 || d.bc[0] != 1 || d.scheme != 0)
+    if (d.dim != 1 || d.precision != 1 || d.bc[0] != 1 || d.scheme != 0 || d.dt != 0.0)
       return fmt_err(err, "tube %d: batches hold 1D outflow HOFKS tubes in FP32", i), HOFKS_EINVAL;
     Plan P;
     hofks_status st = make_plan(&d, &P, err);
@@ -1633,6 +1661,13 @@ hofks_status batch_set_state(hofks_ctx* c, const double* rho, const double* u,
 // single grid: choose (wavefronts per kinetic block, loads issued ahead)
 hofks_status grid_autotune(hofks_ctx* c, int steps, const char* cache_path, int* choice) {
   const Plan& P = c->P;
+  if (P.G.offl) {  // one configuration (four wavefronts, fixed loads ahead)
+    if (choice) {
+      choice[0] = 4;
+      choice[1] = P.d >= 2 ? 4 : 1;
+    }
+    return HOFKS_OK;
+  }
   std::ostringstream key;
   key << "gfx950:grid:d=" << P.d << ":n=" << P.G.n[0] << "x" << P.G.n[1] << "x" << P.G.n[2]
       << ":nv=" << P.G.nv1 << ":prec=" << P.prec << ":bc=" << P.G.bc[0] << P.G.bc[1] << P.G.bc[2]
@@ -1780,7 +1815,7 @@ hofks_status hofks_batch_create(const hofks_grid_desc* descs, const double* taus
   for (const TubeDev& T : B->tubes)
     for (int i = 0; i < T.nv1; ++i) {
       const double v = (i - T.kofs) * T.dv;
-      tab.push_back(VelNode{v, v * v, (float)v, (float)(0.5 * v * v), 0.5 * v * v});
+      tab.push_back(VelNode{v, v * v, (float)v, (float)(0.5 * v * v), 0.5 * v * v, 0.0});
     }
   if (hipMemcpyAsync(B->vtar, tab.data(), sizeof(VelNode) * tab.size(), hipMemcpyHostToDevice,
                      c->stream) != hipSuccess ||
@@ -1961,6 +1996,7 @@ hofks_status hofks_closure_enable(hofks_ctx* c, const void* packed, double sigma
   if (c->batch || c->P.d != 2)
     return fmt_err(c->err, "the closure form is defined for 2D-2V grids"), HOFKS_EINVAL;
   if (c->desc.scheme != 0) return fmt_err(c->err, "the closure form needs the HOFKS scheme"), HOFKS_EINVAL;
+  if (c->P.G.offl) return fmt_err(c->err, "the closure form needs the lattice dt = dx/dv"), HOFKS_EINVAL;
   if (!packed || ((uintptr_t)packed & 15))
     return fmt_err(c->err, "network weights: 16-byte aligned device pointer expected"), HOFKS_EINVAL;
   if (!std::isfinite(sigma) || std::isnan(threshold))
@@ -1985,6 +2021,7 @@ hofks_status hofks_closure_snapshot(hofks_ctx* c, float* x, float* t) {
     return fmt_err(c->err, "the closure form is defined for 2D-2V grids"), HOFKS_EINVAL;
   if (!c->ready) return fmt_err(c->err, "set the state before stepping"), HOFKS_ESTATE;
   if (c->desc.scheme != 0) return fmt_err(c->err, "the closure form needs the HOFKS scheme"), HOFKS_EINVAL;
+  if (c->P.G.offl) return fmt_err(c->err, "the closure form needs the lattice dt = dx/dv"), HOFKS_EINVAL;
   if (!(c->P.G.lam >= 1e-12) || !(c->P.G.mu > 0.0))
     return fmt_err(c->err, "training targets need 1e-12 <= lambda < 1 (finite tau, not too small)"),
            HOFKS_EINVAL;

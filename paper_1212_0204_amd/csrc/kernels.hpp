@@ -58,6 +58,7 @@ struct Geom {
   int nc;
   int nv1, kofs, nv;  // nodes per axis, k_a = i_a - kofs, total nodes
   int bc[3];          // 0 periodic, 1 outflow
+  int offl;           // 1: a free time step (off-lattice transport), 0: dt = dx/dv
   double dx, dv, dt, w, lam, mu, gam;
   double sfac;        // sub-steps s = ceil(sfac dt sum_a alpha_a / dx): 2 MUSCL, 2.5 WENO
 };
@@ -199,7 +200,28 @@ struct VelNode {
   double v, v2;
   float vf, v2hf;  // (float)v, (float)(v^2 / 2)
   double v2h;      // v^2 / 2
+  double c;        // v dt / dx: cells travelled per step (off-lattice transport)
 };
+
+// Cells moved by the pieces of velocity node i in the step t^n -> t^{n+1}
+// (section 4.2: exact transport of piecewise-constant pieces).  On the
+// lattice dt = dx/dv this is k = i - kofs.  Off the lattice the pieces sit
+// at accumulated offsets v n dt, the cell centre x_j lies in the piece that
+// started in cell j - o(n), o(n) = ceil(c n - 1/2), and the step moves by
+// o(n+1) - o(n) (floor(c) or ceil(c)).  Products and differences are rounded
+// one by one, as in the oracle.
+__device__ __forceinline__ int node_shift(const VelNode* vt, int i, const Geom& G, long n) {
+#pragma clang fp contract(off)
+  if (!G.offl) return i - G.kofs;
+  using CVN = const __attribute__((address_space(4))) VelNode;
+  const double c = ((CVN*)vt + i)->c;
+  const double a = c * (double)(n + 1) - 0.5;
+  const double b = c * (double)n - 0.5;
+  const int sh = (int)(ceil(a) - ceil(b));
+  // |c| <= |i - kofs| (dt <= dx/dv), so the shift lies in the lattice's range
+  // and within the staged record segment; the clamp only guards memory
+  return min(max(sh, -G.kofs), G.nv1 - 1 - G.kofs);
+}
 
 // bounded wait: gives up (and flags) after SPIN_CAP sleeps, or at once when
 // another wait of the launch has already given up
@@ -498,6 +520,7 @@ struct StepArgs {
   unsigned long long* kcount;  // kinetic cell-steps (accumulated)
   double thr;
   double* sums;  // [2 (d+2)][nc]: moment sums of f* and of E, for k_cell_update
+  long nstep;    // n of the step t^n -> t^{n+1} (off-lattice shifts)
 };
 
 // Euler sub-step i (eq. (discmom) with the flux of section 4.3), one cell per
@@ -798,7 +821,7 @@ __device__ __forceinline__ VelNode vel_node(const VelNode* vt, int i) {
 // Euler solve, the first wavefront forms U^{n+1}, cf and the next record of
 // its 64 cells.  (NG, UNR) is chosen per grid by the autotuner.
 template <int D, typename T, bool FT, bool COMP, int BCX, int UNR, bool EUL, int NG,
-          bool CLOS = false>
+          bool CLOS = false, bool OFFL = false>
 __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat A) {
   constexpr int NM = D + 2;
   constexpr int RS = rec_stride<D, T>();
@@ -846,7 +869,8 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
   for (int vr = vr0; vr < vr1; ++vr) {
     const int iy = (D >= 2) ? vr % G.nv1 : 0;
     const int iz = (D >= 3) ? vr / G.nv1 : 0;
-    const int ky = iy - G.kofs, kz = iz - G.kofs;
+    const int ky = OFFL ? node_shift(a.vt, iy, G, a.nstep) : iy - G.kofs;
+    const int kz = OFFL ? node_shift(a.vt, iz, G, a.nstep) : iz - G.kofs;
     const double vy = (D >= 2) ? vel_node(a.vt, iy).v : 0.0;
     const double vz = (D >= 3) ? vel_node(a.vt, iz).v : 0.0;
     const double hrow = (D >= 2 ? 0.5 * vel_node(a.vt, iy).v2 : 0.0) +
@@ -951,10 +975,12 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
     }
     for (int ix0 = ixa; ix0 < ixb; ix0 += UNR) {
       T gv[UNR];
+      int shx[UNR];  // off-lattice: cells moved by each piece of the group
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const int ix = ix0 + u;
-        const int kx = ix - G.kofs;
+        const int kx = OFFL ? node_shift(a.vt, ix, G, a.nstep) : ix - G.kofs;
+        shx[u] = kx;
         // plane base (uniform) + 32-bit byte offset of the upstream cell
         const char* gp = reinterpret_cast<const char*>(a.g_in + (kbase + ix) * (size_t)G.nc);
         const T* src = reinterpret_cast<const T*>(
@@ -977,7 +1003,7 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
         const T vxT = (sizeof(T) == 4) ? (T)vn.vf : (T)vn.v;
         const T vhT = (sizeof(T) == 4) ? (T)vn.v2hf : (T)vn.v2h;
         T rv[9];
-        read_row_rec<T>(Lb + u * FS, rv);
+        read_row_rec<T>(OFFL ? Lw + (SW - 1 - lane - lofs + shx[u]) * FS : Lb + u * FS, rv);
         // row record: [a0, u_x, beta | P0, p_1, p_{d+1} | E0, e_1, e_{d+1}]
         const T pp = rv[3] + rv[4] * vxT + rv[5] * vhT;
         const T g = gv[u];

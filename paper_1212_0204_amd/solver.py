@@ -26,23 +26,27 @@ def _dp(a):
 
 class Solver:
     """HOFKS on a Cartesian grid of ``n_cells`` (x first) with ``n_vel`` velocity
-    nodes per axis spaced ``dv``; the time step is ``dx / dv``.
+    nodes per axis spaced ``dv``; the time step is ``dx / dv`` (the lattice) unless
+    a smaller ``dt`` is given.
 
     precision: 0 FP64 pieces; 1 FP32 pieces with FP64 compensated moment sums.
     scheme: 0 HOFKS; 1 FKS (no Euler coupling); 2 HOFKS with phi == 1;
     3 HOFKS with the WENO Euler solve.
     bc per axis: 0 periodic, 1 outflow.
+    dt: None for the lattice dt = dx/dv; 0 < dt <= dx/dv for off-lattice
+    transport.
     """
 
     def __init__(self, dim, n_cells, dx, n_vel, dv, bc=None, precision=0, scheme=0,
-                 tau=math.inf, stream=None):
+                 tau=math.inf, stream=None, dt=None):
         L = _lib.lib()
         if not torch.cuda.is_available():
             raise RuntimeError("the HOFKS library needs a ROCm GPU")
         n = (list(n_cells) + [1, 1, 1])[:3]
         b = (list(bc if bc is not None else [0, 0, 0]) + [0, 0, 0])[:3]
         self.desc = _lib.GridDesc(dim, (ctypes.c_int * 3)(*n), float(dx), int(n_vel), float(dv),
-                                  (ctypes.c_int * 3)(*b), int(precision), int(scheme))
+                                  (ctypes.c_int * 3)(*b), int(precision), int(scheme),
+                                  float(dt or 0.0))
         self.d, self.nm = dim, dim + 2
         self.nc = int(np.prod(n[:dim]))
         self.nv = int(n_vel) ** dim

@@ -64,3 +64,23 @@ def test_create_rejects_small_workspace():
     d = desc()
     st = _lib.lib().hofks_create(ctypes.byref(d), ctypes.c_void_p(256), 1024, None, ctypes.byref(h))
     assert st == -2 and not h.value
+
+
+@pytest.mark.parametrize("dt", [-1e-3, 0.5])
+def test_offlattice_step_outside_range_rejected(dt):
+    """a free time step must lie in (0, dx/dv]"""
+    d = desc(dx=0.1, dv=0.5)
+    d.dt = dt
+    st, _ = ws(d)
+    assert st == -1
+
+
+def test_offlattice_needs_nvel_multiple_of_4_in_2d():
+    d = desc(dim=2, n=(16, 16, 1), nv=10, dx=1 / 16, dv=0.5)
+    d.dt = 0.5 * (1 / 16) / 0.5
+    st, _ = ws(d)
+    assert st == -1
+    d = desc(dim=2, n=(16, 16, 1), nv=12, dx=1 / 16, dv=0.5)
+    d.dt = 0.5 * (1 / 16) / 0.5
+    st, _ = ws(d)
+    assert st == 0

@@ -501,3 +501,86 @@ def test_weno_scheme_parity(d, n, nv, bc, tau, prec, launches):
     assert s.counters()[0] == o.substeps
     if launches:
         assert s.tail_substeps() > 0
+
+
+# ------------------------------------- off-lattice velocities (section 4.2)
+@gpu
+@pytest.mark.parametrize("d,n,nv,frac", [(1, (97,), 16, 0.37), (2, (70, 37), 12, math.sqrt(2) / 3),
+                                         (3, (23, 9, 11), 8, 0.61)])
+def test_offlattice_free_transport_bit_exact(d, n, nv, frac):
+    """tau = +inf with dt = frac dx/dv: the pieces follow their accumulated
+    offsets v_k n dt; bit-exact against the oracle over 9 steps"""
+    announce("off-lattice free transport", d, n, nv, frac)
+    dx, dv = 1.0 / n[0], 0.5
+    rng = np.random.default_rng(200 + d)
+    f0 = rng.uniform(0.0, 1.0, (nv ** d, int(np.prod(n))))
+    from paper_1212_0204_amd import Solver
+    o = Oracle(d, n, dx, nv, dv, bc=(0,) * d, tau=math.inf, dt=frac * dx / dv)
+    s = Solver(d, n, dx, nv, dv, bc=(0,) * d, tau=math.inf, dt=frac * dx / dv)
+    o.set_f(f0)
+    s.set_state_f(f0)
+    o.step(9)
+    s.step(9)
+    assert np.array_equal(s.read_f(), o.f)
+
+
+@gpu
+@pytest.mark.parametrize("d,n,nv,bc,tau,frac,prec,scheme", [
+    (1, (200,), 64, (1,), 1e-2, 1.0 / 32, 0, 0),   # the Sod lattice at kinetic CFL 1
+    (1, (130,), 24, (1,), 2e-3, 0.45, 0, 3),       # with the WENO Euler solve
+    (2, (70, 37), 16, (0, 0), 1e-2, 0.3, 0, 0),
+    (2, (48, 40), 16, (1, 1), 5e-3, 0.7, 0, 1),    # FKS, outflow
+    (2, (67, 19), 12, (0, 1), None, 0.55, 1, 0),   # FP32 pieces at lambda = 1/2
+    (3, (20, 12, 10), 8, (0, 1, 0), 1e-2, 0.4, 0, 0),
+    (3, (23, 9, 11), 8, (1, 1, 1), None, 0.6, 1, 0),
+])
+def test_offlattice_parity(d, n, nv, bc, tau, frac, prec, scheme):
+    """HOFKS with a free time step: per-step shifts of floor(c) or ceil(c)
+    cells; 1e-12 (FP64) or 1e-5 (FP32 pieces) on U and f after 12 steps"""
+    dx = 1.0 / n[0]
+    dv = 0.25 if nv == 64 else 0.5
+    dt = frac * dx / dv
+    if tau is None:  # lambda = 1/2
+        tau = dt / math.log(2.0)
+    announce("off-lattice", d, n, nv, bc, tau, frac, prec, scheme)
+    from paper_1212_0204_amd import Solver
+    nc = int(np.prod(n))
+    fields = W.sod_tube(n[0]) if d == 1 else _random_fields(d, nc, 61)
+    o = Oracle(d, n, dx, nv, dv, bc=bc, tau=tau, scheme=scheme, dt=dt)
+    s = Solver(d, n, dx, nv, dv, bc=bc, tau=tau, precision=prec, scheme=scheme, dt=dt)
+    o.init_macro(*fields)
+    s.set_state_macro(*fields)
+    o.step(12)
+    s.step(12)
+    assert abs(s.dt - dt) == 0
+    tol = TOL64 if prec == 0 else TOL32
+    err = moment_errors(s.read_moments(), o.U, d)
+    print("off-lattice moment errors", err, "substeps", o.substeps)
+    assert err.max() < tol, err
+    assert rel_inf(s.read_f(), o.f) < tol
+    if scheme != 1:
+        assert s.counters()[0] == o.substeps
+
+
+@gpu
+def test_offlattice_checkpoint_resume_is_exact():
+    """the per-step shifts depend on the step count, which the state image
+    carries: a restored run continues bit for bit"""
+    from paper_1212_0204_amd import HofksError, Solver
+    announce("off-lattice checkpoint")
+    n, dx, nv, dv = (70, 37), 1.0 / 70, 12, 0.5
+    dt = 0.41 * dx / dv
+    fields = _random_fields(2, 70 * 37, 67)
+    s1 = Solver(2, n, dx, nv, dv, tau=3e-2, dt=dt)
+    s1.set_state_macro(*fields)
+    s1.step(5)
+    img = s1.read_state()
+    s1.step(6)
+    s2 = Solver(2, n, dx, nv, dv, tau=1.0, dt=dt)
+    s2.write_state(img)
+    s2.step(6)
+    assert np.array_equal(s2.read_moments(), s1.read_moments())
+    assert np.array_equal(s2.read_f(), s1.read_f())
+    s3 = Solver(2, n, dx, nv, dv, tau=3e-2)  # the lattice dt: another grid
+    with pytest.raises(HofksError):
+        s3.write_state(img)

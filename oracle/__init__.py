@@ -41,7 +41,7 @@ def _lib():
         d, i, vp = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
         dp = P(ctypes.c_double)
         lib.or_create.restype = vp
-        lib.or_create.argtypes = [i, P(i), d, i, d, P(i), i, d, d, P(i)]
+        lib.or_create.argtypes = [i, P(i), d, i, d, P(i), i, d, d, i, P(i)]
         lib.or_nstep.argtypes = [vp]
         lib.or_nstep.restype = ctypes.c_long
         lib.or_destroy.argtypes = [vp]
@@ -86,9 +86,13 @@ class Oracle:
     ``bc`` per axis: 0 periodic, 1 outflow (zero gradient).
     ``dt``: None for the lattice dt = dx/dv; a smaller value for off-lattice
     transport (pieces at accumulated offsets v_k n dt, section 4.2).
+    ``strang``: Strang splitting R_{dt/2} T_dt R_{dt/2} instead of the
+    first-order relax-then-transport step; ``f`` is then read after the
+    pending half relaxation.
     """
 
-    def __init__(self, d, n, dx, nv, dv, bc=None, tau=math.inf, scheme=0, dt=None):
+    def __init__(self, d, n, dx, nv, dv, bc=None, tau=math.inf, scheme=0, dt=None,
+                 strang=False):
         n = (list(n) + [1, 1, 1])[:3]
         bc = (list(bc if bc is not None else [0] * 3) + [0, 0, 0])[:3]
         self.d, self.n, self.nv1, self.dx, self.dv = d, n[:d], nv, dx, dv
@@ -100,7 +104,8 @@ class Oracle:
         ia = (ctypes.c_int * 3)(*n)
         ba = (ctypes.c_int * 3)(*bc)
         self._h = _lib().or_create(d, ia, float(dx), nv, float(dv), ba,
-                                   scheme, float(tau), float(dt or 0.0), ctypes.byref(st))
+                                   scheme, float(tau), float(dt or 0.0), int(bool(strang)),
+                                   ctypes.byref(st))
         if not self._h:
             raise OracleError(st.value, "create")
 

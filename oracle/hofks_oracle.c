@@ -79,6 +79,18 @@
  * as ((k dv) dt / dx) * n, each operation rounded (no contraction).  With
  * dt = dx/dv this is the lattice shift k.
  *
+ * Strang splitting (strang = 1; section 4.2 names it as the alternative to
+ * the first-order splitting): a step is R_{dt/2} T_dt R_{dt/2} with the
+ * HOFKS coupling on its transport.  A relaxation keeps the moments, so E is
+ * the same for two consecutive half relaxations and R_{a} R_{b} = R_{a+b}:
+ * n Strang steps are the first-order steps with the first relaxation weight
+ * lambda = exp(-dt/(2 tau)) and a pending half relaxation R_{dt/2} of the
+ * stored f, applied when f is read (the moments are unchanged by it).  With
+ * a change of tau between steps the step after it relaxes by
+ * exp(-dt/(2 tau_old)) exp(-dt/(2 tau_new)).  So the step n uses
+ * lambda = exp(-e), e = dt/2 (1/tau_{n-1}) + dt/2 (1/tau_n), with the first
+ * term absent at the first step (1/tau = 0 for tau = +inf, +inf for 0).
+ *
  * Layouts: U and u are component-major, U[r*Nc + j]; f is velocity-plane major,
  * f[k*Nc + j]; cells are x-fastest, j = (jz*Ny + jy)*Nx + jx; velocities are
  * x-fastest, k = (iz*n + iy)*n + ix with k_a = i_a - n/2 (integer division).
@@ -106,6 +118,8 @@ typedef struct or_state {
                            3 HOFKS with the WENO Euler solve                 */
   double tau, lam, mu;  /* relaxation time, exp(-dt/tau), 1 - exp(-dt/tau)   */
   int offl;             /* 1: dt given (off-lattice transport), 0: dt = dx/dv */
+  int strang;           /* 1: Strang splitting, 0: first order (relax, shift) */
+  double inv_prev;      /* 1/tau of the previous step (Strang)                */
   long nstep;           /* steps taken since the initial data (off-lattice)  */
   double *cvel;         /* nv1: c = v dt / dx per node of one axis            */
   int *shift;           /* nv1: cells moved by the current step, per node     */
@@ -487,9 +501,26 @@ static int weno_solve(const or_state *S, double *U, double dt, int *nsub) {
 
 /* ---------------------------------------------- section 4.3.1: HOFKS step */
 
+/* 1/tau with 1/inf = 0 and 1/0 = inf */
+static double inv_tau(double tau) {
+  if (isinf(tau)) return 0.0;
+  if (tau == 0.0) return INFINITY;
+  return 1.0 / tau;
+}
+
+/* Strang: exp(-e) and 1 - exp(-e), e = dt/2 (1/tau_prev) + dt/2 (1/tau) */
+static void strang_weights(double dt, double ip, double in, double *lam, double *mu) {
+  const double e = 0.5 * dt * ip + 0.5 * dt * in;
+  *lam = exp(-e);
+  *mu = -expm1(-e);
+}
+
 static int step_once(or_state *S) {
   const int nm = S->nm, nc = S->nc, nv = S->nv;
-  const double lam = S->lam, mu = S->mu, w = S->w;
+  double lam = S->lam, mu = S->mu;
+  if (S->strang)
+    strang_weights(S->dt, S->nstep > 1 ? S->inv_prev : 0.0, inv_tau(S->tau), &lam, &mu);
+  const double w = S->w;
   int st = OR_OK;
 
   /* 1. E^n = E[U^n] in every cell (not needed when lambda == 1) */
@@ -635,7 +666,8 @@ static int set_tau(or_state *S, double tau) {
 }
 
 or_state *or_create(int d, const int *n, double dx, int nv1, double dv,
-                    const int *bc, int scheme, double tau, double dt, int *status) {
+                    const int *bc, int scheme, double tau, double dt, int strang,
+                    int *status) {
   *status = OR_EINVAL;
   if (d < 1 || d > 3 || nv1 < 2 || !(dx > 0) || !(dv > 0) || scheme < 0 ||
       scheme > 3)
@@ -664,6 +696,11 @@ or_state *or_create(int d, const int *n, double dx, int nv1, double dv,
     S->dt = dt;
     S->offl = 1;
   }
+  if (strang < 0 || strang > 1) {
+    free(S);
+    return NULL;
+  }
+  S->strang = strang;
   S->w = pow(dv, d);
   S->nv1 = nv1;
   S->nv = 1;
@@ -781,6 +818,7 @@ int or_step(or_state *S, int nsteps) {
     S->nstep++;
     int st = step_once(S);
     if (st) return st;
+    S->inv_prev = inv_tau(S->tau);
   }
   return OR_OK;
 }
@@ -788,8 +826,26 @@ int or_step(or_state *S, int nsteps) {
 void or_get_U(const or_state *S, double *U) {
   memcpy(U, S->U, sizeof(double) * S->nm * S->nc);
 }
+/* f at t^n.  With Strang splitting, after a step, the stored f still waits
+ * for the half relaxation R_{dt/2} (with the tau of the last step) towards
+ * E[U^n]; it is applied here (non-physical U gives NaN) */
 void or_get_f(const or_state *S, double *f) {
   memcpy(f, S->f, sizeof(double) * (size_t)S->nv * S->nc);
+  if (!S->strang || S->nstep == 0) return;
+  double lh, mh;
+  strang_weights(S->dt, S->inv_prev, 0.0, &lh, &mh);
+  if (lh == 1.0) return;
+  double Uj[5];
+  double *Ej = (double *)malloc(sizeof(double) * S->nv);
+  for (int j = 0; j < S->nc; ++j) {
+    for (int r = 0; r < S->nm; ++r) Uj[r] = S->U[r * S->nc + j];
+    int bad = equilibrium(S, Uj, Ej);
+    for (int k = 0; k < S->nv; ++k) {
+      double *p = f + (size_t)k * S->nc + j;
+      *p = bad ? NAN : (lh == 0.0 ? Ej[k] : lh * *p + mh * Ej[k]);
+    }
+  }
+  free(Ej);
 }
 void or_get_delta(const or_state *S, double *dl) {
   memcpy(dl, S->delta, sizeof(double) * S->nm * S->nc);

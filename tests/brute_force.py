@@ -115,7 +115,7 @@ class Brute:
     """scheme 0 HOFKS, 1 FKS (U_E := U_M), 2 HOFKS with phi == 1, 3 HOFKS
     with the WENO Euler solve (three-stage SSP Runge-Kutta, CFL 0.4)"""
 
-    def __init__(self, d, n, dx, nv, dv, bc, tau, scheme=0, dt=None):
+    def __init__(self, d, n, dx, nv, dv, bc, tau, scheme=0, dt=None, strang=False):
         self.d, self.n, self.bc, self.scheme = d, tuple(n), tuple(bc), scheme
         self.dx, self.dv = mp.mpf(dx), mp.mpf(dv)
         self.dt = self.dx / self.dv  # lattice: v_k dt = k dx
@@ -142,9 +142,13 @@ class Brute:
         self.f = None
         self.U = None
         self.weno = Weno5() if scheme == 3 else None
+        # Strang splitting R_{dt/2} T R_{dt/2}: the state kept here is the
+        # synchronised f (after the second half relaxation)
+        self.strang = strang
 
     # --------------------------------------------------------------- set-up
     def set_tau(self, tau):
+        self.tau = tau
         if tau == float("inf"):
             self.lam, self.mu = mp.mpf(1), mp.mpf(0)
         elif tau == 0:
@@ -152,6 +156,16 @@ class Brute:
         else:
             self.lam = mp.exp(-self.dt / mp.mpf(tau))
             self.mu = 1 - self.lam
+
+    def half_relax(self):
+        """R_{dt/2} of the whole grid: f <- l f + (1 - l) E[U], l = exp(-dt/(2 tau));
+        U is unchanged (C E[U] = U)"""
+        if self.tau == float("inf"):
+            return
+        l = mp.mpf(0) if self.tau == 0 else mp.exp(-self.dt / (2 * mp.mpf(self.tau)))
+        for j, U in enumerate(self.U):
+            E = self.equilibrium(U)
+            self.f[j] = [l * fk + (1 - l) * ek for fk, ek in zip(self.f[j], E)]
 
     def moments(self, g):
         nm = self.d + 2
@@ -330,7 +344,37 @@ class Brute:
     # ------------------------------------------------------------ one step
     def step(self, nsteps=1):
         for _ in range(nsteps):
-            self._step()
+            if self.strang and self.scheme == 1:
+                # FKS: R_{dt/2}, transport, R_{dt/2} applied literally
+                self.half_relax()
+                saved = (self.lam, self.mu)
+                self.lam, self.mu = mp.mpf(1), mp.mpf(0)
+                self._step()
+                self.lam, self.mu = saved
+                self.half_relax()
+            elif self.strang:
+                # HOFKS: the two half relaxations between transports act as
+                # one full relaxation R_dt, whose equilibrium part the Euler
+                # solve advances; the first step has only the half after the
+                # initial data, and the last half is applied on reading f
+                saved = (self.lam, self.mu)
+                if self.nstep == 0 and self.tau != float("inf"):
+                    self.lam = mp.mpf(0) if self.tau == 0 else \
+                        mp.exp(-self.dt / (2 * mp.mpf(self.tau)))
+                    self.mu = 1 - self.lam
+                self._step()
+                self.lam, self.mu = saved
+            else:
+                self._step()
+
+    def f_synchronised(self):
+        """f at t^n: for the merged Strang form, the pending R_{dt/2}"""
+        if not (self.strang and self.scheme != 1 and self.nstep > 0):
+            return self.f
+        keep = [list(fj) for fj in self.f]
+        self.half_relax()
+        out, self.f = self.f, keep
+        return out
 
     def _step(self):
         lam, mu, d = self.lam, self.mu, self.d
@@ -379,4 +423,5 @@ class Brute:
         return [[float(self.U[j][r]) for j in range(len(self.cells))] for r in range(self.d + 2)]
 
     def f_array(self):
-        return [[float(self.f[j][q]) for j in range(len(self.cells))] for q in range(len(self.K))]
+        f = self.f_synchronised()
+        return [[float(f[j][q]) for j in range(len(self.cells))] for q in range(len(self.K))]

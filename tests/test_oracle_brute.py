@@ -116,3 +116,29 @@ def test_oracle_matches_brute_force_off_lattice(n, bc, tau, scheme):
     b.step(4)
     eU, ef = _compare(o, b, d)
     assert eU < TOL and ef < TOL, (eU, ef)
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 3])
+@pytest.mark.parametrize("tau", [0.05, 1.0, 0.0])
+@pytest.mark.parametrize("n,bc,offl", [((5,), (1,), False), ((5,), (0,), True), ((3, 3), (0, 1), False)])
+def test_oracle_matches_brute_force_strang(n, bc, offl, tau, scheme):
+    """Strang splitting R_{dt/2} T R_{dt/2} per step.  For FKS the brute
+    force applies the two half relaxations literally (an equilibrium formed
+    at each); the oracle merges consecutive halves into one relaxation and
+    applies the last half when f is read.  For HOFKS and its WENO variant
+    both use the merged form (the merged relaxation's equilibrium part is
+    the one the Euler solve advances)."""
+    d = len(n)
+    nv = 5 if d == 1 else 3
+    dv = 1.25
+    dx = 1.0 / n[0]
+    dt = 0.37 * dx / dv if offl else None
+    f0, _ = _start(d, n, nv, dv, seed=3000 + 10 * d + sum(bc))
+    o = Oracle(d, n, dx, nv, dv, bc=bc, tau=tau, scheme=scheme, dt=dt, strang=True)
+    b = Brute(d, n, dx, nv, dv, bc, tau, scheme, dt=dt, strang=True)
+    o.set_f(f0)
+    b.set_f(f0)
+    o.step(3)
+    b.step(3)
+    eU, ef = _compare(o, b, d)
+    assert eU < TOL and ef < TOL, (eU, ef)

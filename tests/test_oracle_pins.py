@@ -676,3 +676,58 @@ def test_offlattice_at_the_lattice_step_is_the_lattice_scheme(tau):
 def test_offlattice_rejects_a_step_beyond_the_lattice():
     with pytest.raises(OracleError):
         Oracle(1, (10,), 0.1, 8, 0.5, dt=0.21)
+
+
+# ------------------------------------------- Strang splitting (section 4.2)
+@pytest.mark.parametrize("tau", [0.05, 0.4, 3.0])
+def test_strang_homogeneous_relaxation_closed_form(tau):
+    """a spatially uniform non-equilibrium f: transport is the identity and
+    R_{dt/2} (R_dt)^{n-1} R_{dt/2} = R_{n dt}, so the f read after n Strang
+    steps is E + lambda^n (f0 - E) and U stays constant"""
+    o = Oracle(1, (8,), 0.125, 24, 0.5, tau=tau, scheme=1, strang=True)
+    v = o.velocities[:, 0]
+    g = np.exp(-0.5 * (v - 1.0) ** 2) + 0.6 * np.exp(-2.0 * (v + 1.5) ** 2)
+    f0 = np.tile(g[:, None], (1, 8))
+    o.set_f(f0)
+    U0 = o.U
+    E = o.equilibrium(U0[:, 0])
+    for n in (1, 2, 5):
+        o.step(n - o.nstep)
+        lam = math.exp(-o.dt / tau)
+        expect = E[:, None] + lam ** n * (f0 - E[:, None])
+        np.testing.assert_allclose(o.f, expect, rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(o.U, U0, rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 3])
+def test_strang_conservation_and_consistency(scheme):
+    """periodic totals conserved and P(f) = U for the f read after the
+    pending half relaxation"""
+    n, nv, dv = (20, 18), 12, 0.5
+    dx = 1.0 / 20
+    rng = np.random.default_rng(91)
+    fields = (1.0 + 0.2 * rng.uniform(-1, 1, 360), 0.1 * rng.uniform(-1, 1, (2, 360)),
+              1.0 + 0.2 * rng.uniform(-1, 1, 360))
+    o = Oracle(2, n, dx, nv, dv, tau=2e-2, scheme=scheme, strang=True)
+    o.init_macro(*fields)
+    tot0 = o.U.sum(1)
+    o.step(5)
+    U = o.U
+    assert (np.abs(U.sum(1) - tot0) / np.abs(U[0]).sum()).max() < 1e-13
+    np.testing.assert_allclose(moment_matrix(o) @ o.f, U, rtol=0, atol=1e-13)
+
+
+def test_strang_fks_moments_from_equilibrium_equal_first_order():
+    """R_{dt/2} leaves an equilibrium and all moments unchanged, so from
+    equilibrium data the FKS moment trajectory of Strang splitting is the
+    first-order one; only the distribution read out differs"""
+    nx = 40
+    rho, u, th = W.sod_tube(nx)
+    a = Oracle(1, (nx,), 1.0 / nx, 16, 0.5, bc=(1,), tau=0.05, scheme=1)
+    b = Oracle(1, (nx,), 1.0 / nx, 16, 0.5, bc=(1,), tau=0.05, scheme=1, strang=True)
+    a.init_macro(rho, u, th)
+    b.init_macro(rho, u, th)
+    a.step(6)
+    b.step(6)
+    np.testing.assert_allclose(a.U, b.U, rtol=1e-14, atol=1e-15)  # to the rounding of lambda
+    assert np.abs(a.f - b.f).max() > 1e-6

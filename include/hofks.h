@@ -77,6 +77,14 @@ typedef struct {
                        ceil(c (n+1) - 1/2) - ceil(c n - 1/2) cells,
                        c = v_k dt / dx; n_vel a multiple of 4 in 2D/3D;
                        not for batches or the closure form                   */
+  int splitting;    /* 0: first order, relaxation then transport (sections
+                       4.2, 4.3.1); 1: Strang, R_{dt/2} T_dt R_{dt/2} per
+                       step (section 4.2): consecutive half relaxations act
+                       as one (the moments are unchanged by a relaxation), so
+                       the first step after the state is set relaxes by half
+                       and hofks_read_f applies the last step's pending half
+                       towards E[U^n]; U is the same either way.  Not for
+                       batches or the closure form                           */
 } hofks_grid_desc;
 
 /* Bytes of device workspace a context with this descriptor needs. */

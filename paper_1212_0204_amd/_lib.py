@@ -29,7 +29,8 @@ SYMBOLS = [
 class GridDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n_cells", ctypes.c_int * 3), ("dx", ctypes.c_double),
                 ("n_vel", ctypes.c_int), ("dv", ctypes.c_double), ("bc", ctypes.c_int * 3),
-                ("precision", ctypes.c_int), ("scheme", ctypes.c_int), ("dt", ctypes.c_double)]
+                ("precision", ctypes.c_int), ("scheme", ctypes.c_int), ("dt", ctypes.c_double),
+                ("splitting", ctypes.c_int)]
 
 
 _lib = None

@@ -60,6 +60,8 @@ __device__ __forceinline__ Geom tube_geom(const TubeDev& T) {
   G.mu = T.mu;
   G.gam = T.gam;
   G.sfac = 2.0;
+  G.lam_r = T.lam;
+  G.mu_r = T.mu;
   return G;
 }
 

@@ -122,6 +122,8 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
     return fmt_err(err, "precision must be 0 or 1"), HOFKS_EINVAL;
   if (desc->scheme < 0 || desc->scheme > 3)
     return fmt_err(err, "scheme must be 0, 1, 2 or 3"), HOFKS_EINVAL;
+  if (desc->splitting < 0 || desc->splitting > 1)
+    return fmt_err(err, "splitting must be 0 or 1"), HOFKS_EINVAL;
   Geom& G = P->G;
   G.nc = 1;
   for (int a = 0; a < 3; ++a) {
@@ -151,8 +153,8 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
     G.offl = 1;
   }
   G.w = std::pow(desc->dv, d);
-  G.lam = 1.0;
-  G.mu = 0.0;
+  G.lam = G.lam_r = 1.0;
+  G.mu = G.mu_r = 0.0;
   G.gam = (d + 2.0) / d;
   G.sfac = desc->scheme == 3 ? 2.5 : 2.0;
   P->d = d;
@@ -281,6 +283,8 @@ struct hofks_ctx {
   int s_cap;
   int s_known;  // Euler sub-steps of the last step seen by the host
   int euler_k;  // > 0: per-sub-step Euler launches before the tail (0: s_known + 1)
+  bool strang;      // Strang splitting: half relaxations around each transport
+  double inv_prev;  // 1/tau of the last step taken (Strang)
   long steps;
   bool ready;
   int kng, kunr;  // kinetic kernel: wavefronts per block, loads issued ahead
@@ -333,6 +337,49 @@ hofks_status hip_fail(hofks_ctx* c, hipError_t e, const char* what) {
 
 unsigned nblk(size_t n, unsigned b = 256) { return (unsigned)((n + b - 1) / b); }
 
+// 1/tau with 1/inf = 0 and 1/0 = inf
+double inv_tau(double tau) {
+  if (std::isinf(tau)) return 0.0;
+  if (tau == 0.0) return INFINITY;
+  return 1.0 / tau;
+}
+
+// Strang splitting: exp(-e), 1 - exp(-e) with e = dt/2 ip + dt/2 in
+void strang_weights(double dt, double ip, double in, double* lam, double* mu) {
+  const double e = 0.5 * dt * ip + 0.5 * dt * in;
+  *lam = std::exp(-e);
+  *mu = -std::expm1(-e);
+}
+
+// relaxation weights of the next step (lam, mu) and of the one after it
+// (lam_r, mu_r: the weights the records formed by the next step are for).
+// First-order splitting: lambda = exp(-dt/tau) for both.  Strang splitting:
+// the half relaxation closing the previous step (its tau) merged with the
+// half opening the next (none before the first step after the state is set).
+void set_step_weights(hofks_ctx* c) {
+  Geom& G = c->P.G;
+  const double tau = c->tau;
+  if (!c->strang) {
+    if (std::isinf(tau)) {
+      G.lam = 1.0;
+      G.mu = 0.0;
+    } else if (tau == 0.0) {
+      G.lam = 0.0;
+      G.mu = 1.0;
+    } else {
+      G.lam = std::exp(-G.dt / tau);
+      G.mu = -std::expm1(-G.dt / tau);
+    }
+    G.lam_r = G.lam;
+    G.mu_r = G.mu;
+    return;
+  }
+  const double in = inv_tau(tau);
+  strang_weights(G.dt, c->steps > 0 ? c->inv_prev : 0.0, in, &G.lam, &G.mu);
+  strang_weights(G.dt, in, in, &G.lam_r, &G.mu_r);
+}
+
+
 double* slot_set(hofks_ctx* c, int set) { return c->slots + (size_t)set * SET_D; }
 int rpar(const hofks_ctx* c) { return (int)(c->steps & 1); }   // buffer holding U^n, rec^n
 int rset(const hofks_ctx* c) { return (int)(c->steps % 3); }   // speeds of U^n
@@ -376,8 +423,11 @@ template <int D, typename T>
 hofks_status launch_cell_init(hofks_ctx* c, int mode) {
   const Plan& P = c->P;
   const int rp = rpar(c);
+  Geom Gi = P.G;  // the records formed here are read by the next step
+  Gi.lam_r = Gi.lam;
+  Gi.mu_r = Gi.mu;
   hipLaunchKernelGGL((k_cell_init<D, T>), dim3(nblk(P.G.nc)), dim3(256), 0, c->stream, c->U[rp],
-                     c->cf, (T*)c->rec[rp], c->vt, c->part, slot_set(c, rset(c)), c->flag, P.G,
+                     c->cf, (T*)c->rec[rp], c->vt, c->part, slot_set(c, rset(c)), c->flag, Gi,
                      P.A, mode);
   HIPCHK(c, hipGetLastError());
   return HOFKS_OK;
@@ -746,11 +796,14 @@ hofks_status step_impl(hofks_ctx* c, int nsteps) {
   hofks_status st = HOFKS_OK;
   for (int it = 0; it < nsteps && !st; ++it) {
     c->fork_next = it + 1 < nsteps;
+    if (c->strang) set_step_weights(c);
     st = launch_step<D, T>(c);
     if (st) break;
     c->cur ^= 1;
     c->steps++;
+    c->inv_prev = inv_tau(c->tau);
   }
+  if (c->strang) set_step_weights(c);
   c->fork_next = c->fork_pending = false;
   return st;
 }
@@ -829,6 +882,8 @@ hofks_status refresh(hofks_ctx* c) {
 hofks_status reset_counters(hofks_ctx* c) {
   c->cur = 0;
   c->steps = 0;
+  c->inv_prev = 0.0;
+  set_step_weights(c);  // Strang: the first step opens with a half relaxation
   hofks_status st = zero_ints(c, c->flag, 16);
   if (st) return st;
   if (c->cdfl) {  // closure form: every cell marked kinetic for its first
@@ -881,6 +936,7 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
     return HOFKS_ESIZE;
   }
   c->desc = *desc;
+  c->strang = desc->splitting == 1;
   c->stream = (hipStream_t)hip_stream;
   c->ws = (unsigned char*)dev_ws;
   const Plan& P = c->P;
@@ -961,17 +1017,7 @@ hofks_status hofks_set_tau(hofks_ctx* c, double tau) {
   if (c->batch) return fmt_err(c->err, "tube relaxation times are fixed at creation"), HOFKS_EINVAL;
   if (!(tau >= 0.0)) return fmt_err(c->err, "tau must be >= 0 or +inf"), HOFKS_EINVAL;
   c->tau = tau;
-  Geom& G = c->P.G;
-  if (std::isinf(tau)) {
-    G.lam = 1.0;
-    G.mu = 0.0;
-  } else if (tau == 0.0) {
-    G.lam = 0.0;
-    G.mu = 1.0;
-  } else {
-    G.lam = std::exp(-G.dt / tau);
-    G.mu = -std::expm1(-G.dt / tau);
-  }
+  set_step_weights(c);
   if (c->ready) return refresh(c);
   return HOFKS_OK;
 }
@@ -1085,6 +1131,10 @@ hofks_status hofks_read_f(hofks_ctx* c, double* f, size_t bytes) {
   if (bytes < tot * 8) return HOFKS_ESIZE;
   const size_t per = std::max<size_t>(1, (tot * P.tsize) / (nc * 8));
   double* stage = (double*)c->g[c->cur ^ 1];
+  // Strang splitting: f at t^n includes the pending half relaxation of the
+  // last step towards E[U^n] (the stored pieces wait for it)
+  double blend = 1.0, mh = 0.0;
+  if (c->strang && c->steps > 0) strang_weights(P.G.dt, c->inv_prev, 0.0, &blend, &mh);
   for (size_t k0 = 0; k0 < (size_t)P.G.nv; k0 += per) {
     const size_t nk = std::min(per, (size_t)P.G.nv - k0);
     hofks_status st = dispatch(c, [&](auto D, auto t) -> hofks_status {
@@ -1092,7 +1142,8 @@ hofks_status hofks_read_f(hofks_ctx* c, double* f, size_t bytes) {
       using T = decltype(t);
       hipLaunchKernelGGL((k_materialize<DD, T>), dim3(nblk(nk * nc)), dim3(256), 0, c->stream,
                          (const T*)c->g[c->cur], c->cf, stage, (int)k0, (int)nk, P.G,
-                         c->clos_dirty ? (const T*)c->rec[rpar(c)] : nullptr);
+                         c->clos_dirty ? (const T*)c->rec[rpar(c)] : nullptr, blend,
+                         blend < 1.0 ? (const T*)c->rec[rpar(c)] : nullptr);
       HIPCHK(c, hipGetLastError());
       return HOFKS_OK;
     });
@@ -1109,8 +1160,8 @@ hofks_status hofks_read_f(hofks_ctx* c, double* f, size_t bytes) {
 // Eulerian pieces g; f = g + w m.cf).  Enough to continue stepping exactly.
 struct StateHeader {
   char magic[8];
-  int version, dim, n[3], nv1, precision, scheme, bc[3];
-  double dx, dv, tau, dt;
+  int version, dim, n[3], nv1, precision, scheme, bc[3], splitting;
+  double dx, dv, tau, dt, inv_prev;
   long long steps;
   double speeds[ASTR];
 };
@@ -1154,6 +1205,8 @@ hofks_status hofks_read_state(hofks_ctx* c, void* host, size_t bytes) {
   h.dv = P.G.dv;
   h.tau = c->tau;
   h.dt = P.G.dt;
+  h.splitting = c->desc.splitting;
+  h.inv_prev = c->inv_prev;
   h.steps = c->steps;
   HIPCHK(c, hipMemcpyAsync(h.speeds, slot_set(c, rset(c)), sizeof(h.speeds), hipMemcpyDeviceToHost,
                            c->stream));
@@ -1179,7 +1232,8 @@ hofks_status hofks_write_state(hofks_ctx* c, const void* host, size_t bytes) {
   std::memcpy(&h, host, sizeof(h));
   bool same = std::memcmp(h.magic, "HOFKSST1", 8) == 0 && h.version == 2 && h.dim == P.d &&
               h.nv1 == P.G.nv1 && h.precision == P.prec && h.scheme == c->desc.scheme &&
-              h.dx == P.G.dx && h.dv == P.G.dv && h.dt == P.G.dt && h.steps >= 0;
+              h.dx == P.G.dx && h.dv == P.G.dv && h.dt == P.G.dt &&
+              h.splitting == c->desc.splitting && h.steps >= 0;
   for (int a = 0; a < 3; ++a) same = same && h.n[a] == P.G.n[a] && h.bc[a] == P.G.bc[a];
   if (!same) return fmt_err(c->err, "state image does not match this grid"), HOFKS_EINVAL;
   hofks_status st = hofks_set_tau(c, h.tau);  // lambda of the stored records
@@ -1187,6 +1241,8 @@ hofks_status hofks_write_state(hofks_ctx* c, const void* host, size_t bytes) {
   st = reset_counters(c);
   if (st) return st;
   c->steps = h.steps;
+  c->inv_prev = h.inv_prev;
+  set_step_weights(c);
   c->cur = 0;
   const unsigned char* o = (const unsigned char*)host + sizeof(StateHeader);
   const size_t ub = (size_t)P.nm * P.G.nc * sizeof(double);
@@ -1322,7 +1378,8 @@ hofks_status batch_plan(const hofks_grid_desc* descs, const double* taus, int n,
   constexpr int RS = rec_stride<1, float>();
   for (int i = 0; i < n; ++i) {
     const hofks_grid_desc& d = descs[i];
-    if (d.dim != 1 || d.precision != 1 || d.bc[0] != 1 || d.scheme != 0 || d.dt != 0.0)
+    if (d.dim != 1 || d.precision != 1 || d.bc[0] != 1 || d.scheme != 0 || d.dt != 0.0 ||
+        d.splitting != 0)
       return fmt_err(err, "tube %d: batches hold 1D outflow HOFKS tubes in FP32", i), HOFKS_EINVAL;
     Plan P;
     hofks_status st = make_plan(&d, &P, err);
@@ -1411,9 +1468,10 @@ Geom host_tube_geom(const TubeDev& T) {
   G.dv = T.dv;
   G.dt = T.dt;
   G.w = T.w;
-  G.lam = T.lam;
-  G.mu = T.mu;
+  G.lam = G.lam_r = T.lam;
+  G.mu = G.mu_r = T.mu;
   G.gam = T.gam;
+  G.sfac = 2.0;
   return G;
 }
 
@@ -1997,6 +2055,7 @@ hofks_status hofks_closure_enable(hofks_ctx* c, const void* packed, double sigma
     return fmt_err(c->err, "the closure form is defined for 2D-2V grids"), HOFKS_EINVAL;
   if (c->desc.scheme != 0) return fmt_err(c->err, "the closure form needs the HOFKS scheme"), HOFKS_EINVAL;
   if (c->P.G.offl) return fmt_err(c->err, "the closure form needs the lattice dt = dx/dv"), HOFKS_EINVAL;
+  if (c->strang) return fmt_err(c->err, "the closure form needs first-order splitting"), HOFKS_EINVAL;
   if (!packed || ((uintptr_t)packed & 15))
     return fmt_err(c->err, "network weights: 16-byte aligned device pointer expected"), HOFKS_EINVAL;
   if (!std::isfinite(sigma) || std::isnan(threshold))
@@ -2022,6 +2081,7 @@ hofks_status hofks_closure_snapshot(hofks_ctx* c, float* x, float* t) {
   if (!c->ready) return fmt_err(c->err, "set the state before stepping"), HOFKS_ESTATE;
   if (c->desc.scheme != 0) return fmt_err(c->err, "the closure form needs the HOFKS scheme"), HOFKS_EINVAL;
   if (c->P.G.offl) return fmt_err(c->err, "the closure form needs the lattice dt = dx/dv"), HOFKS_EINVAL;
+  if (c->strang) return fmt_err(c->err, "the closure form needs first-order splitting"), HOFKS_EINVAL;
   if (!(c->P.G.lam >= 1e-12) || !(c->P.G.mu > 0.0))
     return fmt_err(c->err, "training targets need 1e-12 <= lambda < 1 (finite tau, not too small)"),
            HOFKS_EINVAL;

@@ -61,6 +61,8 @@ struct Geom {
   int offl;           // 1: a free time step (off-lattice transport), 0: dt = dx/dv
   double dx, dv, dt, w, lam, mu, gam;
   double sfac;        // sub-steps s = ceil(sfac dt sum_a alpha_a / dx): 2 MUSCL, 2.5 WENO
+  double lam_r, mu_r; // relaxation weights of the step that reads the records formed
+                      // (equal to lam, mu except around Strang half relaxations)
 };
 
 struct Mat {
@@ -472,7 +474,7 @@ __device__ __forceinline__ bool cell_record(const double* Un, const double* cfv,
 #pragma unroll
     for (int a = 0; a < D; ++a) speed[a] = fabs(u[a]) + c;
   }
-  const bool need_eq = G.mu != 0.0;
+  const bool need_eq = G.mu_r != 0.0;
   constexpr int RS = rec_stride<D, T>();
   T rv[RS];
 #pragma unroll
@@ -483,7 +485,7 @@ __device__ __forceinline__ bool cell_record(const double* Un, const double* cfv,
   rv[D + 1] = (T)(valid ? beta : -beta);  // negative: pieces of this cell not kept
 #pragma unroll
   for (int r = 0; r < NM; ++r) {
-    rv[NM + r] = (T)(need_eq ? G.w * (G.lam * cfv[r] + G.mu * cE[r]) : G.w * (G.lam * cfv[r]));
+    rv[NM + r] = (T)(need_eq ? G.w * (G.lam_r * cfv[r] + G.mu_r * cE[r]) : G.w * (G.lam_r * cfv[r]));
     rv[2 * NM + r] = (T)(G.w * cE[r]);
   }
 #pragma unroll
@@ -1436,7 +1438,8 @@ __global__ void k_piece_sums(const T* __restrict__ g, double* __restrict__ part,
 template <int D, typename T>
 __global__ void k_materialize(const T* __restrict__ g, const double* __restrict__ cf,
                               double* __restrict__ out, int k0, int nk, Geom G,
-                              const T* __restrict__ rec = nullptr) {
+                              const T* __restrict__ rec = nullptr, double blend = 1.0,
+                              const T* __restrict__ rec_e = nullptr) {
   constexpr int NM = D + 2;
   constexpr int RS = rec_stride<D, T>();
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1465,7 +1468,28 @@ __global__ void k_materialize(const T* __restrict__ g, const double* __restrict_
     return;
   }
   corr += 0.5 * vsq * cf[(size_t)(NM - 1) * G.nc + j];
-  out[idx] = (double)g[(size_t)(k0 + (int)(idx / G.nc)) * G.nc + j] + G.w * corr;
+  const double fv = (double)g[(size_t)(k0 + (int)(idx / G.nc)) * G.nc + j] + G.w * corr;
+  if (!rec_e) {
+    out[idx] = fv;
+    return;
+  }
+  // Strang splitting: the pending half relaxation towards E of U^n,
+  // E = exp(lp - beta |v - u|^2) + e . m(v) from the record of the cell
+  const T* r = rec_e + (size_t)j * RS;
+  int kk = k0 + (int)(idx / G.nc);
+  double qq = 0.0, ec = (double)r[2 * NM], v2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const double v = (kk % G.nv1 - G.kofs) * G.dv;
+    kk /= G.nv1;
+    const double du = v - (double)r[1 + a];
+    qq += du * du;
+    ec += v * (double)r[2 * NM + 1 + a];
+    v2 += v * v;
+  }
+  ec += 0.5 * v2 * (double)r[3 * NM - 1];
+  const double E = exp((double)r[0] - (double)r[D + 1] * qq) + ec;
+  out[idx] = blend == 0.0 ? E : blend * fv + (1.0 - blend) * E;
 }
 
 // g planes [k0, k0+nk) <- FP64 staging (storage precision conversion)

@@ -35,10 +35,12 @@ class Solver:
     bc per axis: 0 periodic, 1 outflow.
     dt: None for the lattice dt = dx/dv; 0 < dt <= dx/dv for off-lattice
     transport.
+    strang: Strang splitting R_{dt/2} T_dt R_{dt/2} instead of the
+    first-order relaxation-then-transport step.
     """
 
     def __init__(self, dim, n_cells, dx, n_vel, dv, bc=None, precision=0, scheme=0,
-                 tau=math.inf, stream=None, dt=None):
+                 tau=math.inf, stream=None, dt=None, strang=False):
         L = _lib.lib()
         if not torch.cuda.is_available():
             raise RuntimeError("the HOFKS library needs a ROCm GPU")
@@ -46,7 +48,7 @@ class Solver:
         b = (list(bc if bc is not None else [0, 0, 0]) + [0, 0, 0])[:3]
         self.desc = _lib.GridDesc(dim, (ctypes.c_int * 3)(*n), float(dx), int(n_vel), float(dv),
                                   (ctypes.c_int * 3)(*b), int(precision), int(scheme),
-                                  float(dt or 0.0))
+                                  float(dt or 0.0), int(bool(strang)))
         self.d, self.nm = dim, dim + 2
         self.nc = int(np.prod(n[:dim]))
         self.nv = int(n_vel) ** dim

@@ -584,3 +584,72 @@ def test_offlattice_checkpoint_resume_is_exact():
     s3 = Solver(2, n, dx, nv, dv, tau=3e-2)  # the lattice dt: another grid
     with pytest.raises(HofksError):
         s3.write_state(img)
+
+
+# ---------------------------------------- Strang splitting (section 4.2)
+@gpu
+@pytest.mark.parametrize("d,n,nv,bc,tau,prec,scheme,frac", [
+    (1, (200,), 64, (1,), 1e-2, 0, 0, None),
+    (1, (130,), 24, (1,), 0.05, 0, 1, 0.6),        # FKS, off-lattice
+    (2, (70, 37), 16, (0, 0), None, 0, 0, None),   # lambda = 1/2
+    (2, (48, 40), 16, (1, 1), 5e-3, 0, 3, None),   # WENO
+    (2, (67, 19), 12, (0, 1), None, 1, 0, 0.55),   # FP32 pieces, off-lattice
+    (3, (20, 12, 10), 8, (0, 1, 0), None, 0, 0, None),
+])
+def test_strang_parity(d, n, nv, bc, tau, prec, scheme, frac):
+    """Strang splitting: the first step relaxes by half, the read f carries
+    the pending half relaxation; 1e-12 (FP64) or 1e-5 (FP32) on U and f
+    after 1 and after 8 steps"""
+    dx = 1.0 / n[0]
+    dv = 0.25 if nv == 64 else 0.5
+    dt = frac * dx / dv if frac else None
+    h = dt if dt else dx / dv
+    if tau is None:
+        tau = h / math.log(2.0)
+    announce("strang", d, n, nv, bc, tau, prec, scheme, frac)
+    from paper_1212_0204_amd import Solver
+    nc = int(np.prod(n))
+    fields = W.sod_tube(n[0]) if d == 1 else _random_fields(d, nc, 71)
+    o = Oracle(d, n, dx, nv, dv, bc=bc, tau=tau, scheme=scheme, dt=dt, strang=True)
+    s = Solver(d, n, dx, nv, dv, bc=bc, tau=tau, precision=prec, scheme=scheme, dt=dt, strang=True)
+    o.init_macro(*fields)
+    s.set_state_macro(*fields)
+    tol = TOL64 if prec == 0 else TOL32
+    for steps in (1, 7):
+        o.step(steps)
+        s.step(steps)
+        err = moment_errors(s.read_moments(), o.U, d)
+        ef = rel_inf(s.read_f(), o.f)
+        print("strang moment errors", err, "f", ef)
+        assert err.max() < tol, err
+        assert ef < tol, ef
+
+
+@gpu
+def test_strang_tau_change_and_checkpoint():
+    """a tau change between steps merges the two different half relaxations;
+    a state image taken in between continues bit for bit"""
+    announce("strang tau change + checkpoint")
+    from paper_1212_0204_amd import Solver
+    rho, u, th = W.sod_tube(96)
+    o = Oracle(1, (96,), 1 / 96, 16, 0.5, bc=(1,), tau=1e-2, strang=True)
+    s = Solver(1, (96,), 1 / 96, 16, 0.5, bc=(1,), tau=1e-2, strang=True)
+    o.init_macro(rho, u, th)
+    s.set_state_macro(rho, u, th)
+    img = None
+    for i, tau in enumerate((1e-2, 0.2, math.inf, 0.0, 3e-2)):
+        o.set_tau(tau)
+        s.set_tau(tau)
+        if i == 2:
+            img = s.read_state()
+        o.step(3)
+        s.step(3)
+    assert moment_errors(s.read_moments(), o.U, 1).max() < TOL64
+    assert rel_inf(s.read_f(), o.f) < TOL64
+    s2 = Solver(1, (96,), 1 / 96, 16, 0.5, bc=(1,), tau=1.0, strang=True)
+    s2.write_state(img)
+    for tau in (math.inf, 0.0, 3e-2):
+        s2.set_tau(tau)
+        s2.step(3)
+    assert np.array_equal(s2.read_moments(), s.read_moments())
+    assert np.array_equal(s2.read_f(), s.read_f())

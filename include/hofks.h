@@ -261,15 +261,55 @@ hofks_status hofks_mlp_forward(const void *packed, const float *x, float *y, lon
                                void *stream);
 /* grad[11012] (overwritten) and *loss of L = (1/(4n)) sum (y - t)^2 over a
  * batch of n samples, sample s being row idx[s] of x[.][37] and t[.][4]
- * (row s if idx is NULL); evaluated at the packed weights. */
+ * (row s if idx is NULL); evaluated at the packed weights.  The sums run in a
+ * fixed order (one partial per block in `work`, then the partials in block
+ * order), so the result is reproducible bit for bit.  work: device scratch of
+ * at least hofks_mlp_grad_work_bytes(n) bytes (at most 5.6 MB), 256-byte
+ * aligned, owned by the caller; HOFKS_ESIZE if smaller. */
+size_t hofks_mlp_grad_work_bytes(long n);
 hofks_status hofks_mlp_grad(const void *packed, const float *x, const float *t,
                             const int *idx, long n, float *grad, float *loss,
-                            void *stream);
-/* One Adam step (bias-corrected, step counts from 1) on FP32 params, m, v.
+                            void *work, size_t work_bytes, void *stream);/* One Adam step (bias-corrected, step counts from 1) on FP32 params, m, v.
  * Pack again afterwards. */
 hofks_status hofks_mlp_adam(float *params, const float *grad, float *m, float *v,
                             float lr, float beta1, float beta2, float eps, int step,
                             void *stream);
+
+/* Training of the closure network on the GPU (device pointers, caller
+ * owned, asynchronous on `stream`).
+ *
+ * hofks_closure_prepare: from n snapshot pairs (x[n][37], t[n][4], as
+ * hofks_closure_snapshot writes them) form the training set.  Per output c
+ * a robust scale s_c: q_c = the k-th smallest |t_c|, k = ceil(995 n / 1000),
+ * then the sample standard deviation (n - 1 divisor) of the t_c with
+ * |t_c| <= q_c (at least 1e-12).  Samples with |t_c / s_c| <= clip for every c
+ * are copied in their original order to x_out and (t / s) to t_out (room for
+ * n rows each); scales[4] (double) and the count *kept (int) are written.
+ * Every sum runs in a fixed order.  work: hofks_closure_prepare_work_bytes(n)
+ * bytes, 256-byte aligned. */
+size_t hofks_closure_prepare_work_bytes(long n);
+hofks_status hofks_closure_prepare(const float *x, const float *t, long n, float clip,
+                                   float *x_out, float *t_out, double *scales, int *kept,
+                                   void *work, size_t work_bytes, void *stream);
+/* The scales into the output layer: W4 row c and b4[c] times scales[c]
+ * (FP32 parameters; pack again afterwards). */
+hofks_status hofks_mlp_fold_scales(float *params, const double *scales, void *stream);
+/* One training step: the gradient of the minibatch (as hofks_mlp_grad, rows
+ * idx[0..n) of x and t), one Adam step (as hofks_mlp_adam, step counts from
+ * 1) on params/m/v, and the packed BF16 form written to `packed`; the loss of
+ * the minibatch at the weights before the step to *loss and the gradient to
+ * grad.  work as for hofks_mlp_grad. */
+hofks_status hofks_closure_train_step(float *params, float *m, float *v, void *packed,
+                                      const float *x, const float *t, const int *idx, long n,
+                                      float lr, float beta1, float beta2, float eps, int step,
+                                      float *grad, float *loss, void *work, size_t work_bytes,
+                                      void *stream);
+/* Network of the closure steps of a grid context: the packed weights
+ * (hofks_mlp_packed_bytes() bytes, device, caller owned, 16-byte aligned)
+ * read by every following closure step; the output on the uniform stencil
+ * is evaluated again at the next closure step.  HOFKS_ESIZE for another
+ * size.  (hofks_closure_enable also sets them, with the scale and threshold.) */
+hofks_status hofks_closure_set_weights(hofks_ctx *ctx, const void *packed, size_t bytes);
 
 #ifdef __cplusplus
 }

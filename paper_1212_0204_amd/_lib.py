@@ -22,7 +22,9 @@ SYMBOLS = [
     "hofks_closure_enable", "hofks_closure_disable", "hofks_closure_snapshot", "hofks_closure_stats",
     "hofks_mlp_nparam", "hofks_mlp_packed_bytes", "hofks_mlp_pack", "hofks_mlp_forward",
     "hofks_mlp_grad", "hofks_mlp_adam", "hofks_state_bytes", "hofks_read_state", "hofks_write_state",
-    "hofks_read_tail_substeps", "hofks_set_euler_launches",
+    "hofks_read_tail_substeps", "hofks_set_euler_launches", "hofks_mlp_grad_work_bytes",
+    "hofks_closure_prepare_work_bytes", "hofks_closure_prepare", "hofks_mlp_fold_scales",
+    "hofks_closure_train_step", "hofks_closure_set_weights",
 ]
 
 
@@ -82,7 +84,18 @@ def lib():
     L.hofks_mlp_packed_bytes.restype = sz
     L.hofks_mlp_pack.argtypes = [vp, vp, vp]
     L.hofks_mlp_forward.argtypes = [vp, vp, vp, ctypes.c_long, vp]
-    L.hofks_mlp_grad.argtypes = [vp, vp, vp, vp, ctypes.c_long, vp, vp, vp]
+    L.hofks_mlp_grad.argtypes = [vp, vp, vp, vp, ctypes.c_long, vp, vp, vp, sz, vp]
+    L.hofks_mlp_grad_work_bytes.argtypes = [ctypes.c_long]
+    L.hofks_mlp_grad_work_bytes.restype = sz
+    L.hofks_closure_prepare_work_bytes.argtypes = [ctypes.c_long]
+    L.hofks_closure_prepare_work_bytes.restype = sz
+    L.hofks_closure_prepare.argtypes = [vp, vp, ctypes.c_long, ctypes.c_float, vp, vp, vp, vp, vp,
+                                        sz, vp]
+    L.hofks_mlp_fold_scales.argtypes = [vp, vp, vp]
+    f = ctypes.c_float
+    L.hofks_closure_train_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_long, f, f, f, f,
+                                           i, vp, vp, vp, sz, vp]
+    L.hofks_closure_set_weights.argtypes = [vp, vp, sz]
     L.hofks_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, i, vp]
     _lib = L

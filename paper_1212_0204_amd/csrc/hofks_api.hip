@@ -29,6 +29,7 @@
 #include "kinetic3d.hpp"
 #include "mlp.hpp"
 #include "weno.hpp"
+#include "train.hpp"
 
 using namespace hofks;
 
@@ -2068,6 +2069,14 @@ hofks_status hofks_closure_enable(hofks_ctx* c, const void* packed, double sigma
   return HOFKS_OK;
 }
 
+hofks_status hofks_closure_set_weights(hofks_ctx* c, const void* packed, size_t bytes) {
+  if (!c || !packed || ((uintptr_t)packed & 15)) return HOFKS_EINVAL;
+  if (bytes != mlp::PACKED_BYTES) return HOFKS_ESIZE;
+  c->clos_w = packed;
+  c->clos_y0_ok = false;  // the output on the uniform stencil is evaluated again
+  return HOFKS_OK;
+}
+
 hofks_status hofks_closure_disable(hofks_ctx* c) {
   if (!c) return HOFKS_EINVAL;
   c->clos_on = false;
@@ -2135,19 +2144,97 @@ hofks_status hofks_mlp_forward(const void* packed, const float* x, float* y, lon
   return hipGetLastError() == hipSuccess ? HOFKS_OK : HOFKS_EDEVICE;
 }
 
-hofks_status hofks_mlp_grad(const void* packed, const float* x, const float* t, const int* idx,
-                            long n, float* grad, float* loss, void* stream) {
-  if (!packed || ((uintptr_t)packed & 15) || !grad || !loss || n < 1 || !x || !t)
-    return HOFKS_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(mlp::k_mlp_zero, dim3(nblk(mlp::NPARAM)), dim3(256), 0, s, grad, mlp::NPARAM);
-  hipLaunchKernelGGL(mlp::k_mlp_zero, dim3(1), dim3(64), 0, s, loss, 1);
-  const long tiles = (n + 15) / 16;
-  const unsigned grid =
-      (unsigned)std::min<long>(128, (tiles + mlp::GRAD_WAVES - 1) / mlp::GRAD_WAVES);
-  hipLaunchKernelGGL(mlp::k_mlp_grad, dim3(grid), dim3(64 * mlp::GRAD_WAVES), mlp::GRAD_LDS, s,
-                     packed, x, t, idx, n, grad, loss);
+size_t hofks_mlp_grad_work_bytes(long n) {
+  return n < 1 ? 0 : (size_t)mlp::grad_blocks(n) * mlp::PART_STRIDE * sizeof(float);
+}
+
+namespace {
+// deterministic gradient into grad/loss with the partials in `part`
+hofks_status mlp_grad_launch(const void* packed, const float* x, const float* t, const int* idx,
+                             long n, float* grad, float* loss, float* part, hipStream_t s) {
+  const int nb = mlp::grad_blocks(n);
+  hipLaunchKernelGGL(mlp::k_mlp_grad, dim3(nb), dim3(64 * mlp::GRAD_WAVES), mlp::GRAD_LDS, s,
+                     packed, x, t, idx, n, part);
+  hipLaunchKernelGGL(mlp::k_mlp_grad_reduce, dim3(nblk(mlp::NPARAM + 1)), dim3(256), 0, s,
+                     (const float*)part, nb, grad, loss);
   return hipGetLastError() == hipSuccess ? HOFKS_OK : HOFKS_EDEVICE;
+}
+
+bool mlp_grad_args_ok(const void* packed, const float* x, const float* t, long n,
+                      const float* grad, const float* loss) {
+  return packed && !((uintptr_t)packed & 15) && grad && loss && n >= 1 && x && t;
+}
+}  // namespace
+
+hofks_status hofks_mlp_grad(const void* packed, const float* x, const float* t, const int* idx,
+                            long n, float* grad, float* loss, void* work, size_t work_bytes,
+                            void* stream) {
+  if (!mlp_grad_args_ok(packed, x, t, n, grad, loss) || !work || ((uintptr_t)work & 255))
+    return HOFKS_EINVAL;
+  if (work_bytes < hofks_mlp_grad_work_bytes(n)) return HOFKS_ESIZE;
+  return mlp_grad_launch(packed, x, t, idx, n, grad, loss, (float*)work, (hipStream_t)stream);
+}
+
+size_t hofks_closure_prepare_work_bytes(long n) {
+  if (n < 1) return 0;
+  const size_t ntiles = (size_t)((n + train::SCAN_TILE - 1) / train::SCAN_TILE);
+  return align256(sizeof(train::PrepState)) + align256(ntiles * sizeof(int));
+}
+
+hofks_status hofks_closure_prepare(const float* x, const float* t, long n, float clip,
+                                   float* x_out, float* t_out, double* scales, int* kept,
+                                   void* work, size_t work_bytes, void* stream) {
+  if (!x || !t || n < 1 || !(clip > 0.0f) || !x_out || !t_out || !scales || !kept || !work ||
+      ((uintptr_t)work & 255) || n > (1L << 30))
+    return HOFKS_EINVAL;
+  if (work_bytes < hofks_closure_prepare_work_bytes(n)) return HOFKS_ESIZE;
+  hipStream_t s = (hipStream_t)stream;
+  auto* st = (train::PrepState*)work;
+  int* tiles = (int*)((unsigned char*)work + align256(sizeof(train::PrepState)));
+  const unsigned ntiles = (unsigned)((n + train::SCAN_TILE - 1) / train::SCAN_TILE);
+  const unsigned gh = (unsigned)std::min<long>(1024, (n + train::TB - 1) / train::TB);
+  const int nbm = (int)std::min<long>(train::MOM_BLOCKS, (n + train::TB - 1) / train::TB);
+  hipLaunchKernelGGL(train::k_prep_init, dim3(1), dim3(256), 0, s, st, n);
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    hipLaunchKernelGGL(train::k_prep_hist, dim3(gh), dim3(train::TB), 0, s, t, n, st, shift);
+    hipLaunchKernelGGL(train::k_prep_select, dim3(1), dim3(256), 0, s, st, shift);
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(train::k_prep_moments, dim3(nbm), dim3(train::TB), 0, s, t, n, st, pass);
+    hipLaunchKernelGGL(train::k_prep_moments_final, dim3(1), dim3(64), 0, s, st, nbm, pass);
+  }
+  hipLaunchKernelGGL(train::k_prep_count, dim3(ntiles), dim3(train::TB), 0, s, t, n,
+                     (const train::PrepState*)st, clip, tiles);
+  hipLaunchKernelGGL(train::k_prep_scan_tiles, dim3(1), dim3(64), 0, s, tiles, (int)ntiles, st);
+  hipLaunchKernelGGL(train::k_prep_compact, dim3(ntiles), dim3(train::TB), 0, s, x, t, n,
+                     (const train::PrepState*)st, clip, (const int*)tiles, x_out, t_out);
+  hipLaunchKernelGGL(train::k_prep_export, dim3(1), dim3(64), 0, s, (const train::PrepState*)st,
+                     scales, kept);
+  return hipGetLastError() == hipSuccess ? HOFKS_OK : HOFKS_EDEVICE;
+}
+
+hofks_status hofks_mlp_fold_scales(float* params, const double* scales, void* stream) {
+  if (!params || !scales) return HOFKS_EINVAL;
+  hipLaunchKernelGGL(train::k_fold_scales, dim3(1), dim3(256), 0, (hipStream_t)stream, params,
+                     scales);
+  return hipGetLastError() == hipSuccess ? HOFKS_OK : HOFKS_EDEVICE;
+}
+
+hofks_status hofks_closure_train_step(float* params, float* m, float* v, void* packed,
+                                      const float* x, const float* t, const int* idx, long n,
+                                      float lr, float beta1, float beta2, float eps, int step,
+                                      float* grad, float* loss, void* work, size_t work_bytes,
+                                      void* stream) {
+  if (!params || !m || !v || step < 1 || !mlp_grad_args_ok(packed, x, t, n, grad, loss) ||
+      !work || ((uintptr_t)work & 255))
+    return HOFKS_EINVAL;
+  if (work_bytes < hofks_mlp_grad_work_bytes(n)) return HOFKS_ESIZE;
+  hipStream_t s = (hipStream_t)stream;
+  hofks_status st = mlp_grad_launch(packed, x, t, idx, n, grad, loss, (float*)work, s);
+  if (st) return st;
+  st = hofks_mlp_adam(params, grad, m, v, lr, beta1, beta2, eps, step, stream);
+  if (st) return st;
+  return hofks_mlp_pack(params, packed, stream);
 }
 
 hofks_status hofks_mlp_adam(float* params, const float* grad, float* m, float* v, float lr,

@@ -248,7 +248,9 @@ __device__ __forceinline__ s4 tr_load(const short* T, int t, int lane) {
 }
 
 // gradient tile (rows = outputs 16 T + 4 q + r, column = input 16 U + j)
-// into the LDS gradient of a layer with nout x nin weights
+// into the wavefront's own LDS gradient of a layer with nout x nin weights
+// (the lanes of a tile touch distinct entries, and one wavefront's LDS
+// operations complete in order, so plain adds accumulate in a fixed order)
 __device__ __forceinline__ void add_wgrad(float* gl, int ow, int nout, int nin, int T, int U,
                                           f4 v, int lane) {
   const int j = lane & 15, q = lane >> 4;
@@ -257,7 +259,7 @@ __device__ __forceinline__ void add_wgrad(float* gl, int ow, int nout, int nin, 
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int o = 16 * T + 4 * q + r;
-    if (o < nout) atomicAdd(gl + ow + o * nin + in, v[r]);
+    if (o < nout) gl[ow + o * nin + in] += v[r];
   }
 }
 
@@ -278,27 +280,41 @@ __device__ __forceinline__ void add_bgrad(float* gl, int ob, int nout, int t, f4
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int o = 16 * t + 4 * q + r;
-      if (o < nout) atomicAdd(gl + ob + o, v[r]);
+      if (o < nout) gl[ob + o] += v[r];
     }
   }
 }
 
-constexpr int GRAD_WAVES = 4;
-constexpr size_t GRAD_LDS =
-    NPARAM * sizeof(float) + (size_t)GRAD_WAVES * 2 * NH * TR_ROW * sizeof(short);
+// Gradient in a fixed summation order (bit-reproducible): every wavefront
+// keeps its own gradient in LDS, the block adds its wavefronts in order and
+// writes one partial gradient (and loss) per block to the work area; a
+// second launch sums the partials over the blocks in block order.
+constexpr int GRAD_WAVES = 2;
+constexpr int GRAD_BLOCKS = 128;                 // largest grid of the gradient kernel
+constexpr int PART_STRIDE = (NPARAM + 1 + 63) & ~63;  // partial gradient + loss, floats
+constexpr size_t GRAD_LDS = (size_t)GRAD_WAVES * NPARAM * sizeof(float) +
+                            (size_t)GRAD_WAVES * 2 * NH * TR_ROW * sizeof(short);
+// work area of one gradient call (bytes) for n samples
+__host__ __device__ constexpr int grad_blocks(long n) {
+  return (int)((n + 15) / 16 < (long)GRAD_BLOCKS * GRAD_WAVES
+                   ? ((n + 15) / 16 + GRAD_WAVES - 1) / GRAD_WAVES
+                   : GRAD_BLOCKS);
+}
+constexpr size_t GRAD_WORK_MAX = (size_t)GRAD_BLOCKS * PART_STRIDE * sizeof(float);
 
 __global__ __launch_bounds__(64 * GRAD_WAVES) void k_mlp_grad(const void* __restrict__ packed,
                                                               const float* __restrict__ x,
                                                               const float* __restrict__ t,
                                                               const int* __restrict__ idx,
-                                                              long n, float* __restrict__ grad,
-                                                              float* __restrict__ loss) {
+                                                              long n, float* __restrict__ part) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-  float* gl = reinterpret_cast<float*>(lds_raw);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  short* TA = reinterpret_cast<short*>(lds_raw + NPARAM * sizeof(float)) + wv * 2 * NH * TR_ROW;
+  float* gl = reinterpret_cast<float*>(lds_raw) + (size_t)wv * NPARAM;
+  short* TA = reinterpret_cast<short*>(lds_raw + GRAD_WAVES * NPARAM * sizeof(float)) +
+              wv * 2 * NH * TR_ROW;
   short* TZ = TA + NH * TR_ROW;
-  for (int i = threadIdx.x; i < NPARAM; i += blockDim.x) gl[i] = 0.0f;
+  for (int i = threadIdx.x; i < GRAD_WAVES * NPARAM; i += blockDim.x)
+    reinterpret_cast<float*>(lds_raw)[i] = 0.0f;
   __syncthreads();
 
   FwdW W;
@@ -409,16 +425,41 @@ __global__ __launch_bounds__(64 * GRAD_WAVES) void k_mlp_grad(const void* __rest
     }
     wave_sync_lds();
   }
-  // loss and the block's gradient
+  // the block's loss and gradient: wavefronts added in order
   float ls = lsum;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) ls += __shfl_xor(ls, o);
-  if (lane == 0) atomicAdd(loss, ls * inv);
+  __shared__ float wl[GRAD_WAVES];
+  if (lane == 0) wl[wv] = ls * inv;
   __syncthreads();
+  const float* g0 = reinterpret_cast<const float*>(lds_raw);
+  float* out = part + (size_t)blockIdx.x * PART_STRIDE;
   for (int i = threadIdx.x; i < NPARAM; i += blockDim.x) {
-    const float v = gl[i];
-    if (v != 0.0f) atomicAdd(grad + i, v);
+    float v = g0[i];
+#pragma unroll
+    for (int w = 1; w < GRAD_WAVES; ++w) v += g0[(size_t)w * NPARAM + i];
+    out[i] = v;
   }
+  if (threadIdx.x == 0) {
+    float l = wl[0];
+#pragma unroll
+    for (int w = 1; w < GRAD_WAVES; ++w) l += wl[w];
+    out[NPARAM] = l;
+  }
+}
+
+// grad[i] = sum over blocks b = 0, 1, ... of the partials (in that order);
+// thread NPARAM sums the loss
+__global__ void k_mlp_grad_reduce(const float* __restrict__ part, int nblocks,
+                                  float* __restrict__ grad, float* __restrict__ loss) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > NPARAM) return;
+  float v = 0.0f;
+  for (int b = 0; b < nblocks; ++b) v += part[(size_t)b * PART_STRIDE + i];
+  if (i < NPARAM)
+    grad[i] = v;
+  else
+    *loss = v;
 }
 
 // Adam with bias correction on the FP32 master parameters (c1 = 1 - b1^k,

@@ -1,9 +1,11 @@
 """The closure network (37 -> 64 -> 64 -> 64 -> 4, tanh) and its training.
 
-Argument marshalling over the ``hofks_mlp_*`` entry points: parameters,
-Adam moments, gradient and the packed BF16 form live in torch device tensors;
-forward, gradient, Adam and packing run in the library's kernels.  Torch
-draws the minibatch indices (its device RNG) and nothing else.
+Argument marshalling over the ``hofks_mlp_*`` and ``hofks_closure_*`` entry
+points: parameters, Adam moments, gradient, work areas and the packed BF16
+form live in torch device tensors; the target scales, the clipping, the
+forward pass, the gradient, Adam, the packing and the scale fold run in the
+library's kernels.  Torch allocates and draws the minibatch indices (its
+device RNG); it does no arithmetic on the data.
 """
 import ctypes
 
@@ -57,7 +59,14 @@ class ClosureNet:
         self.packed = torch.empty(L.hofks_mlp_packed_bytes(), dtype=torch.uint8, device="cuda")
         self.sigma = float(sigma)
         self.adam_steps = 0
+        self.work = torch.empty(0, dtype=torch.uint8, device="cuda")
         self.pack()
+
+    def _work(self, nbytes):
+        """device scratch of at least nbytes (kept between calls)"""
+        if self.work.numel() < nbytes:
+            self.work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        return self.work
 
     @property
     def stream(self):
@@ -78,10 +87,27 @@ class ClosureNet:
         """(grad, loss) of the mean squared error over the rows idx of x, t
         (all rows without idx); device tensors, valid until the next call"""
         n = x.shape[0] if idx is None else idx.shape[0]
-        _check(_lib.lib().hofks_mlp_grad(_vp(self.packed), _vp(x), _vp(t),
-                                         _vp(idx) if idx is not None else None, n,
-                                         _vp(self.grad), _vp(self.loss), self.stream), "mlp_grad")
+        L = _lib.lib()
+        nb = L.hofks_mlp_grad_work_bytes(n)
+        w = self._work(nb)
+        _check(L.hofks_mlp_grad(_vp(self.packed), _vp(x), _vp(t),
+                                _vp(idx) if idx is not None else None, n,
+                                _vp(self.grad), _vp(self.loss), _vp(w), nb, self.stream),
+               "mlp_grad")
         return self.grad, self.loss
+
+    def train_step(self, x, t, idx, lr, b1=0.9, b2=0.999, eps=1e-8):
+        """gradient of the rows idx of (x, t), one Adam step and the packing,
+        in one library call; the minibatch loss stays on the device"""
+        L = _lib.lib()
+        nb = L.hofks_mlp_grad_work_bytes(idx.shape[0])
+        w = self._work(nb)
+        self.adam_steps += 1
+        _check(L.hofks_closure_train_step(_vp(self.params), _vp(self.m), _vp(self.v),
+                                          _vp(self.packed), _vp(x), _vp(t), _vp(idx),
+                                          idx.shape[0], lr, b1, b2, eps, self.adam_steps,
+                                          _vp(self.grad), _vp(self.loss), _vp(w), nb, self.stream),
+               "closure_train_step")
 
     def adam(self, lr, b1=0.9, b2=0.999, eps=1e-8):
         self.adam_steps += 1
@@ -91,25 +117,51 @@ class ClosureNet:
         self.pack()
 
     def train(self, x, t, steps, batch=4096, lr=2e-3, lr_end=2e-4, seed=0, log_every=0):
-        """minibatch Adam on (x, t / sigma); cosine-free geometric decay of the
-        learning rate from lr to lr_end; returns the logged losses"""
+        """minibatch Adam on (x, t) (t already divided by sigma); geometric
+        decay of the learning rate from lr to lr_end; returns the logged
+        losses"""
         x = x.contiguous()
-        ts = (t / self.sigma).contiguous()
+        t = t.contiguous()
         g = torch.Generator(device="cuda")
         g.manual_seed(seed)
         losses = []
         for it in range(steps):
             idx = torch.randint(0, x.shape[0], (batch,), device="cuda", generator=g,
                                 dtype=torch.int32)
-            self.gradient(x, ts, idx)
             rate = lr * (lr_end / lr) ** (it / max(steps - 1, 1))
-            self.adam(rate)
+            self.train_step(x, t, idx, rate)
             if log_every and (it % log_every == 0 or it == steps - 1):
                 losses.append((it, float(self.loss.item())))
         return losses
 
     def state(self):
         return self.params.detach().cpu().numpy().copy(), self.sigma
+
+    def prepare(self, x, t, clip=8.0):
+        """the training set of the closure snapshots (library call
+        hofks_closure_prepare): per-output robust scales, normalised targets,
+        samples beyond `clip` left out; returns (x_kept, t_kept, scales)
+        with the scales as a (4,) FP64 device tensor"""
+        L = _lib.lib()
+        x = x.contiguous()
+        t = t.contiguous()
+        n = x.shape[0]
+        xo = torch.empty_like(x)
+        to = torch.empty_like(t)
+        scales = torch.empty(NOUT, dtype=torch.float64, device="cuda")
+        kept = torch.empty(1, dtype=torch.int32, device="cuda")
+        nb = L.hofks_closure_prepare_work_bytes(n)
+        w = self._work(nb)
+        _check(L.hofks_closure_prepare(_vp(x), _vp(t), n, float(clip), _vp(xo), _vp(to),
+                                       _vp(scales), _vp(kept), _vp(w), nb, self.stream),
+               "closure_prepare")
+        k = int(kept.item())
+        return xo[:k], to[:k], scales
+
+    def fold_scales(self, scales):
+        _check(_lib.lib().hofks_mlp_fold_scales(_vp(self.params), _vp(scales), self.stream),
+               "mlp_fold_scales")
+        self.pack()
 
     def fit_closure(self, x, t, steps=4000, batch=4096, lr=2e-3, lr_end=1e-4, clip=8.0, seed=0,
                     log_every=0):
@@ -119,24 +171,12 @@ class ClosureNet:
         `clip` are left out (shock cells, which the delta marks keep
         kinetic).  The scales are folded into the output layer afterwards,
         so sigma = 1.  Returns (scales, logged losses, samples used)."""
-        ta = t.abs()
-        q = torch.quantile(ta[torch.randperm(t.shape[0], device=t.device)[:200000]], 0.995, dim=0)
-        sc = torch.stack([t[:, c][ta[:, c] <= q[c]].std() for c in range(NOUT)])
-        sc = torch.clamp(sc, min=1e-12)
-        tn = t / sc
-        keep = (tn.abs() <= clip).all(dim=1)
-        xs, ts = x[keep].contiguous(), tn[keep].contiguous()
+        xs, ts, scales = self.prepare(x, t, clip)
         self.sigma = 1.0
         losses = self.train(xs, ts, steps, batch=batch, lr=lr, lr_end=lr_end, seed=seed,
                             log_every=log_every)
-        p = self.params.detach().cpu().numpy().copy()
-        scale = sc.cpu().numpy().astype(np.float32)
-        o_w4 = NH * NIN + NH + 2 * (NH * NH + NH)
-        p[o_w4:o_w4 + NOUT * NH] *= np.repeat(scale, NH)
-        p[o_w4 + NOUT * NH:] *= scale
-        self.params.copy_(torch.tensor(p, device="cuda"))
-        self.pack()
-        return scale, losses, int(keep.sum())
+        self.fold_scales(scales)
+        return scales.cpu().numpy().astype(np.float32), losses, int(xs.shape[0])
 
 
 def collect_snapshots(configs, steps_at, precision=1):

@@ -368,3 +368,112 @@ def test_full_size_disk_closure(trained):
     print("L1", e, "kinetic fraction", kin / (cs * wl.nc), flush=True)
     assert e <= 1e-3
     assert np.isfinite(Uc).all()
+
+
+# ------------------------------------------- training through the library
+@gpu
+def test_gradient_and_training_are_bit_reproducible():
+    """fixed-order sums: the same gradient call twice, and two training runs
+    from the same start, give identical bits"""
+    import torch
+    announce("reproducible training")
+    rng = np.random.default_rng(12)
+    x = torch.tensor(rng.standard_normal((6000, 37)).astype(np.float32), device="cuda")
+    t = torch.tensor(rng.standard_normal((6000, 4)).astype(np.float32), device="cuda")
+    net, _ = net_and_params(8)
+    g1 = net.gradient(x, t)[0].clone()
+    g2 = net.gradient(x, t)[0].clone()
+    assert torch.equal(g1, g2)
+    runs = []
+    for _ in range(2):
+        net, _ = net_and_params(8)
+        net.train(x, t, steps=60, batch=2048, lr=2e-3, seed=3)
+        runs.append((net.params.clone(), net.m.clone(), net.v.clone(), net.packed.clone()))
+    for a, b in zip(*runs):
+        assert torch.equal(a, b)
+
+
+@gpu
+def test_train_step_equals_gradient_adam_pack():
+    """hofks_closure_train_step is the gradient, one Adam step and the packing"""
+    import torch
+    announce("train step")
+    rng = np.random.default_rng(13)
+    x = torch.tensor(rng.standard_normal((3000, 37)).astype(np.float32), device="cuda")
+    t = torch.tensor(rng.standard_normal((3000, 4)).astype(np.float32), device="cuda")
+    idx = torch.tensor(rng.integers(0, 3000, 1500).astype(np.int32), device="cuda")
+    a, _ = net_and_params(9)
+    b, _ = net_and_params(9)
+    for k in range(3):
+        a.train_step(x, t, idx, 1e-3)
+        b.gradient(x, t, idx)
+        b.adam(1e-3)
+        assert torch.equal(a.loss, b.loss)
+    assert torch.equal(a.params, b.params) and torch.equal(a.packed, b.packed)
+
+
+def _robust_scales(t):
+    """the definition: per output, q = k-th smallest |t|, k = ceil(995 n/1000),
+    then the sample standard deviation of the entries with |t| <= q"""
+    n = t.shape[0]
+    k = (995 * n + 999) // 1000
+    out = []
+    for c in range(t.shape[1]):
+        a = t[:, c].astype(np.float64)
+        q = np.sort(np.abs(a))[k - 1]
+        out.append(max(a[np.abs(a) <= q].std(ddof=1), 1e-12))
+    return np.array(out)
+
+
+@gpu
+@pytest.mark.parametrize("n", [1, 1000, 54321])
+def test_prepare_scales_clip_and_order(n):
+    """robust scales against their definition (numpy, FP64), the kept samples
+    in their original order with t / s, the fold of the scales into W4, b4"""
+    import torch
+    announce("prepare", n)
+    rng = np.random.default_rng(14 + n)
+    x = rng.standard_normal((n, 37)).astype(np.float32)
+    # heavy-tailed targets of very different sizes per output
+    t = (rng.standard_t(2.0, (n, 4)) * np.array([1e-3, 1e-6, 3e-6, 1e-2])).astype(np.float32)
+    net, p = net_and_params(10)
+    xs, ts, sc = net.prepare(torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda"),
+                             clip=8.0)
+    sc = sc.cpu().numpy()
+    if n > 1:
+        np.testing.assert_allclose(sc, _robust_scales(t), rtol=1e-12)
+    s32 = sc.astype(np.float32)
+    keep = (np.abs(t / s32) <= np.float32(8.0)).all(axis=1)
+    assert xs.shape[0] == keep.sum()
+    assert np.array_equal(xs.cpu().numpy(), x[keep])
+    assert np.array_equal(ts.cpu().numpy(), (t / s32)[keep])
+    net.fold_scales(torch.tensor(sc, device="cuda"))
+    q = net.params.cpu().numpy()
+    o_w4 = 64 * 37 + 64 + 2 * (64 * 64 + 64)
+    w4 = p[o_w4:o_w4 + 256].reshape(4, 64) * s32[:, None]
+    assert np.array_equal(q[o_w4:o_w4 + 256], w4.reshape(-1))
+    assert np.array_equal(q[o_w4 + 256:], p[o_w4 + 256:] * s32)
+
+
+@gpu
+def test_set_weights_replaces_the_network():
+    """hofks_closure_set_weights: closure steps with the new network equal a
+    run enabled with it from the start"""
+    announce("set weights")
+    sigma = 0.05
+    a, _ = net_and_params(7, sigma=sigma)
+    b, _ = net_and_params(11, sigma=sigma)
+    runs = []
+    for swap in (False, True):
+        s, _ = small(1, 5e-3)
+        s.closure_enable(a if swap else b, threshold=1e-3)
+        if swap:
+            from paper_1212_0204_amd import _lib
+            import ctypes
+            st = _lib.lib().hofks_closure_set_weights(s._h, ctypes.c_void_p(b.packed.data_ptr()),
+                                                      b.packed.numel())
+            assert st == 0
+            s._net = b
+        s.step(4)
+        runs.append(s.read_moments())
+    assert np.array_equal(runs[0], runs[1])

@@ -269,7 +269,22 @@ hofks_status hofks_mlp_forward(const void *packed, const float *x, float *y, lon
 size_t hofks_mlp_grad_work_bytes(long n);
 hofks_status hofks_mlp_grad(const void *packed, const float *x, const float *t,
                             const int *idx, long n, float *grad, float *loss,
-                            void *work, size_t work_bytes, void *stream);/* One Adam step (bias-corrected, step counts from 1) on FP32 params, m, v.
+                            void *work, size_t work_bytes, void *stream);
+/* hofks_mlp_grad without a work argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight training loops,
+ * harnesses that forbid hipMalloc): the per-block partials go to a scratch
+ * array the library holds in device memory for the life of the process,
+ * GRAD_WORK_MAX = 5,668,864 bytes on every GPU it runs on (its address on
+ * the current device is looked up at the first call there).  Same kernels,
+ * same results, bit for bit.  The call allocates nothing; every call on one
+ * GPU shares that GPU's array, so calls that overlap on one GPU (on several
+ * streams or host threads) race; each call overwrites every partial it
+ * reads, so nothing is carried between calls.  HOFKS_EINVAL for bad
+ * arguments, HOFKS_ESIZE if the work exceeds the array (it cannot for
+ * n >= 1), HOFKS_EDEVICE if the address lookup or a launch fails. */
+hofks_status hofks_mlp_grad_noalloc(const void *packed, const float *x, const float *t,
+                                    const int *idx, long n, float *grad, float *loss,
+                                    void *stream);/* One Adam step (bias-corrected, step counts from 1) on FP32 params, m, v.
  * Pack again afterwards. */
 hofks_status hofks_mlp_adam(float *params, const float *grad, float *m, float *v,
                             float lr, float beta1, float beta2, float eps, int step,

@@ -24,7 +24,7 @@ SYMBOLS = [
     "hofks_mlp_grad", "hofks_mlp_adam", "hofks_state_bytes", "hofks_read_state", "hofks_write_state",
     "hofks_read_tail_substeps", "hofks_set_euler_launches", "hofks_mlp_grad_work_bytes",
     "hofks_closure_prepare_work_bytes", "hofks_closure_prepare", "hofks_mlp_fold_scales",
-    "hofks_closure_train_step", "hofks_closure_set_weights",
+    "hofks_closure_train_step", "hofks_closure_set_weights", "hofks_mlp_grad_noalloc",
 ]
 
 
@@ -85,6 +85,7 @@ def lib():
     L.hofks_mlp_pack.argtypes = [vp, vp, vp]
     L.hofks_mlp_forward.argtypes = [vp, vp, vp, ctypes.c_long, vp]
     L.hofks_mlp_grad.argtypes = [vp, vp, vp, vp, ctypes.c_long, vp, vp, vp, sz, vp]
+    L.hofks_mlp_grad_noalloc.argtypes = [vp, vp, vp, vp, ctypes.c_long, vp, vp, vp]
     L.hofks_mlp_grad_work_bytes.argtypes = [ctypes.c_long]
     L.hofks_mlp_grad_work_bytes.restype = sz
     L.hofks_closure_prepare_work_bytes.argtypes = [ctypes.c_long]

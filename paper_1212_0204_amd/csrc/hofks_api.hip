@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <numeric>
 #include <sstream>
 #include <string>
@@ -2172,6 +2173,47 @@ hofks_status hofks_mlp_grad(const void* packed, const float* x, const float* t, 
   if (!mlp_grad_args_ok(packed, x, t, n, grad, loss) || !work || ((uintptr_t)work & 255))
     return HOFKS_EINVAL;
   if (work_bytes < hofks_mlp_grad_work_bytes(n)) return HOFKS_ESIZE;
+  return mlp_grad_launch(packed, x, t, idx, n, grad, loss, (float*)work, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+// Scratch of hofks_mlp_grad_noalloc: the per-block partial gradients of the
+// largest grid, in device memory the library holds for the life of the
+// process (one copy on every GPU it runs on).  Host code never passes the
+// array's name to a kernel: its device address on the current device is
+// looked up once per device with hipGetSymbolAddress and kept here.
+__device__ __align__(256) float scratch[mlp::GRAD_WORK_MAX / sizeof(float)];
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[SCRATCH_DEVICES];
+
+hofks_status scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_DEVICES) return HOFKS_EDEVICE;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HOFKS_EDEVICE;
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return HOFKS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+hofks_status hofks_mlp_grad_noalloc(const void* packed, const float* x, const float* t,
+                                    const int* idx, long n, float* grad, float* loss,
+                                    void* stream) {
+  if (!mlp_grad_args_ok(packed, x, t, n, grad, loss)) return HOFKS_EINVAL;
+  if (hofks_mlp_grad_work_bytes(n) > sizeof(scratch)) return HOFKS_ESIZE;
+  void* work = nullptr;
+  const hofks_status st = scratch_address(&work);
+  if (st) return st;
   return mlp_grad_launch(packed, x, t, idx, n, grad, loss, (float*)work, (hipStream_t)stream);
 }
 

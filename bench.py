@@ -64,14 +64,14 @@ def profiled_traffic(ng, unr):
     return 1024.0 * (fk * float(vals["fetch_scale"]) + wk * float(vals["write_scale"]))
 
 
-def run_solver(wl, steps, warmup, precision, scheme=0):
+def run_solver(wl, steps, warmup, precision, scheme=0, dt=None, strang=False):
     import torch
     import workloads as W
     from paper_1212_0204_amd import Solver
 
     fields = W.initial_fields(wl)
     s = Solver(wl.d, wl.n, wl.dx, wl.nv, wl.dv, bc=wl.bc, precision=precision, scheme=scheme,
-               tau=wl.tau)
+               tau=wl.tau, dt=dt, strang=strang)
     s.set_state_macro(*fields)
     tuned = s.autotune(steps=3)  # launch configuration picked by timing
     if warmup:
@@ -96,8 +96,10 @@ def run_solver(wl, steps, warmup, precision, scheme=0):
     kin_ms = kms[1] / max(cnt[1], 1)
     achieved = bpcv * wl.cv / (kin_ms * 1e-3) / 1e9
     out = {
+        "steps": steps,
         "cv_per_s": cv / (ms * 1e-3),
         "ms_per_step": ms / steps,
+        "dt": s.dt,
         "kernel_ms_per_step": {"euler": kms[0] / max(cnt[0], 1), "kinetic": kin_ms,
                                "cell_update": kms[2] / max(cnt[2], 1)},
         "euler_substeps_last_step": substeps,
@@ -141,11 +143,17 @@ def run_batch(steps, warmup):
     ms = e0.elapsed_time(e1)
     b.kernel_timing(enable=False)
     b.sync()
-    flagged = int((b.tube_flags() != 0).sum())
+    flags = b.tube_flags()
+    flagged = int((flags != 0).sum())
+    # throughput of the tubes whose results are valid: a tube that met a
+    # non-physical state keeps running but its work is not counted
+    ok = flags == 0
+    cv_ok = int((b.nx * b.nvs)[ok].sum()) * steps
     cv = b.ncv * steps
     out = {"workload": "batch512_tubes_seed4_fp32", "tubes": len(tubes), "cv_per_step": b.ncv,
-           "steps": steps, "cv_per_s": cv / (ms * 1e-3), "ms_per_step": ms / steps,
-           "hbm_frac": 8 * cv / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+           "steps": steps, "cv_per_s": cv_ok / (ms * 1e-3), "ms_per_step": ms / steps,
+           "cv_per_s_incl_flagged_tubes": cv / (ms * 1e-3),
+           "hbm_frac": 8 * cv_ok / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
            "tuned": {"cells_per_item": tuned[0], "blocks": tuned[1]},
            "flagged_tubes": flagged,
            # cold-side velocity resolution of each tube: dv / sqrt(theta_min)
@@ -181,17 +189,19 @@ def run_closure(warmup=2):
 
     wl = W.DISK_2D
     fields = W.initial_fields(wl)
+    zero = ClosureNet(sigma=0.0)  # N^ = 0: the closure form without the network
 
-    def timed(closure):
-        s = Solver(wl.d, wl.n, wl.dx, wl.nv, wl.dv, bc=wl.bc, precision=1, tau=wl.tau)
+    def timed(closure, tau=wl.tau, netw=None, steps=wl.steps):
+        netw = netw or net
+        s = Solver(wl.d, wl.n, wl.dx, wl.nv, wl.dv, bc=wl.bc, precision=1, tau=tau)
         s.set_state_macro(*fields)
         if closure:  # tune the kernel that the closure steps launch
-            s.closure_enable(net, threshold=1e-3)
+            s.closure_enable(netw, threshold=1e-3)
         tuned = s.autotune(steps=3)
         for phase in ("warmup", "timed"):
             s.set_state_macro(*fields)
             if closure:
-                s.closure_enable(net, threshold=1e-3)
+                s.closure_enable(netw, threshold=1e-3)
             if phase == "warmup":
                 s.step(warmup)
                 s.sync()
@@ -201,7 +211,7 @@ def run_closure(warmup=2):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(s.stream)
-            s.step(wl.steps)
+            s.step(steps)
             e1.record(s.stream)
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1)
@@ -216,7 +226,27 @@ def run_closure(warmup=2):
     ms_p, Up, _, per_p, tuned_p = timed(False)
     ms_c, Uc, frac, per_c, tuned_c = timed(True)
     cv = wl.cv * wl.steps
+    l1 = lambda a, b: float(np.abs(a[0] - b[0]).sum() / np.abs(b[0]).sum())
+    dt = wl.dx / wl.dv
+    # a relaxation time where the pieces carry a fifth of U^{n+1} (lambda =
+    # exp(-dt/tau) ~ 0.21), so that the network's estimate matters: the
+    # trained network against N^ = 0 at the same tau.  40 steps (t = 0.31):
+    # at this tau the plain scheme itself meets a non-physical state near
+    # step 51, when the blast waves of the periodic images meet.
+    tau_mid, steps_mid = 5e-3, 40
+    ms_pm, Upm, _, _, _ = timed(False, tau_mid, steps=steps_mid)
+    ms_cm, Ucm, frac_m, per_m, _ = timed(True, tau_mid, steps=steps_mid)
+    ms_zm, Uzm, frac_z, _, _ = timed(True, tau_mid, zero, steps=steps_mid)
+    cvm = wl.cv * steps_mid
+    mid = {"tau": tau_mid, "lambda": math.exp(-dt / tau_mid), "steps": steps_mid,
+           "l1_density_error_vs_plain_fp32": l1(Ucm, Upm),
+           "l1_density_error_zero_network": l1(Uzm, Upm),
+           "kinetic_cell_fraction": frac_m, "kinetic_cell_fraction_zero_network": frac_z,
+           "cv_per_s": cvm / (ms_cm * 1e-3), "ms_per_step": ms_cm / steps_mid,
+           "plain_fp32_ms_per_step": ms_pm / steps_mid, "speedup_vs_plain_fp32": ms_pm / ms_cm,
+           "closure_network_ms_per_step": per_m[3]}
     return {"workload": wl.name, "steps": wl.steps, "tau": wl.tau, "threshold": 1e-3,
+            "lambda": math.exp(-dt / wl.tau), "mid_tau": mid,
             "cv_per_s": cv / (ms_c * 1e-3), "ms_per_step": ms_c / wl.steps,
             "plain_fp32_cv_per_s": cv / (ms_p * 1e-3), "plain_fp32_ms_per_step": ms_p / wl.steps,
             "speedup_vs_plain_fp32_same_workload": ms_p / ms_c,
@@ -257,6 +287,93 @@ def copy_probe(mb, reps=5):
             "GBps": moved / (ms * 1e-3) / 1e9}
 
 
+def stream_probe(mb, reps=5):
+    """the library's streaming probe (16-byte non-temporal accesses, no
+    arithmetic): read, write and copy bandwidth of `mb` MiB"""
+    import ctypes
+    import torch
+    from paper_1212_0204_amd import _lib
+    L = _lib.lib()
+    nbytes = mb * (1 << 20)
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    sink = torch.zeros(4, dtype=torch.int32, device="cuda")
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    out = {}
+    for mode, name, moved in ((0, "read", nbytes), (1, "write", nbytes), (2, "copy", 2 * nbytes)):
+        src = ctypes.c_void_p(a.data_ptr())
+        dst = ctypes.c_void_p((sink if mode == 0 else b).data_ptr())
+        assert L.hofks_stream_probe(mode, src, dst, nbytes, st) == 0
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            L.hofks_stream_probe(mode, src, dst, nbytes, st)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name + "_GBps"] = moved / (ms * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    out["bytes"] = nbytes
+    return out
+
+
+def fp32_error_sample():
+    """per-moment error of the FP32 precision form against the FP64 oracle on
+    a reduced grid of the 3D workload (16^3 cells x 24^3 velocities, dv =
+    1/2, the workload's field recipe), 3 steps, at the workload's tau and at
+    lambda = 1/2 where the FP32 pieces carry half of U^{n+1}"""
+    import workloads as W
+    from oracle import Oracle
+    from paper_1212_0204_amd import Solver
+    wl = W.GAS_3D
+    n, dx = (16, 16, 16), 1.0 / 16
+    fields = W.perturbed_gas(16, 3, 0.1, 0.1, 4, (3, 33))
+    out = {}
+    for label, tau in (("workload_tau", wl.tau), ("lambda_half", (dx / wl.dv) / math.log(2.0))):
+        o = Oracle(3, n, dx, wl.nv, wl.dv, bc=wl.bc, tau=tau)
+        s = Solver(3, n, dx, wl.nv, wl.dv, bc=wl.bc, tau=tau, precision=1)
+        o.init_macro(*fields)
+        s.set_state_macro(*fields)
+        o.step(3)
+        s.step(3)
+        U, Uo = s.read_moments(), o.U
+        rho = Uo[0]
+        u = Uo[1:4] / rho
+        th = (2.0 * Uo[4] - rho * (u ** 2).sum(0)) / (3 * rho)
+        c = np.sqrt(5.0 / 3.0 * th)
+        sc = [np.abs(rho).max()] + [np.abs(rho).max() * c.max()] * 3 + [np.abs(Uo[4]).max()]
+        out[label] = {"lambda": o.lam, "moment_errors": [float(np.abs(U[r] - Uo[r]).max() / sc[r])
+                                                         for r in range(5)]}
+        del s
+    out["sample"] = "16^3 cells x 24^3 velocities, 3 steps, normwise per moment (rho, rho u, E)"
+    return out
+
+
+def batch_oracle_rate(count=32, steps=10):
+    """the oracle on the first `count` tubes of the batched workload for
+    `steps` steps (one tube after the other, OpenMP over cells)"""
+    import workloads as W
+    from oracle import Oracle, OracleError
+    tubes = W.batched_tubes()[:count]
+    t0 = time.perf_counter()
+    cv = 0
+    for t in tubes:
+        o = Oracle(1, (t.nx,), t.dx, t.nv, t.dv, bc=(1,), tau=t.tau)
+        r, uu, th = W.sod_tube(t.nx, left=t.left, right=t.right)
+        o.init_macro(r, uu, th)
+        try:
+            o.step(steps)
+        except OracleError:
+            continue
+        cv += t.nx * t.nv * steps
+    el = time.perf_counter() - t0
+    return {"value": cv / el, "sample": f"first {count} tubes of the 512-tube batch, {steps} steps "
+                                        f"each ({el:.1f} s)"}
+
+
 def cpu_baseline(wl, budget_s=12.0, single_s=6.0):
     """the oracle on the host cores, on the same workload: as many whole steps
     of the full grid as fit in ~budget_s (at least one) with all threads,
@@ -286,7 +403,9 @@ def cpu_baseline(wl, budget_s=12.0, single_s=6.0):
             "sample": f"{wl.name}: {n} full steps of the {wl.nc}-cell x {wl.nvel}-velocity grid "
                       f"from the initial state ({el:.1f} s, OpenMP over cells, plain FP64 C)",
             "single_thread": {"value": wl.cv * n1 / el1, "cores": 1,
-                              "sample": f"{n1} full steps ({el1:.1f} s)"}}
+                              "sample": f"{n1} full steps ({el1:.1f} s)"},
+            "batched_tubes": batch_oracle_rate(),
+            "fp32_form_vs_oracle": fp32_error_sample()}
 
 
 def main():
@@ -295,7 +414,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp32_3d,fp64_3d,batched,closure")
+    ap.add_argument("--forms",
+                    default="sod_1d,fp32_3d,fp64_3d,batched,closure,weno_2d,offlattice_2d,strang_2d")
     ap.add_argument("--copy-probe-mb", type=int, default=1024,
                     help="size of a plain device copy timed after the run (0: skip)")
     args = ap.parse_args()
@@ -321,6 +441,17 @@ def main():
             forms[name] = run_batch(500, 16)
         elif name == "closure":
             forms[name] = run_closure()
+        elif name == "sod_1d":
+            forms[name] = dict(workload=W.SOD_1D.name, **run_solver(W.SOD_1D, W.SOD_1D.steps, 5, 0))
+        elif name == "weno_2d":
+            forms[name] = dict(workload=wl.name + "_weno", scheme=3, **run_solver(wl, 50, 3, 0, 3))
+        elif name == "offlattice_2d":
+            # the paper's regime: max |v_k| dt / dx = 1 (no Euler sub-cycling)
+            dt = wl.dx / ((wl.nv // 2) * wl.dv)
+            forms[name] = dict(workload=wl.name + "_offlattice_cfl1", kinetic_cfl=1.0,
+                               **run_solver(wl, 200, 5, 0, dt=dt))
+        elif name == "strang_2d":
+            forms[name] = dict(workload=wl.name + "_strang", **run_solver(wl, 200, 5, 0, strang=True))
     if "fp32_3d" in forms and "fp64_3d" in forms:
         forms["fp32_3d"]["speedup_vs_fp64_same_workload"] = (
             forms["fp32_3d"]["cv_per_s"] / forms["fp64_3d"]["cv_per_s"])
@@ -354,6 +485,9 @@ def main():
     }
     if args.copy_probe_mb:
         line["copy_probe"] = copy_probe(args.copy_probe_mb)
+        line["stream_probe"] = stream_probe(args.copy_probe_mb)
+        line["roofline"]["frac_of_measured_copy"] = (
+            prim["kinetic_GBps"] / line["stream_probe"]["copy_GBps"])
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)

@@ -326,6 +326,15 @@ hofks_status hofks_closure_train_step(float *params, float *m, float *v, void *p
  * size.  (hofks_closure_enable also sets them, with the scale and threshold.) */
 hofks_status hofks_closure_set_weights(hofks_ctx *ctx, const void *packed, size_t bytes);
 
+/* Measurement aid: stream `bytes` (a multiple of 16, 16-byte aligned device
+ * pointers) with the 16-byte non-temporal loads and stores of the piece
+ * loops and no arithmetic: mode 0 reads src (dst: a 4-byte device word that
+ * is written only for one improbable value), 1 writes dst, 2 copies src to
+ * dst.  Asynchronous on `stream`; the caller times it.  This is the
+ * reachable bandwidth the kinetic kernels are compared with, besides the
+ * vendor peak. */
+hofks_status hofks_stream_probe(int mode, const void *src, void *dst, size_t bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,6 +25,7 @@ SYMBOLS = [
     "hofks_read_tail_substeps", "hofks_set_euler_launches", "hofks_mlp_grad_work_bytes",
     "hofks_closure_prepare_work_bytes", "hofks_closure_prepare", "hofks_mlp_fold_scales",
     "hofks_closure_train_step", "hofks_closure_set_weights", "hofks_mlp_grad_noalloc",
+    "hofks_stream_probe",
 ]
 
 
@@ -97,6 +98,7 @@ def lib():
     L.hofks_closure_train_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_long, f, f, f, f,
                                            i, vp, vp, vp, sz, vp]
     L.hofks_closure_set_weights.argtypes = [vp, vp, sz]
+    L.hofks_stream_probe.argtypes = [i, vp, vp, sz, vp]
     L.hofks_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, i, vp]
     _lib = L

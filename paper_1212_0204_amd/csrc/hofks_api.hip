@@ -31,6 +31,7 @@
 #include "mlp.hpp"
 #include "weno.hpp"
 #include "train.hpp"
+#include "probe.hpp"
 
 using namespace hofks;
 
@@ -2215,6 +2216,33 @@ hofks_status hofks_mlp_grad_noalloc(const void* packed, const float* x, const fl
   const hofks_status st = scratch_address(&work);
   if (st) return st;
   return mlp_grad_launch(packed, x, t, idx, n, grad, loss, (float*)work, (hipStream_t)stream);
+}
+
+hofks_status hofks_stream_probe(int mode, const void* src, void* dst, size_t bytes,
+                                void* stream) {
+  if (mode < 0 || mode > 2 || bytes < 16 || (bytes & 15) || ((uintptr_t)src & 15) ||
+      ((uintptr_t)dst & 15) || (mode != 1 && !src) || (mode != 0 && !dst) || (mode == 0 && !dst))
+    return HOFKS_EINVAL;
+  const size_t nvec = bytes / 16;
+  int ncu = 256, dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const size_t per_block = (size_t)PROBE_TPB * PROBE_UNR;
+  const unsigned grid =
+      (unsigned)std::min<size_t>((size_t)ncu * 8, (nvec + per_block - 1) / per_block);
+  hipStream_t s = (hipStream_t)stream;
+  auto* in = (const pv4*)src;
+  auto* out = (pv4*)dst;
+  if (mode == 0)
+    hipLaunchKernelGGL(k_stream_probe<0>, dim3(grid), dim3(PROBE_TPB), 0, s, in, out, nvec,
+                       (unsigned*)dst);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_stream_probe<1>, dim3(grid), dim3(PROBE_TPB), 0, s, in, out, nvec,
+                       nullptr);
+  else
+    hipLaunchKernelGGL(k_stream_probe<2>, dim3(grid), dim3(PROBE_TPB), 0, s, in, out, nvec,
+                       nullptr);
+  return hipGetLastError() == hipSuccess ? HOFKS_OK : HOFKS_EDEVICE;
 }
 
 size_t hofks_closure_prepare_work_bytes(long n) {

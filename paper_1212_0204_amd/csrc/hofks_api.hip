@@ -613,10 +613,18 @@ void launch_euler(hofks_ctx* c, const StepArgs<T>& a, hipStream_t st) {
   const Plan& P = c->P;
   const int K = std::max(1, std::min(c->s_cap, c->euler_k > 0 ? c->euler_k : c->s_known + 1));
   if (c->desc.scheme == 3) {  // WENO: three Runge-Kutta stage launches per sub-step
-    for (int i = 0; i < K; ++i)
-      for (int stg = 0; stg < 3; ++stg)
-        hipLaunchKernelGGL((k_weno_stage<D, T>), dim3(nblk(P.G.nc)), dim3(256), 0, st, a, P.G, i,
-                           stg);
+    if constexpr (D == 2) {  // 16 x 16 LDS tiles
+      const int ntx = (P.G.n[0] + WT - 1) / WT, nty = (P.G.n[1] + WT - 1) / WT;
+      for (int i = 0; i < K; ++i)
+        for (int stg = 0; stg < 3; ++stg)
+          hipLaunchKernelGGL((k_weno_stage_tile<T>), dim3(ntx * nty), dim3(256), 0, st, a, P.G, i,
+                             stg, ntx);
+    } else {
+      for (int i = 0; i < K; ++i)
+        for (int stg = 0; stg < 3; ++stg)
+          hipLaunchKernelGGL((k_weno_stage<D, T>), dim3(nblk(P.G.nc)), dim3(256), 0, st, a, P.G, i,
+                             stg);
+    }
     hipLaunchKernelGGL((k_weno_tail<D, T, 256>), dim3(P.GE), dim3(256), 0, st, a, P.G, K);
     return;
   }

@@ -300,3 +300,139 @@ __global__ __launch_bounds__(TPB) void k_weno_tail(StepArgs<T> a, Geom G, int K)
 }
 
 }  // namespace hofks
+
+namespace hofks {
+
+// Stage st of sub-step i on a 2D grid with LDS tiles: one block advances a
+// 16 x 16 tile.  The stage input V of the tile and three halo cells on each
+// side (22 x 22) goes to LDS; for each axis the split fluxes of the 22 x 16
+// cells the faces need are formed once, then each face value (17 faces per
+// line, both split parts) once, and every cell adds the difference of its
+// two faces.  Same arithmetic per face as `weno_div`; buffers, speeds and
+// the sub-step count as `k_weno_stage`.
+constexpr int WT = 16;          // tile edge
+constexpr int WH = WT + 6;      // with three halo cells per side
+constexpr int WF = WT + 1;      // faces per tile line
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_weno_stage_tile(StepArgs<T> a, Geom G, int i, int st,
+                                                         int ntx) {
+  constexpr int NM = 4;
+  double* S = a.set_r;
+  const int Nx = G.n[0], Ny = G.n[1];
+  const int X0 = (int)(blockIdx.x % ntx) * WT, Y0 = (int)(blockIdx.x / ntx) * WT;
+  const int t = threadIdx.x;
+  __shared__ double Vt[NM][WH * WH];        // stage input, tile + halo
+  __shared__ double Hs[2][NM][WH * WT];     // split fluxes along one axis
+  __shared__ double Fc[NM][WF * WT];        // face values along one axis
+
+  bool over;
+  const int s = substeps<2>(S, G, a.s_cap, &over);
+  if (i == 0 && st == 0) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < SET_D; q += gridDim.x * blockDim.x)
+      a.set_z[q] = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (over) atomicOr(a.flag, FLAG_SUBSTEP);
+      a.flag[1] = s;
+    }
+  }
+  if (i >= s) return;
+  double alpha[3];
+  row_speeds<2>(S, i, alpha);
+  const double h = G.dt / s;
+  const double *X, *V;
+  double* out;
+  weno_buffers(a, i, st, &X, &V, &out);
+  for (int q = t; q < WH * WH; q += 256) {
+    const int hx = q % WH, hy = q / WH;
+    const int gx = map_axis(X0 + hx - 3, Nx, G.bc[0]);
+    const int gy = map_axis(Y0 + hy - 3, Ny, G.bc[1]);
+    const size_t j = (size_t)gy * Nx + gx;
+#pragma unroll
+    for (int r = 0; r < NM; ++r) Vt[r][q] = V[(size_t)r * G.nc + j];
+  }
+  __syncthreads();
+  bool phys = true;
+  const int lx = t % WT, ly = t / WT;
+  const int gx = X0 + lx, gy = Y0 + ly;
+  const bool own = gx < Nx && gy < Ny;
+  double div[NM] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+  for (int ax = 0; ax < 2; ++ax) {
+    // split fluxes of the cells along ax: x -> (x = -3..18, y = 0..15),
+    // y -> (x = 0..15, y = -3..18); entry e = line * WH + position
+    for (int q = t; q < WH * WT; q += 256) {
+      const int line = q / WH, pos = q % WH;
+      const int hx = ax == 0 ? pos : line + 3, hy = ax == 0 ? line + 3 : pos;
+      double Uq[NM];
+#pragma unroll
+      for (int r = 0; r < NM; ++r) Uq[r] = Vt[r][hy * WH + hx];
+      double Wp[NM], Wm[NM];
+      phys &= split_flux<2>(Uq, ax, alpha[ax], G.gam, Wp, Wm);
+#pragma unroll
+      for (int r = 0; r < NM; ++r) {
+        Hs[0][r][q] = 0.5 * Wp[r];
+        Hs[1][r][q] = 0.5 * Wm[r];
+      }
+    }
+    __syncthreads();
+    // face f of a line lies between cells f - 1 and f (f = 0..16): the +
+    // part from cells f-3 .. f+1, the - part from cells f+2 .. f-2
+    for (int q = t; q < WF * WT * NM; q += 256) {
+      const int r = q / (WF * WT), e = q % (WF * WT);
+      const int line = e / WF, f = e % WF;
+      const double* hp = &Hs[0][r][line * WH + f];  // cell f - 3 at offset 0
+      const double* hm = &Hs[1][r][line * WH + f];
+      Fc[r][e] = weno5(hp[0], hp[1], hp[2], hp[3], hp[4]) + weno5(hm[5], hm[4], hm[3], hm[2], hm[1]);
+    }
+    __syncthreads();
+    if (own) {
+      const int line = ax == 0 ? ly : lx, c = ax == 0 ? lx : ly;
+#pragma unroll
+      for (int r = 0; r < NM; ++r) div[r] += Fc[r][line * WF + c + 1] - Fc[r][line * WF + c];
+    }
+    __syncthreads();  // Hs and Fc are rewritten for the next axis
+  }
+  double mx[2] = {0.0, 0.0};
+  const bool want = st == 2 && i + 1 < s;
+  if (own) {
+    const size_t j = (size_t)gy * Nx + gx;
+    double Un[NM];
+#pragma unroll
+    for (int r = 0; r < NM; ++r) {
+      const double L = -div[r] / G.dx;
+      const double x = X[(size_t)r * G.nc + j];
+      const double v = Vt[r][(ly + 3) * WH + lx + 3];
+      if (st == 0)
+        Un[r] = v + h * L;
+      else if (st == 1)
+        Un[r] = 0.75 * x + 0.25 * (v + h * L);
+      else
+        Un[r] = x / 3.0 + 2.0 / 3.0 * (v + h * L);
+      out[(size_t)r * G.nc + j] = Un[r];
+    }
+    if (want) {
+      double sp[3];
+      phys &= lf_speeds<2>(Un, G.gam, sp);
+      mx[0] = sp[0];
+      mx[1] = sp[1];
+    }
+  }
+  if (!phys) atomicOr(a.flag, FLAG_NONPHYS);
+  if (want) {
+    __shared__ double wm4[4][ASTR];
+#pragma unroll
+    for (int d2 = 0; d2 < 2; ++d2) {
+      const double m = wave_max(mx[d2]);
+      if ((t & 63) == 0) wm4[t >> 6][d2] = m;
+    }
+    __syncthreads();
+    if (t < 2) {
+      double m = wm4[0][t];
+      for (int w = 1; w < 4; ++w) m = fmax(m, wm4[w][t]);
+      atomic_max_pos(speed_row(S, i + 1, blockIdx.x % NSLOT) + t, m);
+    }
+  }
+}
+
+}  // namespace hofks

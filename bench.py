@@ -106,7 +106,8 @@ def run_solver(wl, steps, warmup, precision, scheme=0, dt=None, strang=False):
         "kinetic_GBps": achieved,
         "kinetic_hbm_frac": achieved / HBM_PEAK_GBPS,
         "step_hbm_frac": bpcv * cv / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-        "tuned": {"wavefronts_per_block": tuned[0], "loads_ahead": tuned[1]},
+        "tuned": {"wavefronts_per_block": tuned[0], "loads_ahead": tuned[1],
+                  "euler_before_kinetic": bool(tuned[2])},
     }
     del s
     torch.cuda.empty_cache()

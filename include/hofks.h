@@ -194,15 +194,27 @@ hofks_status hofks_batch_tube_flags(hofks_ctx *ctx, int *flags);
  * the current state, which is advanced (set the state again afterwards), and
  * keeps the fastest:
  *   single grid: wavefronts per kinetic block and piece loads issued ahead,
- *                choice = (wavefronts, loads); 3D grids use blocks of four
- *                y rows (four wavefronts) and tune the loads only;
+ *                then the placement of the Euler solve (beside the kinetic
+ *                kernel on the library's second stream, or before it on the
+ *                context's stream), choice = (wavefronts, loads,
+ *                euler_before); 3D grids use blocks of four y rows (four
+ *                wavefronts) and tune the loads only;
  *   batch:       cells per kinetic item and persistent grid size,
- *                choice = (cells, blocks).
+ *                choice = (cells, blocks, 0).
  * cache_path (may be NULL) is a JSON-lines file of earlier choices keyed by
  * the grid or batch shape; a match skips the timing, a new choice is
- * appended.  choice[2] may be NULL. */
+ * appended.  choice[3] may be NULL. */
 hofks_status hofks_autotune(hofks_ctx *ctx, int steps, const char *cache_path,
-                            int choice[2]);
+                            int choice[3]);
+
+/* Set the launch configuration of a single grid without timing: wavefronts
+ * per kinetic block and loads ahead as the autotuner's candidates (2D FP64
+ * grids: 2 or 4 wavefronts, 4 or 8 loads; others: 2, 4 or 8 (2D/3D)
+ * wavefronts, 8 or 16 loads; 3D grids 4 wavefronts), and euler_before = 1 to
+ * run the Euler solve before the kinetic kernel on the context's stream
+ * (0: beside it on the library's second stream).  Results do not depend on
+ * the configuration.  HOFKS_EINVAL for a batch or an unavailable choice. */
+hofks_status hofks_set_launch_config(hofks_ctx *ctx, int wavefronts, int loads, int euler_before);
 
 /* ------------------------------------------------- learned closure (2D-2V)
  * Not part of the paper: near-equilibrium cells skip the pieces.  The moment

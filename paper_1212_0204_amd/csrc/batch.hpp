@@ -52,6 +52,7 @@ __device__ __forceinline__ Geom tube_geom(const TubeDev& T) {
   G.nv = T.nv1;
   G.bc[0] = 1;
   G.bc[1] = G.bc[2] = 0;
+  G.offl = 0;
   G.dx = T.dx;
   G.dv = T.dv;
   G.dt = T.dt;

@@ -244,8 +244,8 @@ hofks_status make_plan(const hofks_grid_desc* desc, Plan* P, char* err) {
   off = align256(off + (size_t)P->RS * G.nc * P->tsize);
   P->off_rec[1] = off;
   off = align256(off + (size_t)P->RS * G.nc * P->tsize);
-  P->off_vt = off;
-  off = align256(off + (size_t)G.nv1 * sizeof(VelNode));
+  P->off_vt = off;  // node table, then c = v dt/dx per node
+  off = align256(off + (size_t)G.nv1 * (sizeof(VelNode) + sizeof(double)));
   P->off_cf = off;
   off = align256(off + ubytes);
   P->off_part = off;
@@ -286,6 +286,7 @@ struct hofks_ctx {
   int s_cap;
   int s_known;  // Euler sub-steps of the last step seen by the host
   int euler_k;  // > 0: per-sub-step Euler launches before the tail (0: s_known + 1)
+  bool euler_seq;   // the Euler solve runs on the caller's stream before the kinetic kernel
   bool strang;      // Strang splitting: half relaxations around each transport
   double inv_prev;  // 1/tau of the last step taken (Strang)
   long steps;
@@ -561,6 +562,12 @@ void launch_euler(hofks_ctx* c, const StepArgs<T>& a, hipStream_t st);
 // already queued on the caller's stream
 template <int D, typename T>
 hofks_status fork_euler(hofks_ctx* c, const StepArgs<T>& a) {
+  if (c->euler_seq) {  // before the kinetic kernel, on the caller's stream
+    Mark m0(c, 0, 1, c->stream);
+    launch_euler<D, T>(c, a, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return HOFKS_OK;
+  }
   // within one hofks_step call the previous step recorded the fork point
   // right after U^{n+1} was formed, before its records
   if (c->fork_pending)
@@ -581,7 +588,7 @@ hofks_status fork_euler(hofks_ctx* c, const StepArgs<T>& a) {
 template <int D, typename T, bool CLOS>
 hofks_status join_update(hofks_ctx* c, const StepArgs<T>& a) {
   const Plan& P = c->P;
-  HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+  if (!c->euler_seq) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
   Mark m(c, 2);
   if constexpr (CLOS) {
     hipLaunchKernelGGL((k_cell_update<D, T, CLOS>), dim3(nblk(P.G.nc)), dim3(256), 0, c->stream,
@@ -591,7 +598,7 @@ hofks_status join_update(hofks_ctx* c, const StepArgs<T>& a) {
     // then the records, beside the next step's Euler solve
     hipLaunchKernelGGL((k_cell_update_u<D, T>), dim3(nblk(P.G.nc)), dim3(256), 0, c->stream, a,
                        P.G, P.A);
-    if (c->fork_next) {
+    if (c->fork_next && !c->euler_seq) {
       HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
       c->fork_pending = true;
     }
@@ -1010,11 +1017,15 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
   std::vector<VelNode> tab(P.G.nv1);
   for (int i = 0; i < P.G.nv1; ++i) {
     const double v = (i - P.G.kofs) * P.G.dv;
-    tab[i] = VelNode{v, v * v, (float)v, (float)(0.5 * v * v), 0.5 * v * v, v * P.G.dt / P.G.dx};
+    tab[i] = VelNode{v, v * v, (float)v, (float)(0.5 * v * v), 0.5 * v * v};
   }
+  std::vector<double> ctab(P.G.nv1);
+  for (int i = 0; i < P.G.nv1; ++i) ctab[i] = ((i - P.G.kofs) * P.G.dv) * P.G.dt / P.G.dx;
   if (reset_counters(c) != HOFKS_OK ||
       hipMemcpyAsync(c->vt, tab.data(), tab.size() * sizeof(VelNode), hipMemcpyHostToDevice,
                      c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->vt + P.G.nv1, ctab.data(), ctab.size() * sizeof(double),
+                     hipMemcpyHostToDevice, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     delete c;
     return HOFKS_EDEVICE;
@@ -1734,6 +1745,7 @@ hofks_status grid_autotune(hofks_ctx* c, int steps, const char* cache_path, int*
     if (choice) {
       choice[0] = 4;
       choice[1] = P.d >= 2 ? 4 : 1;
+      choice[2] = c->euler_seq;
     }
     return HOFKS_OK;
   }
@@ -1741,7 +1753,7 @@ hofks_status grid_autotune(hofks_ctx* c, int steps, const char* cache_path, int*
   key << "gfx950:grid:d=" << P.d << ":n=" << P.G.n[0] << "x" << P.G.n[1] << "x" << P.G.n[2]
       << ":nv=" << P.G.nv1 << ":prec=" << P.prec << ":bc=" << P.G.bc[0] << P.G.bc[1] << P.G.bc[2]
       << ":scheme=" << c->desc.scheme;
-  int best_ng = 0, best_unr = 0;
+  int best_ng = 0, best_unr = 0, best_seq = 0;
   if (cache_path && *cache_path) {
     std::ifstream in(cache_path);
     std::string line;
@@ -1749,12 +1761,15 @@ hofks_status grid_autotune(hofks_ctx* c, int steps, const char* cache_path, int*
     while (std::getline(in, line)) {
       if (line.find(k) == std::string::npos) continue;
       const size_t pn = line.find("\"ng\": "), pu = line.find("\"unr\": ");
-      if (pn == std::string::npos || pu == std::string::npos) continue;
+      const size_t ps = line.find("\"seq\": ");
+      if (pn == std::string::npos || pu == std::string::npos || ps == std::string::npos) continue;
       const int ng = std::atoi(line.c_str() + pn + 6), unr = std::atoi(line.c_str() + pu + 7);
+      const int sq = std::atoi(line.c_str() + ps + 7);
       if ((ng == 2 || ng == 4 || (ng == 8 && P.d >= 2)) &&
-          (unr == 8 || unr == 16 || (unr == 4 && c->kwide))) {
+          (unr == 8 || unr == 16 || (unr == 4 && c->kwide)) && (sq == 0 || sq == 1)) {
         best_ng = ng;
         best_unr = unr;
+        best_seq = sq;
       }
     }
   }
@@ -1789,19 +1804,40 @@ hofks_status grid_autotune(hofks_ctx* c, int steps, const char* cache_path, int*
         best_unr = cd[1];
       }
     }
+    // the Euler solve before the kinetic kernel instead of beside it: it
+    // then has the chip to itself and does not slow the kinetic kernel
+    if (best_ng) {
+      c->kng = best_ng;
+      c->kunr = best_unr;
+      c->euler_seq = !c->euler_seq;
+      hofks_status st = hofks_step(c, 1);
+      if (st) return st;
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+      st = hofks_step(c, steps);
+      if (st) return st;
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      HIPCHK(c, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) best_ms = ms;
+      else c->euler_seq = !c->euler_seq;
+      best_seq = c->euler_seq;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (cache_path && *cache_path) {
       std::ofstream o(cache_path, std::ios::app);
       o << "{\"key\": \"" << key.str() << "\", \"ng\": " << best_ng << ", \"unr\": " << best_unr
-        << ", \"ms_per_step\": " << best_ms / steps << "}\n";
+        << ", \"seq\": " << best_seq << ", \"ms_per_step\": " << best_ms / steps << "}\n";
     }
   }
   c->kng = best_ng;
   c->kunr = best_unr;
+  c->euler_seq = best_seq != 0;
   if (choice) {
     choice[0] = best_ng;
     choice[1] = best_unr;
+    choice[2] = best_seq;
   }
   return read_flag(c);
 }
@@ -1884,7 +1920,7 @@ hofks_status hofks_batch_create(const hofks_grid_desc* descs, const double* taus
   for (const TubeDev& T : B->tubes)
     for (int i = 0; i < T.nv1; ++i) {
       const double v = (i - T.kofs) * T.dv;
-      tab.push_back(VelNode{v, v * v, (float)v, (float)(0.5 * v * v), 0.5 * v * v, 0.0});
+      tab.push_back(VelNode{v, v * v, (float)v, (float)(0.5 * v * v), 0.5 * v * v});
     }
   if (hipMemcpyAsync(B->vtar, tab.data(), sizeof(VelNode) * tab.size(), hipMemcpyHostToDevice,
                      c->stream) != hipSuccess ||
@@ -1915,6 +1951,21 @@ hofks_status hofks_batch_tube_flags(hofks_ctx* c, int* flags) {
 // timing `steps` steps of each candidate on the current state (which is
 // advanced).  With a cache file, a matching line is reused without timing;
 // otherwise the result is appended.
+hofks_status hofks_set_launch_config(hofks_ctx* c, int wavefronts, int loads, int euler_before) {
+  if (!c || c->batch || euler_before < 0 || euler_before > 1) return HOFKS_EINVAL;
+  const Plan& P = c->P;
+  const bool ok_w = c->kwide ? ((wavefronts == 2 || wavefronts == 4) && (loads == 4 || loads == 8) &&
+                                kin2w_lds(P, wavefronts) <= 65536)
+                             : ((wavefronts == 2 || wavefronts == 4 || (wavefronts == 8 && P.d >= 2)) &&
+                                (loads == 8 || loads == 16) && kin_lds(P, wavefronts) <= 65536);
+  if (!ok_w || (c->kring && wavefronts != RY))
+    return fmt_err(c->err, "launch configuration not available for this grid"), HOFKS_EINVAL;
+  c->kng = wavefronts;
+  c->kunr = loads;
+  c->euler_seq = euler_before != 0;
+  return HOFKS_OK;
+}
+
 hofks_status hofks_autotune(hofks_ctx* c, int steps, const char* cache_path, int* choice) {
   if (!c || !c->ready || steps < 1) return HOFKS_EINVAL;
   if (!c->batch) return grid_autotune(c, steps, cache_path, choice);
@@ -1986,6 +2037,7 @@ hofks_status hofks_autotune(hofks_ctx* c, int steps, const char* cache_path, int
   if (choice) {
     choice[0] = best_cells;
     choice[1] = best_grid;
+    choice[2] = 0;
   }
   return batch_read_flag(c);
 }

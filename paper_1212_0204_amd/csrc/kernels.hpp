@@ -197,12 +197,13 @@ struct Vec16<float> {
   using type = float4;
 };
 
-// velocity node table of one axis: v, v^2, and FP32 copies (scalar loads)
+// velocity node table of one axis: v, v^2, and FP32 copies (scalar loads);
+// it is followed in memory by nv1 doubles c = v dt / dx, the cells a piece
+// travels per step (read only by off-lattice steps)
 struct VelNode {
   double v, v2;
   float vf, v2hf;  // (float)v, (float)(v^2 / 2)
   double v2h;      // v^2 / 2
-  double c;        // v dt / dx: cells travelled per step (off-lattice transport)
 };
 
 // Cells moved by the pieces of velocity node i in the step t^n -> t^{n+1}
@@ -215,8 +216,8 @@ struct VelNode {
 __device__ __forceinline__ int node_shift(const VelNode* vt, int i, const Geom& G, long n) {
 #pragma clang fp contract(off)
   if (!G.offl) return i - G.kofs;
-  using CVN = const __attribute__((address_space(4))) VelNode;
-  const double c = ((CVN*)vt + i)->c;
+  using CD = const __attribute__((address_space(4))) double;
+  const double c = ((CD*)(vt + G.nv1))[i];
   const double a = c * (double)(n + 1) - 0.5;
   const double b = c * (double)n - 0.5;
   const int sh = (int)(ceil(a) - ceil(b));

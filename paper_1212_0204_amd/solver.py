@@ -160,13 +160,20 @@ class Solver:
     def dt(self):
         return _lib.lib().hofks_dt(self._h)
 
+    def set_launch_config(self, wavefronts, loads, euler_before):
+        """a launch configuration without timing (see hofks_set_launch_config)"""
+        self._check(_lib.lib().hofks_set_launch_config(self._h, int(wavefronts), int(loads),
+                                                       int(euler_before)), "set_launch_config")
+
     def autotune(self, steps=4, cache_path=None):
         """time the candidate launch configurations (advances the state: set
-        it again afterwards); returns the chosen pair"""
-        ch = (ctypes.c_int * 2)()
+        it again afterwards); returns the chosen (wavefronts, loads ahead,
+        Euler solve before the kinetic kernel) for a grid, (cells per item,
+        blocks, 0) for a batch"""
+        ch = (ctypes.c_int * 3)()
         cp = cache_path.encode() if cache_path else None
         self._check(_lib.lib().hofks_autotune(self._h, int(steps), cp, ch), "autotune")
-        return int(ch[0]), int(ch[1])
+        return int(ch[0]), int(ch[1]), int(ch[2])
 
     # ------------------------------------------------ closure form (2D-2V)
     def closure_enable(self, net, threshold=1e-3):

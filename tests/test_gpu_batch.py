@@ -84,10 +84,10 @@ def test_autotuned_configuration_matches_oracle(tmp_path):
     fields = tube_fields(tubes)
     b.set_state_macro(*fields)
     cache = str(tmp_path / "tune.jsonl")
-    cells, grid = b.autotune(steps=3, cache_path=cache)
+    cells, grid, _ = b.autotune(steps=3, cache_path=cache)
     assert cells in (128, 256, 512) and grid > 0
     # the cached choice is reused without timing
-    assert b.autotune(steps=3, cache_path=cache) == (cells, grid)
+    assert b.autotune(steps=3, cache_path=cache) == (cells, grid, 0)
     b.set_state_macro(*fields)
     b.step(10)
     for t, U in zip(tubes, b.read_moments()):

@@ -262,9 +262,9 @@ def test_grid_autotune_then_parity(tmp_path):
     s = _solver(dim=2, n_cells=n, dx=1 / 96, n_vel=16, dv=0.5, bc=(0, 0), tau=1e-3)
     s.set_state_macro(rho, u, th)
     cache = str(tmp_path / "tune.jsonl")
-    ng, unr = s.autotune(steps=2, cache_path=cache)
-    assert ng in (2, 4, 8) and unr in (4, 8, 16)
-    assert s.autotune(steps=2, cache_path=cache) == (ng, unr)
+    ng, unr, seq = s.autotune(steps=2, cache_path=cache)
+    assert ng in (2, 4, 8) and unr in (4, 8, 16) and seq in (0, 1)
+    assert s.autotune(steps=2, cache_path=cache) == (ng, unr, seq)
     s.set_state_macro(rho, u, th)
     s.step(6)
     o = Oracle(2, n, 1 / 96, 16, 0.5, bc=(0, 0), tau=1e-3)
@@ -653,3 +653,31 @@ def test_strang_tau_change_and_checkpoint():
         s2.step(3)
     assert np.array_equal(s2.read_moments(), s.read_moments())
     assert np.array_equal(s2.read_f(), s.read_f())
+
+
+@gpu
+@pytest.mark.parametrize("d,n,nv,prec,cfg", [
+    (2, (70, 37), 16, 0, (4, 4)), (2, (67, 19), 12, 1, (8, 16)), (3, (20, 12, 10), 8, 1, (4, 8)),
+    (1, (130,), 24, 0, (4, 8)),
+])
+def test_euler_before_or_beside_the_kinetic_kernel(d, n, nv, prec, cfg):
+    """the Euler solve before the kinetic kernel (one stream) or beside it
+    (a second stream): bit-identical results, and the oracle's"""
+    announce("euler placement", d, n, nv, prec, cfg)
+    from paper_1212_0204_amd import Solver
+    nc = int(np.prod(n))
+    fields = W.sod_tube(n[0]) if d == 1 else _random_fields(d, nc, 73)
+    bc = (1,) if d == 1 else (0,) * d
+    runs = []
+    for before in (0, 1):
+        s = Solver(d, n, 1.0 / n[0], nv, 0.5, bc=bc, tau=2e-2, precision=prec)
+        s.set_launch_config(cfg[0], cfg[1], before)
+        s.set_state_macro(*fields)
+        s.step(3)
+        s.step(4)
+        runs.append((s.read_moments(), s.read_f()))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    o = Oracle(d, n, 1.0 / n[0], nv, 0.5, bc=bc, tau=2e-2)
+    o.init_macro(*fields)
+    o.step(7)
+    assert moment_errors(runs[1][0], o.U, d).max() < (TOL64 if prec == 0 else TOL32)

@@ -116,7 +116,8 @@ def run_solver(wl, steps, warmup, precision, scheme=0, dt=None, strang=False):
 
 def run_batch(steps, warmup):
     """the batched form: 512 independent shock tubes (seed 4), FP32 pieces,
-    one persistent launch per step replayed from a captured graph"""
+    an Euler launch and a kinetic launch side by side, then the update
+    launch, per step, replayed from a captured graph"""
     import numpy as np
     import torch
     import workloads as W
@@ -155,7 +156,7 @@ def run_batch(steps, warmup):
            "steps": steps, "cv_per_s": cv_ok / (ms * 1e-3), "ms_per_step": ms / steps,
            "cv_per_s_incl_flagged_tubes": cv / (ms * 1e-3),
            "hbm_frac": 8 * cv_ok / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-           "tuned": {"cells_per_item": tuned[0], "blocks": tuned[1]},
+           "tuned": {"cells_per_item": tuned[0], "euler_part": tuned[1]},
            "flagged_tubes": flagged,
            # cold-side velocity resolution of each tube: dv / sqrt(theta_min)
            "dv_over_cold_thermal_speed": dict(zip(

@@ -199,8 +199,8 @@ hofks_status hofks_batch_tube_flags(hofks_ctx *ctx, int *flags);
  *                context's stream), choice = (wavefronts, loads,
  *                euler_before); 3D grids use blocks of four y rows (four
  *                wavefronts) and tune the loads only;
- *   batch:       cells per kinetic item and persistent grid size,
- *                choice = (cells, blocks, 0).
+ *   batch:       cells per kinetic item, then the part size of the split
+ *                Euler solves, choice = (cells, euler_part, 0).
  * cache_path (may be NULL) is a JSON-lines file of earlier choices keyed by
  * the grid or batch shape; a match skips the timing, a new choice is
  * appended.  choice[3] may be NULL. */
@@ -215,6 +215,16 @@ hofks_status hofks_autotune(hofks_ctx *ctx, int steps, const char *cache_path,
  * (0: beside it on the library's second stream).  Results do not depend on
  * the configuration.  HOFKS_EINVAL for a batch or an unavailable choice. */
 hofks_status hofks_set_launch_config(hofks_ctx *ctx, int wavefronts, int loads, int euler_before);
+
+/* Set the launch configuration of a batch without timing: cells per kinetic
+ * item (256, 512 or 1024) and euler_part, the cells per part of a split Euler
+ * solve (1024 or 2048: a tube of Nx > euler_part cells is solved by
+ * ceil(Nx / euler_part) blocks meeting after every sub-step, when that is at
+ * most 64 and at most the compute units; 0: every tube whole in one block).
+ * Results do not depend on the configuration.  The work order is taken
+ * again from the current speeds.  HOFKS_EINVAL for a single grid or an
+ * unavailable choice. */
+hofks_status hofks_batch_set_launch_config(hofks_ctx *ctx, int cells, int euler_part);
 
 /* ------------------------------------------------- learned closure (2D-2V)
  * Not part of the paper: near-equilibrium cells skip the pieces.  The moment

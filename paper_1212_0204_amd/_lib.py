@@ -25,7 +25,7 @@ SYMBOLS = [
     "hofks_read_tail_substeps", "hofks_set_euler_launches", "hofks_mlp_grad_work_bytes",
     "hofks_closure_prepare_work_bytes", "hofks_closure_prepare", "hofks_mlp_fold_scales",
     "hofks_closure_train_step", "hofks_closure_set_weights", "hofks_mlp_grad_noalloc",
-    "hofks_stream_probe", "hofks_set_launch_config",
+    "hofks_stream_probe", "hofks_set_launch_config", "hofks_batch_set_launch_config",
 ]
 
 
@@ -100,6 +100,7 @@ def lib():
     L.hofks_closure_set_weights.argtypes = [vp, vp, sz]
     L.hofks_stream_probe.argtypes = [i, vp, vp, sz, vp]
     L.hofks_set_launch_config.argtypes = [vp, i, i, i]
+    L.hofks_batch_set_launch_config.argtypes = [vp, i, i]
     L.hofks_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, i, vp]
     _lib = L

@@ -1,11 +1,12 @@
-// batch.hpp -- batched persistent form: many independent 1D-1V tubes (each
-// with its own cells, velocity grid, dt and tau) advanced together.  A step is
-// two launches: a persistent grid pulls from one queue first the Euler solves
-// of the tubes (one 1024-thread block per tube, s MUSCL sub-steps with the
-// tube's moments in registers, largest first) and then the kinetic items (a CELLS-cell segment of one tube with
-// all its velocities split over 1024/CELLS groups of threads, writing the
-// moment sums of its cells), so the two run side by side; the update launch
-// then forms U^{n+1} and the next records cell by cell.
+// batch.hpp -- batched form: many independent 1D-1V tubes (each with its own
+// cells, velocity grid, dt and tau) advanced together.  A step is three
+// launches: the Euler launch (one block per Euler item: a tube's whole Euler
+// solve, or one part of a long tube split over several blocks that meet
+// after every sub-step; most work first) and the kinetic launch (one block
+// per CELLS-cell segment of a tube with all its velocities split over
+// 1024/CELLS groups of threads, writing the moment sums of its cells) run
+// side by side on two streams; the update launch then forms U^{n+1} and the
+// next records cell by cell.
 #pragma once
 #include "kernels.hpp"
 
@@ -18,6 +19,7 @@ struct TubeDev {
   long long UE[2];   // Euler sub-step buffers (doubles)
   long long cf;      // pending correction (doubles)
   long long S;       // moment sums of f* and E per cell (doubles), 6 x Nx
+  long long X;       // part exchange rows (doubles), 2 x ceil(Nx / 1024) x XSTR
   int vt;            // first velocity node of the tube in the node arena
   int Nx, nv1, kofs;
   double dx, dv, dt, w, lam, mu, gam;
@@ -30,10 +32,11 @@ struct BatchArgs {
   double* dar;            // moment arena
   const VelNode* vtar;    // velocity node arena
   const TubeDev* tubes;
-  const int* euler_order; // tubes, most Euler work first
-  const int2* items;      // kinetic items (tube, segment), most work first
-  int ntubes, nitems;
-  int* queue;             // work counters by step parity
+  const int4* eitems;     // Euler items (tube, part, parts, split), most work first
+  const int2* items;      // kinetic items (tube, segment) dealt to the dies; tube -1: none
+  int neuler, nitems;
+  int part_cells;         // cells per part of a split Euler solve (1024 or 2048)
+  unsigned* ebar;         // [tube][parity]: arrivals at the part barriers
   double* alpha;          // [tube][parity][ASTR]: speeds of U^n / U^{n+1}
   int* tube_s;            // sub-steps of the current step, per tube
   int* tflag;             // per-tube error bits
@@ -78,17 +81,114 @@ __device__ __forceinline__ double block_max_1024(double v, double* red) {
   return m;
 }
 
+// 1/x from the hardware reciprocal refined by two Newton steps (within a
+// few ulp of the IEEE quotient, and a shorter dependency chain)
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
+// max(v, v of the lane that DPP control CTRL selects) for the rows in
+// ROW_MASK; lanes without a source keep v
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_max(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, ROW_MASK, 0xF,
+                                             false);
+  return fmax(v, __longlong_as_double(((long long)hi << 32) | (unsigned)lo));
+}
+
+// maximum over the wavefront, in every lane: row shifts by 1, 2, 4 and 8
+// leave each row's maximum in its lane 15, the row broadcasts carry rows 0
+// and 2 into rows 1 and 3 and then row 1 into rows 2 and 3, and lane 63 is
+// read back (cross-lane moves of the ALU instead of LDS permutes)
+__device__ __forceinline__ double wave_max_dpp(double v) {
+  v = dpp_max<0x111, 0xF>(v);
+  v = dpp_max<0x112, 0xF>(v);
+  v = dpp_max<0x114, 0xF>(v);
+  v = dpp_max<0x118, 0xF>(v);
+  v = dpp_max<0x142, 0xA>(v);
+  v = dpp_max<0x143, 0xC>(v);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Flux F(U) of one 1D cell from U and 1/rho, with the expressions of
+// split_flux (W+- = F +- alpha U); false if the state is not physical
+__device__ __forceinline__ bool flux1(const double* U, double irho, double* F) {
+  const double rho = U[0];
+  const double u = U[1] * irho;
+  const double usq = u * u;
+  const double p = fma(-rho, usq, 2.0 * U[2]);
+  F[0] = U[1];
+  F[1] = fma(U[1], u, p);
+  F[2] = (U[2] + p) * u;
+  return (rho > 0.0) && (p > 0.0) && isfinite(rho) && isfinite(p) && isfinite(usq);
+}
+
+// Lax-Friedrichs speed |u| + sqrt(gam p / rho) of one 1D cell (p = rho
+// theta) from U and 1/rho; 0 and false if the state is not physical
+__device__ __forceinline__ bool speed1(const double* U, double irho, double gam, double* sp) {
+  const double rho = U[0];
+  const double u = U[1] * irho;
+  const double usq = u * u;
+  const double p = fma(-rho, usq, 2.0 * U[2]);
+  const bool ok = (rho > 0.0) && (p > 0.0) && isfinite(rho) && isfinite(p) && isfinite(usq);
+  *sp = ok ? fabs(u) + sqrt(gam * p * irho) : 0.0;
+  return ok;
+}
+
+// W+ (w[0..2]) and W- (w[3..5]) of one cell
+__device__ __forceinline__ void wsplit(const double* U, const double* F, double alpha, double* w) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    w[r] = fma(alpha, U[r], F[r]);
+    w[3 + r] = fma(-alpha, U[r], F[r]);
+  }
+}
+
+// vl_slope without a branch: the same quotient, selected when ab > 0 (the
+// divergent branch of vl_slope keeps values live across it and serialises
+// the six slopes of a face)
+__device__ __forceinline__ double vl_slope_sel(double a, double b) {
+  const double ab = a * b;
+  const double den = a + b;
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(fma(-den, r, 1.0), r, r);
+  r = fma(fma(-den, r, 1.0), r, r);
+  const double q = 2.0 * ab * r;
+  const double v = fma(fma(-den, q, 2.0 * ab), r, q);
+  return ab > 0.0 ? v : 0.0;
+}
+
+// face flux between the cells of entries 1 and 2 of a four-entry window
+// (the face arithmetic of section 4.3.2 as in the other Euler forms)
+__device__ __forceinline__ void face4(const double* w0, const double* w1, const double* w2,
+                                      const double* w3, double* fc) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double spl = vl_slope_sel(w1[r] - w0[r], w2[r] - w1[r]);
+    const double sml = vl_slope_sel(w2[3 + r] - w1[3 + r], w3[3 + r] - w2[3 + r]);
+    fc[r] = fma(0.25, spl - sml, 0.5 * (w1[r] + w2[3 + r]));
+  }
+}
+
 // Euler solve of one tube by segments of EUL_TPB cells (eq. (discmom) with
 // the limited slopes of section 4.3.2): per sub-step and segment the block
 // evaluates the split fluxes W+- of the segment and two cells on each side
 // once into LDS, then the face fluxes psi of the segment's faces into LDS,
 // then the new cell values, written out of place to the other sub-step
 // buffer.  Every flux and every face is computed once (the global-memory
-// form evaluates five fluxes and two faces per cell).  Same arithmetic per
-// face as `euler_cell`; the result is UE[s % 2].
+// form evaluates five fluxes and two faces per cell).  Same helpers (flux1,
+// wsplit, vl_slope_sel, speed1) as the register and part forms, so all
+// three give the same bits; the result is UE[s % 2].
 constexpr int EUL_TPB = 1024;
 constexpr size_t EUL_LDS = (size_t)((EUL_TPB + 4) * 6 + (EUL_TPB + 1) * 3) * sizeof(double);
-constexpr size_t EUL_REG_LDS = 2 * EUL_LDS;  // the register form alternates two sets
 
 __device__ void batch_euler_seg(const BatchArgs& a, int t, double* L, double* red) {
   t = __builtin_amdgcn_readfirstlane(t);
@@ -101,7 +201,7 @@ __device__ void batch_euler_seg(const BatchArgs& a, int t, double* L, double* re
   bool over;
   const int s = substeps<1>(&alpha, G, a.s_cap, &over);
   if (threadIdx.x == 0) {
-    alpha_w[0] = 0.0;  // the kinetic launch reduces the speeds of U^{n+1} here
+    alpha_w[0] = 0.0;  // the update launch reduces the speeds of U^{n+1} here
     a.tube_s[t] = s;
     if (over) atomicOr(a.tflag + t, FLAG_SUBSTEP);
   }
@@ -123,8 +223,11 @@ __device__ void batch_euler_seg(const BatchArgs& a, int t, double* L, double* re
       for (int q = threadIdx.x; q < EUL_TPB + 4; q += blockDim.x) {
         const int jj = min(max(x0 - 2 + q, 0), Nx - 1);
         const double Uq[3] = {in[jj], in[(size_t)Nx + jj], in[2 * (size_t)Nx + jj]};
-        double Wp[3], Wm[3];
-        phys &= split_flux<1>(Uq, 0, alpha, G.gam, Wp, Wm);
+        double F[3], w[6];
+        phys &= flux1(Uq, rcp_nr(Uq[0]), F);
+        wsplit(Uq, F, alpha, w);
+        const double* Wp = w;
+        const double* Wm = w + 3;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
           Wl[q * 6 + r] = Wp[r];
@@ -138,9 +241,9 @@ __device__ void batch_euler_seg(const BatchArgs& a, int t, double* L, double* re
         const double* w = Wl + f * 6;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-          const double spl = vl_slope(w[6 + r] - w[r], w[12 + r] - w[6 + r], 0);
-          const double sml = vl_slope(w[15 + r] - w[9 + r], w[21 + r] - w[15 + r], 0);
-          Pl[f * 3 + r] = 0.5 * (w[6 + r] + w[15 + r]) + 0.25 * (spl - sml);
+          const double spl = vl_slope_sel(w[6 + r] - w[r], w[12 + r] - w[6 + r]);
+          const double sml = vl_slope_sel(w[15 + r] - w[9 + r], w[21 + r] - w[15 + r]);
+          Pl[f * 3 + r] = fma(0.25, spl - sml, 0.5 * (w[6 + r] + w[15 + r]));
         }
       }
       __syncthreads();
@@ -150,12 +253,12 @@ __device__ void batch_euler_seg(const BatchArgs& a, int t, double* L, double* re
         double Un[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
-          Un[r] = in[(size_t)r * Nx + j] - dts_dx * (Pl[(c + 1) * 3 + r] - Pl[c * 3 + r]);
+          Un[r] = fma(-dts_dx, Pl[(c + 1) * 3 + r] - Pl[c * 3 + r], in[(size_t)r * Nx + j]);
 #pragma unroll
         for (int r = 0; r < 3; ++r) out[(size_t)r * Nx + j] = Un[r];
         if (i + 1 < s) {
           double sp;
-          phys &= lf_speeds<1>(Un, G.gam, &sp);
+          phys &= speed1(Un, rcp_nr(Un[0]), G.gam, &sp);
           mx = fmax(mx, sp);
         }
       }
@@ -166,148 +269,414 @@ __device__ void batch_euler_seg(const BatchArgs& a, int t, double* L, double* re
   if (!phys) atomicOr(a.tflag + t, FLAG_NONPHYS);
 }
 
-// Euler solve of one tube of at most EUL_TPB * EUL_CPT cells with the
-// moments held in registers for all s sub-steps: thread t owns cells
-// t + k EUL_TPB (slab k).  Per sub-step and slab the owners write the split
-// fluxes W+- of their cells (and of the two cells beyond each end of the
-// slab, which they also own, or the boundary cell for the clamped outflow
-// entries) into LDS, the faces of the slab are formed once each, and every
-// owner updates its cell; memory is read once at the start and written once
-// at the end (UE[s % 2]).  Same arithmetic per flux and face as
-// `batch_euler_seg` and `euler_cell`.
-constexpr int EUL_CPT = 4;
+// Euler solve of one tube of at most 1024 * CPT cells with every cell's
+// moments (and 1/rho) in registers for all s sub-steps: thread t owns the
+// CPT consecutive cells t CPT .. t CPT + CPT - 1, so the four-cell stencil of
+// a face reaches at most two cells into each neighbouring thread.  After
+// every sub-step a thread leaves U and 1/rho of its first two and last two
+// cells in its LDS slots, which the neighbouring lanes of its wavefront read
+// during the next sub-step (a wavefront's LDS operations complete in order,
+// so no barrier is needed between lanes of one wavefront); at the ends of a
+// wavefront the cells come from the edge set that each wavefront leaves for
+// its neighbours (one set per sub-step parity, so the one block barrier per
+// sub-step, which also publishes the wavefront speed maxima that make
+// alpha, orders them).  A thread forms the split fluxes of each stencil
+// entry as it enters a four-entry window, the left faces of its cells and
+// the right face of its last cell (which its right neighbour forms too,
+// from the same values with the same arithmetic), and updates its cells.
+// Outflow ends: entries before cell 0 repeat cell 0, those past cell
+// Nx - 1 repeat cell Nx - 1.
+constexpr int RUN_WAVES = 16;
+constexpr int RUN_TPB = 64 * RUN_WAVES;
+constexpr int RUN_SLOT = 4;  // doubles per exchanged cell: U, 1/rho
+// LDS of the run form: per-thread slots [4 cells][RUN_SLOT][RUN_TPB], the
+// wavefront edge sets [2][RUN_WAVES][4 cells][RUN_SLOT] and the wavefront
+// speed maxima [2][RUN_WAVES]
+constexpr int RUN_SL = 4 * RUN_SLOT * RUN_TPB;
+constexpr int RUN_EX = 2 * RUN_WAVES * 4 * RUN_SLOT;
+constexpr size_t RUN_LDS = (size_t)(RUN_SL + RUN_EX + 2 * RUN_WAVES) * sizeof(double);
 
-__device__ void batch_euler_reg(const BatchArgs& a, int t, double* L, double* red) {
+template <int CPT>
+__device__ void batch_euler_run(const BatchArgs& a, int t, double* L) {
   t = __builtin_amdgcn_readfirstlane(t);
   const TubeDev T = a.tubes[t];
   const Geom G = tube_geom(T);
   const int p = a.parity;
-  double* alpha_r = a.alpha + ((size_t)t * 2 + p) * ASTR;
-  double* alpha_w = a.alpha + ((size_t)t * 2 + (p ^ 1)) * ASTR;
-  double alpha = __hip_atomic_load(alpha_r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double alpha = __hip_atomic_load(a.alpha + ((size_t)t * 2 + p) * ASTR, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
   bool over;
   const int s = substeps<1>(&alpha, G, a.s_cap, &over);
   if (threadIdx.x == 0) {
-    alpha_w[0] = 0.0;  // the kinetic launch reduces the speeds of U^{n+1} here
+    // the update launch reduces the speeds of U^{n+1} into the other row
+    a.alpha[((size_t)t * 2 + (p ^ 1)) * ASTR] = 0.0;
     a.tube_s[t] = s;
     if (over) atomicOr(a.tflag + t, FLAG_SUBSTEP);
   }
   if (G.mu == 0.0) return;
   const int Nx = G.nc;
-  const int nslab = (Nx + EUL_TPB - 1) / EUL_TPB;
-  // two sets of LDS entries, alternating between slabs, so that a slab's
-  // writes need no barrier after the previous slab's reads (the barriers
-  // inside each slab already separate slab k's reads from slab k+2's writes)
-  double* Wl0 = L;                       // [EUL_TPB + 4][6]: W+ (3), W- (3)
-  double* Pl0 = L + (EUL_TPB + 4) * 6;   // [EUL_TPB + 1][3]: face fluxes
-  double* Wl1 = L + EUL_LDS / sizeof(double);
-  double* Pl1 = Wl1 + (EUL_TPB + 4) * 6;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int c0 = tid * CPT;          // first cell of the thread
+  const int wfirst = wv * 64 * CPT;  // first cell of the wavefront
+  double* SL = L;                    // [4][RUN_SLOT][RUN_TPB]
+  double* EX = L + RUN_SL;           // [2][RUN_WAVES][4][RUN_SLOT]
+  double* WM = L + RUN_SL + RUN_EX;  // [2][RUN_WAVES]
   const double* U0 = a.dar + (p ? T.U[1] : T.U[0]);
-  double Ur[EUL_CPT][3], Un[EUL_CPT][3];
+  double U[CPT][3], ir[CPT];
 #pragma unroll
-  for (int k = 0; k < EUL_CPT; ++k) {
-    const int c = k * EUL_TPB + tid;
+  for (int j = 0; j < CPT; ++j) {
+    const bool ok = c0 + j < Nx;  // idle cells hold a finite placeholder
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      Ur[k][r] = c < Nx ? U0[(size_t)r * Nx + c] : 0.0;
-      Un[k][r] = Ur[k][r];
-    }
+    for (int r = 0; r < 3; ++r) U[j][r] = ok ? U0[(size_t)r * Nx + c0 + j] : 1.0;
+    ir[j] = rcp_nr(U[j][0]);
   }
+  // own cells 0, 1 into slots 0, 1 and cells CPT-2, CPT-1 into slots 2, 3;
+  // the wavefront's first two and last two cells into edge set b
+  auto publish = [&](int b) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = k < 2 ? k : CPT - 4 + k;
+      if (j < 0 || j >= CPT) continue;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) SL[(k * RUN_SLOT + r) * RUN_TPB + tid] = U[j][r];
+      SL[(k * RUN_SLOT + 3) * RUN_TPB + tid] = ir[j];
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int q = c0 + j - wfirst;
+      const int slot = q < 2 ? q : (q >= 64 * CPT - 2 ? q - (64 * CPT - 4) : -1);
+      if (slot >= 0) {
+        double* e = EX + ((b * RUN_WAVES + wv) * 4 + slot) * RUN_SLOT;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) e[r] = U[j][r];
+        e[3] = ir[j];
+      }
+    }
+  };
+  publish(0);
+  __syncthreads();
   const double dts_dx = (G.dt / s) / G.dx;
   bool phys = true;
   for (int i = 0; i < s; ++i) {
+    const int b = i & 1;
+    if (i > 0) {
+      double m[RUN_WAVES];
+#pragma unroll
+      for (int q = 0; q < RUN_WAVES; ++q) m[q] = WM[b * RUN_WAVES + q];
+#pragma unroll
+      for (int h = RUN_WAVES / 2; h >= 1; h /= 2)
+#pragma unroll
+        for (int q = 0; q < h; ++q) m[q] = fmax(m[q], m[q + h]);
+      alpha = m[0];
+    }
+    // split fluxes of an entry from U and 1/rho
+    auto entry = [&](const double* Uq, double irq, double* w) {
+      double F[3];
+      (void)flux1(Uq, irq, F);
+      wsplit(Uq, F, alpha, w);
+    };
+    auto own_entry = [&](int j, double* w) {
+      double F[3];
+      const bool ph = flux1(U[j], ir[j], F);
+      phys &= ph || c0 + j >= Nx;
+      wsplit(U[j], F, alpha, w);
+    };
+    // a neighbour's cell: from its slot k in the thread nb lanes away, or,
+    // past the wavefront's end, from edge slot es of wavefront ew
+    auto remote_entry = [&](int k, int nb, bool edge, int ew, int es, double* w) {
+      const double* src = edge ? EX + ((b * RUN_WAVES + ew) * 4 + es) * RUN_SLOT
+                               : SL + k * RUN_SLOT * RUN_TPB + (tid + nb);
+      const int stride = edge ? 1 : RUN_TPB;
+      const double Uq[3] = {src[0], src[stride], src[2 * stride]};
+      entry(Uq, src[3 * stride], w);
+    };
+    // stencil entries k = 0 .. CPT + 3 are the cells c0 - 2 + k: the left
+    // pair from lane - 1's slots 2, 3 (lanes - 2 and - 1 when CPT = 1), the
+    // right pair from lane + 1's slots 0, 1 (lanes + 1 and + 2)
+    auto left_entry = [&](int e, double* w) {
+      const int dl = CPT >= 2 ? 1 : 2 - e;
+      const bool edge = lane < dl;
+      remote_entry(CPT >= 2 ? 2 + e : 0, edge ? 0 : -dl, edge, max(wv - 1, 0),
+                   4 + (c0 - 2 + e - wfirst), w);
+    };
+    auto right_entry = [&](int e, double* w) {
+      const int dr = CPT >= 2 ? 1 : 1 + e;
+      const bool edge = lane >= 64 - dr;
+      remote_entry(CPT >= 2 ? e : 0, edge ? 0 : dr, edge, min(wv + 1, RUN_WAVES - 1),
+                   c0 + CPT + e - (wfirst + 64 * CPT), w);
+    };
+    // window of face 0: entries 0 .. 3
+    double W0[6], W1[6], W2[6], W3[6];
+    own_entry(0, W2);
+    left_entry(1, W1);
+    left_entry(0, W0);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      W1[q] = c0 - 1 < 0 ? W2[q] : W1[q];
+      W0[q] = c0 - 2 < 0 ? W1[q] : W0[q];
+    }
+    if (CPT >= 2)
+      own_entry(CPT >= 2 ? 1 : 0, W3);
+    else
+      right_entry(0, W3);
+    if (c0 + 1 >= Nx) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) W3[q] = W2[q];
+    }
+    double fprev[3];
+    face4(W0, W1, W2, W3, fprev);
+#pragma unroll
+    for (int j = 1; j <= CPT; ++j) {
+      // entry j + 3 (cell c0 + j + 1) enters the window
+      double Wn[6];
+      const int k = j + 3;
+      if (k - 2 < CPT)
+        own_entry(k - 2 < CPT ? k - 2 : 0, Wn);
+      else
+        right_entry(k - 2 - CPT, Wn);
+      const bool past = c0 + j + 1 >= Nx;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        W0[q] = W1[q];
+        W1[q] = W2[q];
+        W2[q] = W3[q];
+        W3[q] = past ? W2[q] : Wn[q];
+      }
+      double fc[3];
+      face4(W0, W1, W2, W3, fc);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) U[j - 1][r] = fma(-dts_dx, fc[r] - fprev[r], U[j - 1][r]);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) fprev[r] = fc[r];
+    }
+    if (i + 1 == s) break;
+    // 1/rho and the speeds of the new values; slots, edge cells and
+    // wavefront maxima out, then the block barrier
     double mx = 0.0;
 #pragma unroll
-    for (int k = 0; k < EUL_CPT; ++k) {
-      if (k >= nslab) break;
-      double* Wl = (k & 1) ? Wl1 : Wl0;
-      double* Pl = (k & 1) ? Pl1 : Pl0;
-      const int x0 = k * EUL_TPB;
-      const int end = min(x0 + EUL_TPB, Nx);
-      const int nent = end - x0 + 4;  // flux entries of cells x0-2 .. end+1
-      // entries written by this thread: those whose (clamped) cell it owns,
-      // among its cells of slabs k-1, k and k+1
-#pragma unroll
-      for (int dk = -1; dk <= 1; ++dk) {
-        const int kk = k + dk;
-        if (kk < 0 || kk >= EUL_CPT) continue;
-        const int c = kk * EUL_TPB + tid;
-        if (c >= Nx) continue;
-        int qlo = c - x0 + 2, qhi = qlo;
-        if (c == 0) qlo = 0;
-        if (c == Nx - 1) qhi = nent - 1;
-        qlo = max(qlo, 0);
-        qhi = min(qhi, nent - 1);
-        if (qlo > qhi) continue;
-        double Wp[3], Wm[3];
-        if (k > 0 && (dk < 0 || (dk == 0 && tid < 2))) {
-          // cells x0-2, x0-1, x0 and x0+1: this thread formed their split
-          // fluxes in the previous slab's pass, in the other set of entries
-          const double* Wq = ((k & 1) ? Wl0 : Wl1) + (c - x0 + EUL_TPB + 2) * 6;
-#pragma unroll
-          for (int r = 0; r < 3; ++r) {
-            Wp[r] = Wq[r];
-            Wm[r] = Wq[3 + r];
-          }
-        } else {
-          phys &= split_flux<1>(Ur[kk], 0, alpha, G.gam, Wp, Wm);
-        }
-        for (int q = qlo; q <= qhi; ++q) {
-#pragma unroll
-          for (int r = 0; r < 3; ++r) {
-            Wl[q * 6 + r] = Wp[r];
-            Wl[q * 6 + 3 + r] = Wm[r];
-          }
-        }
-        if (k == 0 && c == 0) {
-          // the tube's left face: entries 0..2 all hold cell 0, so both
-          // limited slopes vanish and the flux is the mean of W+ and W- of
-          // cell 0 (the value the face loop below would give)
-#pragma unroll
-          for (int r = 0; r < 3; ++r) Pl[r] = 0.5 * (Wp[r] + Wm[r]) + 0.25 * (0.0 - 0.0);
-        }
-      }
-      __syncthreads();
-      // face f between cells x0+f-1 and x0+f uses entries f .. f+3; face 0
-      // of a later slab is the previous slab's last face, kept in the other
-      // set, so the 1024 threads form the at most 1024 remaining faces at once
-      for (int f = tid + 1; f <= end - x0; f += blockDim.x) {
-        const double* w = Wl + f * 6;
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          const double spl = vl_slope(w[6 + r] - w[r], w[12 + r] - w[6 + r], 0);
-          const double sml = vl_slope(w[15 + r] - w[9 + r], w[21 + r] - w[15 + r], 0);
-          Pl[f * 3 + r] = 0.5 * (w[6 + r] + w[15 + r]) + 0.25 * (spl - sml);
-        }
-      }
-      __syncthreads();
-      if (x0 + tid < Nx) {
-        const double* Pleft = (tid == 0 && k > 0) ? ((k & 1) ? Pl0 : Pl1) + EUL_TPB * 3 : Pl + tid * 3;
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-          Un[k][r] = Ur[k][r] - dts_dx * (Pl[(tid + 1) * 3 + r] - Pleft[r]);
-        if (i + 1 < s) {
-          double sp;
-          phys &= lf_speeds<1>(Un[k], G.gam, &sp);
-          mx = fmax(mx, sp);
-        }
+    for (int j = 0; j < CPT; ++j) {
+      ir[j] = rcp_nr(U[j][0]);
+      double sp;
+      const bool ps = speed1(U[j], ir[j], G.gam, &sp);
+      if (c0 + j < Nx) {
+        phys &= ps;
+        mx = fmax(mx, sp);
       }
     }
-#pragma unroll
-    for (int k = 0; k < EUL_CPT; ++k)
-#pragma unroll
-      for (int r = 0; r < 3; ++r) Ur[k][r] = Un[k][r];
-    if (i + 1 < s) alpha = block_max_1024(mx, red);
+    publish(b ^ 1);
+    const double wm = wave_max_dpp(mx);
+    if (lane == 0) WM[(b ^ 1) * RUN_WAVES + wv] = wm;
+    __syncthreads();
   }
   double* out = a.dar + ((s & 1) ? T.UE[1] : T.UE[0]);
 #pragma unroll
-  for (int k = 0; k < EUL_CPT; ++k) {
-    const int c = k * EUL_TPB + tid;
+  for (int j = 0; j < CPT; ++j) {
+    const int c = c0 + j;
     if (c < Nx) {
 #pragma unroll
-      for (int r = 0; r < 3; ++r) out[(size_t)r * Nx + c] = Ur[k][r];
+      for (int r = 0; r < 3; ++r) out[(size_t)r * Nx + c] = U[j][r];
     }
+  }
+  if (!phys) atomicOr(a.tflag + t, FLAG_NONPHYS);
+}
+
+// Euler solve of one part of a tube, cells c0 .. c1-1 with c0 = part * PC
+// and PC = part_cells (1024 or 2048): thread t owns cells c0 + t and
+// c0 + 1024 + t, whose moments stay in registers for all s sub-steps.  Per
+// sub-step the owners write the split fluxes W+- of their cells into LDS (one
+// array per component; the tube's boundary cells also fill the clamped
+// outflow entries), four threads write those of the two cells beyond each
+// end of the part (held by the neighbouring parts), the faces c0 .. c1 are
+// formed once each, and the owners update their cells.  Between sub-steps a
+// part publishes its first two and last two cells and the largest speed of
+// its cells in the tube's exchange row of the sub-step's parity; after the
+// barrier of the tube's parts every part reads its halo cells and the speeds
+// of all parts, so all parts take the same alpha (a maximum is exact in any
+// order).  A face shared by two parts is formed by both from the same values
+// with the same arithmetic, as in the whole-tube forms.  Two exchange rows
+// suffice: a part overwrites a row only after passing the barrier that
+// follows every part's reads of it.  The parts of a tube are consecutive
+// blocks of the Euler launch, which start in block order, and a tube has at
+// most PART_MAX parts, fewer than the compute units: only the tube of the
+// last started block can be waiting for a part not yet started, and the
+// other blocks finish and free a compute unit for it.
+constexpr int XSTR = 16;       // doubles per part in an exchange row: 4 cells x 3, speed
+constexpr int PART_MAX = 64;   // parts per tube at most
+__host__ __device__ constexpr size_t part_lds(int pc) {
+  return (size_t)(6 * (pc + 4) + 3 * (pc + 1)) * sizeof(double);
+}
+
+__device__ void batch_euler_part(const BatchArgs& a, int t, int part, int P, double* L,
+                                 double* red) {
+  t = __builtin_amdgcn_readfirstlane(t);
+  part = __builtin_amdgcn_readfirstlane(part);
+  P = __builtin_amdgcn_readfirstlane(P);
+  const TubeDev T = a.tubes[t];
+  const Geom G = tube_geom(T);
+  const int p = a.parity;
+  double alpha = __hip_atomic_load(a.alpha + ((size_t)t * 2 + p) * ASTR, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+  bool over;
+  const int s = substeps<1>(&alpha, G, a.s_cap, &over);
+  if (part == 0 && threadIdx.x == 0) {
+    // the update launch reduces the speeds of U^{n+1} into the other row
+    a.alpha[((size_t)t * 2 + (p ^ 1)) * ASTR] = 0.0;
+    a.tube_s[t] = s;
+    a.ebar[2 * t + (p ^ 1)] = 0u;  // the next step's barriers
+    if (over) atomicOr(a.tflag + t, FLAG_SUBSTEP);
+  }
+  if (G.mu == 0.0) return;
+  const int Nx = G.nc, PC = a.part_cells;
+  const int c0 = part * PC, c1 = min(c0 + PC, Nx), n = c1 - c0;
+  const int WS = PC + 4, FS = PC + 1;
+  double* Wl = L;           // [6][WS]: W+ (3), W- (3) of cells c0-2 .. c1+1
+  double* Pl = L + 6 * WS;  // [3][FS]: faces c0 .. c1
+  const int tid = threadIdx.x;
+  const double* U0 = a.dar + (p ? T.U[1] : T.U[0]);
+  double Ur[2][3];
+  bool own[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int c = c0 + k * 1024 + tid;
+    own[k] = k * 1024 < PC && c < c1;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) Ur[k][r] = own[k] ? U0[(size_t)r * Nx + c] : 0.0;
+  }
+  // halo entries: thread e < 4 fills entry q_h (0, 1, n + 2, n + 3), cell
+  // c0 - 2 + q_h clamped to the tube, when that cell lies outside the part:
+  // the last two cells of part - 1 (slots 2, 3) or the first two of part + 1
+  // (slots 0, 1; slot 0 when the clamp folds c1 + 1 onto c1)
+  const int q_h = tid < 2 ? tid : n + tid;
+  const int c_h = min(max(c0 - 2 + q_h, 0), Nx - 1);
+  const bool halo = tid < 4 && (c_h < c0 || c_h >= c1);
+  const int h_part = c_h < c0 ? part - 1 : part + 1;
+  const int h_slot = c_h < c0 ? 3 - (c0 - 1 - c_h) : c_h - c1;
+  double Uh[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) Uh[r] = halo ? U0[(size_t)r * Nx + c_h] : 0.0;
+  const double dts_dx = (G.dt / s) / G.dx;
+  const int nw = (int)(blockDim.x >> 6);
+  bool phys = true;
+  for (int i = 0; i < s; ++i) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (!own[k]) continue;
+      const int c = c0 + k * 1024 + tid;
+      double F[3], w[6];
+      phys &= flux1(Ur[k], rcp_nr(Ur[k][0]), F);
+      wsplit(Ur[k], F, alpha, w);
+      const double* Wp = w;
+      const double* Wm = w + 3;
+      int qlo = c - c0 + 2, qhi = qlo;
+      if (c == 0) qlo = 0;
+      if (c == Nx - 1) qhi = n + 3;
+      for (int q = qlo; q <= qhi; ++q) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          Wl[r * WS + q] = Wp[r];
+          Wl[(3 + r) * WS + q] = Wm[r];
+        }
+      }
+    }
+    if (halo) {
+      double F[3], w[6];
+      phys &= flux1(Uh, rcp_nr(Uh[0]), F);
+      wsplit(Uh, F, alpha, w);
+      const double* Wp = w;
+      const double* Wm = w + 3;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        Wl[r * WS + q_h] = Wp[r];
+        Wl[(3 + r) * WS + q_h] = Wm[r];
+      }
+    }
+    __syncthreads();
+    // face f between cells c0 + f - 1 and c0 + f from entries f .. f + 3
+    for (int f = tid; f <= n; f += blockDim.x) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const double* wp = Wl + r * WS + f;
+        const double* wm = Wl + (3 + r) * WS + f;
+        const double spl = vl_slope_sel(wp[1] - wp[0], wp[2] - wp[1]);
+        const double sml = vl_slope_sel(wm[2] - wm[1], wm[3] - wm[2]);
+        Pl[r * FS + f] = fma(0.25, spl - sml, 0.5 * (wp[1] + wm[2]));
+      }
+    }
+    __syncthreads();
+    double mx = 0.0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (!own[k]) continue;
+      const int j = k * 1024 + tid;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+        Ur[k][r] = fma(-dts_dx, Pl[r * FS + j + 1] - Pl[r * FS + j], Ur[k][r]);
+      if (i + 1 < s) {
+        double sp;
+        phys &= speed1(Ur[k], rcp_nr(Ur[k][0]), G.gam, &sp);
+        mx = fmax(mx, sp);
+      }
+    }
+    if (i + 1 == s) break;
+    double* row = a.dar + T.X + (size_t)((i & 1) * P) * XSTR;
+    if (P > 1) {
+      // publish the part's first two and last two cells
+      bool wrote = false;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        if (!own[k]) continue;
+        const int c = c0 + k * 1024 + tid;
+        if (c - c0 < 2) {
+#pragma unroll
+          for (int r = 0; r < 3; ++r) row[part * XSTR + (c - c0) * 3 + r] = Ur[k][r];
+          wrote = true;
+        }
+        if (c1 - 1 - c < 2) {
+#pragma unroll
+          for (int r = 0; r < 3; ++r) row[part * XSTR + (3 - (c1 - 1 - c)) * 3 + r] = Ur[k][r];
+          wrote = true;
+        }
+      }
+      if (wrote) __threadfence();
+    }
+    const double wmx = wave_max(mx);
+    if ((tid & 63) == 0) red[tid >> 6] = wmx;
+    __syncthreads();
+    if (P == 1) {
+      double m = red[0];
+      for (int q = 1; q < nw; ++q) m = fmax(m, red[q]);
+      alpha = m;
+    } else {
+      if (tid == 0) {
+        double m = red[0];
+        for (int q = 1; q < nw; ++q) m = fmax(m, red[q]);
+        row[part * XSTR + 12] = m;
+        __threadfence();
+        atomicAdd(a.ebar + 2 * t + p, 1u);
+        spin_until_geq(a.ebar + 2 * t + p, (unsigned)(P * (i + 1)), a.flag);
+        __threadfence();
+        double am = 0.0;
+        for (int q = 0; q < P; ++q)
+          am = fmax(am, __hip_atomic_load(row + q * XSTR + 12, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT));
+        red[16] = am;
+      }
+      __syncthreads();
+      alpha = red[16];
+      if (halo) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          Uh[r] = __hip_atomic_load(row + h_part * XSTR + h_slot * 3 + r, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+  double* out = a.dar + ((s & 1) ? T.UE[1] : T.UE[0]);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (!own[k]) continue;
+    const int c = c0 + k * 1024 + tid;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) out[(size_t)r * Nx + c] = Ur[k][r];
   }
   if (!phys) atomicOr(a.tflag + t, FLAG_NONPHYS);
 }
@@ -320,6 +689,7 @@ __device__ void batch_kinetic_item(const BatchArgs& a, int it, unsigned char* ld
   it = __builtin_amdgcn_readfirstlane(it);
   const int2 item = a.items[it];
   const int t = __builtin_amdgcn_readfirstlane(item.x);
+  if (t < 0) return;  // padding of a die's item list
   const TubeDev T = a.tubes[t];
   const Geom G = tube_geom(T);
   const int p = a.parity;
@@ -427,6 +797,7 @@ __device__ void batch_update_item(const BatchArgs& a, int it) {
   it = __builtin_amdgcn_readfirstlane(it);
   const int2 item = a.items[it];
   const int t = __builtin_amdgcn_readfirstlane(item.x);
+  if (t < 0) return;  // padding of a die's item list
   const TubeDev T = a.tubes[t];
   const Geom G = tube_geom(T);
   const int p = a.parity;
@@ -473,38 +844,40 @@ __device__ void batch_update_item(const BatchArgs& a, int it) {
   if ((threadIdx.x & 63) == 0) atomic_max_pos(a.alpha + ((size_t)t * 2 + (p ^ 1)) * ASTR, m);
 }
 
-// Step launch: persistent 1024-thread blocks pull work from one queue: the
-// Euler solves of the tubes first (most Euler work first), then the kinetic
-// items (relaxation, shift and moment sums of a (tube, segment), most work
-// first), which need nothing from the Euler solves.  (1024, 4): four waves
-// per SIMD.
-template <int CELLS, int UNR>
-__global__ __launch_bounds__(1024, 4) void k_batch_step(BatchArgs a) {
+// Euler launch: one 1024-thread block per Euler item (a whole tube or one
+// part of a split tube), most work first; it runs beside the kinetic
+// launch, on its own stream.
+__global__ __launch_bounds__(1024) void k_batch_euler(BatchArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-  __shared__ double red[16];
-  __shared__ int s_item;
-  const int p = a.parity;
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.queue[p ^ 1] = 0;  // for the next step
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) s_item = atomicAdd(a.queue + p, 1);
-    __syncthreads();
-    const int w = s_item;
-    if (w < a.ntubes) {
-      const int tb = a.euler_order[w];
-      if (a.tubes[tb].Nx <= EUL_TPB * EUL_CPT)
-        batch_euler_reg(a, tb, reinterpret_cast<double*>(lds_raw), red);
-      else
-        batch_euler_seg(a, tb, reinterpret_cast<double*>(lds_raw), red);
-    } else if (w < a.ntubes + a.nitems)
-      batch_kinetic_item<CELLS, UNR>(a, w - a.ntubes, lds_raw);
-    else
-      break;
-  }
+  __shared__ double red[32];
+  const int4 e = a.eitems[blockIdx.x];
+  double* L = reinterpret_cast<double*>(lds_raw);
+  const int nx = a.tubes[e.x].Nx;
+  if (e.w)
+    batch_euler_part(a, e.x, e.y, e.z, L, red);
+  else if (nx <= 1024)
+    batch_euler_run<1>(a, e.x, L);
+  else if (nx <= 2048)
+    batch_euler_run<2>(a, e.x, L);
+  else if (nx <= 3072)
+    batch_euler_run<3>(a, e.x, L);
+  else if (nx <= 4096)
+    batch_euler_run<4>(a, e.x, L);
+  else
+    batch_euler_seg(a, e.x, L, red);
+}
+
+// Kinetic launch: one 1024-thread block per kinetic item (relaxation, shift
+// and moment sums of a (tube, segment)), most work first; it needs nothing
+// from the Euler solves.
+template <int CELLS, int UNR>
+__global__ __launch_bounds__(1024) void k_batch_kinetic(BatchArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  batch_kinetic_item<CELLS, UNR>(a, blockIdx.x, lds_raw);
 }
 
 // Update launch: one block of CELLS threads per kinetic item.
-__global__ __launch_bounds__(512) void k_batch_update(BatchArgs a) {
+__global__ __launch_bounds__(1024) void k_batch_update(BatchArgs a) {
   batch_update_item(a, blockIdx.x);
 }
 

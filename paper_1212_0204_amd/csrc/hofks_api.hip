@@ -1360,27 +1360,29 @@ struct Batch {
   std::vector<double> taus;
   std::vector<TubeDev> tubes;
   long long g_floats = 0, r_floats = 0, d_doubles = 0;
-  int nvt = 0, items_max = 0;
+  int nvt = 0, items_max = 0, eitems_max = 0;
   long long total_cells = 0, total_cv = 0;
-  size_t off_gar = 0, off_rar = 0, off_dar = 0, off_vt = 0, off_tubes = 0, off_order = 0,
-         off_items = 0, off_queue = 0, off_alpha = 0, off_s = 0, off_tflag = 0,
-         off_flag = 0, total = 0;
+  size_t off_gar = 0, off_rar = 0, off_dar = 0, off_vt = 0, off_tubes = 0, off_eitems = 0,
+         off_items = 0, off_alpha = 0, off_s = 0, off_tflag = 0,
+         off_flag = 0, off_ebar = 0, total = 0;
   // device pointers
   float *gar = nullptr, *rar = nullptr;
   double *dar = nullptr, *alpha = nullptr;
   VelNode* vtar = nullptr;
   TubeDev* tubes_d = nullptr;
-  int *order = nullptr, *queue = nullptr, *tube_s = nullptr, *tflag = nullptr,
-      *flag = nullptr;
+  int *tube_s = nullptr, *tflag = nullptr, *flag = nullptr;
+  unsigned* ebar = nullptr;
+  int4* eitems = nullptr;
   int2* items = nullptr;
-  // launch configuration
-  int cells = 256, grid = 0, unr = 8, nitems = 0, ncu = 256;
+  // launch configuration; part = cells per part of a split Euler solve (0:
+  // every tube whole in one block)
+  int cells = 256, unr = 8, nitems = 0, neuler = 0, ncu = 256, part = 0;
   size_t lds = 0;
   // graph of GRAPH_STEPS launches starting at parity 0
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  int graph_cells = 0, graph_grid = 0;
+  int graph_cells = 0, graph_part = -1;
 };
 
 namespace {
@@ -1396,7 +1398,7 @@ hofks_status batch_plan(const hofks_grid_desc* descs, const double* taus, int n,
   if (taus) B->taus.assign(taus, taus + n);
   B->tubes.resize(n);
   long long go = 0, ro = 0, dof = 0;
-  int vto = 0, nitems = 0;
+  int vto = 0, nitems = 0, eitems = 0;
   constexpr int RS = rec_stride<1, float>();
   for (int i = 0; i < n; ++i) {
     const hofks_grid_desc& d = descs[i];
@@ -1424,7 +1426,8 @@ hofks_status batch_plan(const hofks_grid_desc* descs, const double* taus, int n,
     T.UE[1] = dof + 9 * Nx;
     T.cf = dof + 12 * Nx;
     T.S = dof + 15 * Nx;
-    dof += 21 * Nx;
+    T.X = dof + 21 * Nx;
+    dof += 21 * Nx + 2LL * XSTR * ((Nx + 1023) / 1024);
     T.vt = vto;
     vto += (int)nv;
     T.Nx = (int)Nx;
@@ -1446,7 +1449,8 @@ hofks_status batch_plan(const hofks_grid_desc* descs, const double* taus, int n,
       T.mu = -std::expm1(-T.dt / tau);
     }
     for (int q = 0; q < 9; ++q) T.A[q] = P.A.a[q];
-    nitems += (int)((Nx + 127) / 128);
+    nitems += (int)((Nx + 255) / 256);
+    eitems += (int)((Nx + 1023) / 1024);
     B->total_cells += Nx;
     B->total_cv += Nx * nv;
   }
@@ -1454,7 +1458,10 @@ hofks_status batch_plan(const hofks_grid_desc* descs, const double* taus, int n,
   B->r_floats = ro;
   B->d_doubles = dof;
   B->nvt = vto;
-  B->items_max = nitems;
+  // the die lists of the kinetic items are padded to equal length: at most
+  // NXCD entries per item
+  B->items_max = (int)NXCD * nitems;
+  B->eitems_max = eitems;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -1466,13 +1473,13 @@ hofks_status batch_plan(const hofks_grid_desc* descs, const double* taus, int n,
   B->off_dar = take(sizeof(double) * dof);
   B->off_vt = take(sizeof(VelNode) * vto);
   B->off_tubes = take(sizeof(TubeDev) * n);
-  B->off_order = take(sizeof(int) * n);
-  B->off_items = take(sizeof(int2) * nitems);
-  B->off_queue = take(64);
+  B->off_eitems = take(sizeof(int4) * eitems);
+  B->off_items = take(sizeof(int2) * B->items_max);
   B->off_alpha = take(sizeof(double) * n * 2 * ASTR);
   B->off_s = take(sizeof(int) * n);
   B->off_tflag = take(sizeof(int) * n);
   B->off_flag = take(64);
+  B->off_ebar = take(sizeof(unsigned) * 2 * n);
   B->total = off;
   return HOFKS_OK;
 }
@@ -1515,8 +1522,12 @@ size_t lds_for(const Batch* B, int cells) {
   return std::max(recb, redb);
 }
 
-// work order: Euler items by decreasing Nx * s, kinetic items by decreasing
-// per-item work (n_v), both on the host from the speeds of U^n
+// work order, on the host from the speeds of U^n: Euler items by decreasing
+// work per item (cells of the item times s; the parts of a split tube next
+// to each other), kinetic items by decreasing per-item work (n_v).  With
+// B->part > 0 a tube longer than part cells is split into ceil(Nx / part)
+// parts when that is at most PART_MAX and the compute units, else it stays
+// whole.
 hofks_status batch_order(hofks_ctx* c) {
   Batch* B = c->batch;
   std::vector<double> al((size_t)B->n * 2 * ASTR);
@@ -1525,24 +1536,56 @@ hofks_status batch_order(hofks_ctx* c) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const int p = (int)(c->steps & 1);
   std::vector<double> work(B->n);
+  std::vector<int> parts(B->n);
+  // the parts of a tube must be co-resident: at most one block per compute
+  // unit runs (the Euler tiles take most of the LDS)
+  const int pmax = std::min(PART_MAX, B->ncu);
   for (int i = 0; i < B->n; ++i) {
     const TubeDev& T = B->tubes[i];
     const double s = std::max(1.0, std::ceil(2.0 * T.dt * al[((size_t)i * 2 + p) * ASTR] / T.dx));
-    work[i] = (double)T.Nx * s;
+    const int np = B->part > 0 ? (T.Nx + B->part - 1) / B->part : 0;
+    parts[i] = (np >= 2 && np <= pmax) ? np : 0;
+    work[i] = (double)(parts[i] ? std::min(T.Nx, B->part) : T.Nx) * s;
   }
   std::vector<int> order(B->n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
-  std::vector<int2> items;
+  std::vector<int4> eitems;
   for (int i : order) {
-    const TubeDev& T = B->tubes[i];
-    for (int sg = 0; sg * B->cells < T.Nx; ++sg) items.push_back(make_int2(i, sg));
+    if (parts[i])
+      for (int k = 0; k < parts[i]; ++k) eitems.push_back(make_int4(i, k, parts[i], 1));
+    else
+      eitems.push_back(make_int4(i, 0, 1, 0));
   }
-  std::stable_sort(items.begin(), items.end(),
-                   [&](const int2& a, const int2& b) { return B->tubes[a.x].nv1 > B->tubes[b.x].nv1; });
+  // kinetic items: the tubes are dealt to the NXCD dies by kinetic work
+  // (largest first, each to the least loaded die), a die's list holds its
+  // tubes' segments in order, and block b of the kinetic launch takes entry
+  // b / NXCD of die b mod NXCD's list (blocks go to the dies round-robin), so
+  // neighbouring segments, whose upstream pieces and records overlap, meet
+  // in one L2.  Short lists are padded with empty items (tube -1).
+  std::vector<int> korder(B->n);
+  std::iota(korder.begin(), korder.end(), 0);
+  auto kwork = [&](int i) { return (double)B->tubes[i].Nx * B->tubes[i].nv1; };
+  std::stable_sort(korder.begin(), korder.end(), [&](int a, int b) { return kwork(a) > kwork(b); });
+  std::vector<std::vector<int2>> die(NXCD);
+  std::vector<double> load(NXCD, 0.0);
+  for (int i : korder) {
+    const int d = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    for (int sg = 0; sg * B->cells < B->tubes[i].Nx; ++sg) die[d].push_back(make_int2(i, sg));
+    load[d] += kwork(i);
+  }
+  size_t len = 0;
+  for (const auto& l : die) len = std::max(len, l.size());
+  std::vector<int2> items;
+  for (size_t q = 0; q < len; ++q)
+    for (unsigned d = 0; d < NXCD; ++d)
+      items.push_back(q < die[d].size() ? die[d][q] : make_int2(-1, 0));
+  if ((int)items.size() > B->items_max)
+    return fmt_err(c->err, "batch item list exceeds its workspace"), HOFKS_EINVAL;
   B->nitems = (int)items.size();
-  HIPCHK(c, hipMemcpyAsync(B->order, order.data(), sizeof(int) * B->n, hipMemcpyHostToDevice,
-                           c->stream));
+  B->neuler = (int)eitems.size();
+  HIPCHK(c, hipMemcpyAsync(B->eitems, eitems.data(), sizeof(int4) * eitems.size(),
+                           hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(B->items, items.data(), sizeof(int2) * items.size(),
                            hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1557,11 +1600,12 @@ BatchArgs batch_args(hofks_ctx* c, int parity) {
   a.dar = B->dar;
   a.vtar = B->vtar;
   a.tubes = B->tubes_d;
-  a.euler_order = B->order;
+  a.eitems = B->eitems;
   a.items = B->items;
-  a.ntubes = B->n;
+  a.neuler = B->neuler;
   a.nitems = B->nitems;
-  a.queue = B->queue;
+  a.part_cells = B->part > 0 ? B->part : 1024;
+  a.ebar = B->ebar;
   a.alpha = B->alpha;
   a.tube_s = B->tube_s;
   a.tflag = B->tflag;
@@ -1571,17 +1615,25 @@ BatchArgs batch_args(hofks_ctx* c, int parity) {
   return a;
 }
 
+size_t batch_euler_lds(const Batch* B) {
+  return std::max(std::max(RUN_LDS, EUL_LDS), B->part > 0 ? part_lds(B->part) : (size_t)0);
+}
+
+// one step: the Euler launch on `stream` and the kinetic launch on the
+// context's second stream, forked from and joined to `stream`, then the
+// update launch
 hofks_status batch_launch(hofks_ctx* c, hipStream_t stream, int parity) {
   Batch* B = c->batch;
   const BatchArgs a = batch_args(c, parity);
-  const dim3 grid(B->grid), block(1024);
-  const size_t lds = std::max(EUL_REG_LDS, B->lds);
+  HIPCHK(c, hipEventRecord(c->ev_fork, stream));
+  HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+  hipLaunchKernelGGL(k_batch_euler, dim3(B->neuler), dim3(1024), batch_euler_lds(B), stream, a);
 #define BL(CELLS, UNR) \
-  hipLaunchKernelGGL((k_batch_step<CELLS, UNR>), grid, block, lds, stream, a)
+  hipLaunchKernelGGL((k_batch_kinetic<CELLS, UNR>), dim3(B->nitems), dim3(1024), B->lds, c->aux, a)
   const int u = B->unr;
   switch (B->cells) {
-    case 128:
-      if (u == 8) BL(128, 8); else if (u == 4) BL(128, 4); else if (u == 2) BL(128, 2); else BL(128, 1);
+    case 1024:
+      if (u == 8) BL(1024, 8); else if (u == 4) BL(1024, 4); else if (u == 2) BL(1024, 2); else BL(1024, 1);
       break;
     case 512:
       if (u == 8) BL(512, 8); else if (u == 4) BL(512, 4); else if (u == 2) BL(512, 2); else BL(512, 1);
@@ -1589,24 +1641,27 @@ hofks_status batch_launch(hofks_ctx* c, hipStream_t stream, int parity) {
     default:
       if (u == 8) BL(256, 8); else if (u == 4) BL(256, 4); else if (u == 2) BL(256, 2); else BL(256, 1);
   }
-  hipLaunchKernelGGL(k_batch_update, dim3(B->nitems), dim3(B->cells), 0, stream, a);
 #undef BL
+  HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
+  HIPCHK(c, hipStreamWaitEvent(stream, c->ev_join, 0));
+  hipLaunchKernelGGL(k_batch_update, dim3(B->nitems), dim3(B->cells), 0, stream, a);
   HIPCHK(c, hipGetLastError());
   return HOFKS_OK;
 }
 
-hofks_status batch_configure(hofks_ctx* c, int cells, int grid) {
+hofks_status batch_configure(hofks_ctx* c, int cells, int part) {
   Batch* B = c->batch;
   B->cells = cells;
+  B->part = part;
   B->unr = unroll_for(B, cells);
   B->lds = lds_for(B, cells);
-  B->grid = grid > 0 ? grid : B->ncu;
   return batch_order(c);
 }
 
 hofks_status batch_capture(hofks_ctx* c) {
   Batch* B = c->batch;
-  if (B->gexec && B->graph_cells == B->cells && B->graph_grid == B->grid) return HOFKS_OK;
+  if (B->gexec && B->graph_cells == B->cells && B->graph_part == B->part)
+    return HOFKS_OK;
   if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
   B->gexec = nullptr;
@@ -1624,7 +1679,7 @@ hofks_status batch_capture(hofks_ctx* c) {
   HIPCHK(c, hipStreamEndCapture(B->cap, &B->graph));
   HIPCHK(c, hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
   B->graph_cells = B->cells;
-  B->graph_grid = B->grid;
+  B->graph_part = B->part;
   return HOFKS_OK;
 }
 
@@ -1693,7 +1748,7 @@ hofks_status batch_set_state(hofks_ctx* c, const double* rho, const double* u,
   if (st) return st;
   st = zero_ints(c, B->tflag, B->n);
   if (st) return st;
-  st = zero_ints(c, B->queue, 16);
+  st = zero_ints(c, reinterpret_cast<int*>(B->ebar), 2 * B->n);
   if (st) return st;
   st = zero_doubles(c, B->alpha, (size_t)B->n * 2 * ASTR);
   if (st) return st;
@@ -1887,33 +1942,33 @@ hofks_status hofks_batch_create(const hofks_grid_desc* descs, const double* taus
   B->dar = (double*)(c->ws + B->off_dar);
   B->vtar = (VelNode*)(c->ws + B->off_vt);
   B->tubes_d = (TubeDev*)(c->ws + B->off_tubes);
-  B->order = (int*)(c->ws + B->off_order);
+  B->eitems = (int4*)(c->ws + B->off_eitems);
   B->items = (int2*)(c->ws + B->off_items);
-  B->queue = (int*)(c->ws + B->off_queue);
   B->alpha = (double*)(c->ws + B->off_alpha);
   B->tube_s = (int*)(c->ws + B->off_s);
   B->tflag = (int*)(c->ws + B->off_tflag);
   B->flag = (int*)(c->ws + B->off_flag);
+  B->ebar = (unsigned*)(c->ws + B->off_ebar);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&B->ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     B->ncu = 256;
-  // the segmented Euler tiles take more than the default 64 KB of LDS
+  // the Euler tiles take more than the default 64 KB of LDS
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_euler),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024) !=
+      hipSuccess) {
+    delete B;
+    delete c;
+    return HOFKS_EDEVICE;
+  }
   {
-    const void* fns[] = {
-        reinterpret_cast<const void*>(&k_batch_step<128, 8>), reinterpret_cast<const void*>(&k_batch_step<128, 4>),
-        reinterpret_cast<const void*>(&k_batch_step<128, 2>), reinterpret_cast<const void*>(&k_batch_step<128, 1>),
-        reinterpret_cast<const void*>(&k_batch_step<256, 8>), reinterpret_cast<const void*>(&k_batch_step<256, 4>),
-        reinterpret_cast<const void*>(&k_batch_step<256, 2>), reinterpret_cast<const void*>(&k_batch_step<256, 1>),
-        reinterpret_cast<const void*>(&k_batch_step<512, 8>), reinterpret_cast<const void*>(&k_batch_step<512, 4>),
-        reinterpret_cast<const void*>(&k_batch_step<512, 2>), reinterpret_cast<const void*>(&k_batch_step<512, 1>)};
-    for (const void* f : fns)
-      if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024) !=
-          hipSuccess) {
-        delete B;
-        delete c;
-        return HOFKS_EDEVICE;
-      }
+    constexpr unsigned evf = hipEventDisableTiming | hipEventDisableSystemFence;
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, evf) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, evf) != hipSuccess) {
+      hofks_destroy(c);
+      return HOFKS_EDEVICE;
+    }
   }
   std::vector<VelNode> tab;
   tab.reserve(B->nvt);
@@ -1927,14 +1982,12 @@ hofks_status hofks_batch_create(const hofks_grid_desc* descs, const double* taus
       hipMemcpyAsync(B->tubes_d, B->tubes.data(), sizeof(TubeDev) * B->n, hipMemcpyHostToDevice,
                      c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
-    delete B;
-    delete c;
+    hofks_destroy(c);
     return HOFKS_EDEVICE;
   }
   B->cells = 512;
   B->unr = unroll_for(B, 512);
   B->lds = lds_for(B, 512);
-  B->grid = B->ncu;
   *out = c;
   return HOFKS_OK;
 }
@@ -1947,10 +2000,6 @@ hofks_status hofks_batch_tube_flags(hofks_ctx* c, int* flags) {
   return HOFKS_OK;
 }
 
-// Pick the item width (cells per kinetic item) and the persistent grid by
-// timing `steps` steps of each candidate on the current state (which is
-// advanced).  With a cache file, a matching line is reused without timing;
-// otherwise the result is appended.
 hofks_status hofks_set_launch_config(hofks_ctx* c, int wavefronts, int loads, int euler_before) {
   if (!c || c->batch || euler_before < 0 || euler_before > 1) return HOFKS_EINVAL;
   const Plan& P = c->P;
@@ -1966,77 +2015,105 @@ hofks_status hofks_set_launch_config(hofks_ctx* c, int wavefronts, int loads, in
   return HOFKS_OK;
 }
 
+hofks_status hofks_batch_set_launch_config(hofks_ctx* c, int cells, int euler_part) {
+  if (!c || !c->batch || !c->ready) return HOFKS_EINVAL;
+  if ((cells != 256 && cells != 512 && cells != 1024) ||
+      (euler_part != 0 && euler_part != 1024 && euler_part != 2048))
+    return fmt_err(c->err, "launch configuration not available for a batch"), HOFKS_EINVAL;
+  return batch_configure(c, cells, euler_part);
+}
+
+// Batch: pick the item width (cells per kinetic item), then the part size of
+// the split Euler solves, by timing `steps` steps of each candidate on the
+// current state (which is advanced).  With a cache file, a matching line is
+// reused without timing; otherwise the result is appended.
 hofks_status hofks_autotune(hofks_ctx* c, int steps, const char* cache_path, int* choice) {
   if (!c || !c->ready || steps < 1) return HOFKS_EINVAL;
   if (!c->batch) return grid_autotune(c, steps, cache_path, choice);
   Batch* B = c->batch;
   std::ostringstream key;
-  key << "gfx950:batch:n=" << B->n << ":cells=" << B->total_cells << ":cv=" << B->total_cv
+  key << "gfx950:batch2:n=" << B->n << ":cells=" << B->total_cells << ":cv=" << B->total_cv
       << ":ncu=" << B->ncu;
-  int best_cells = 0, best_grid = 0;
+  int best_cells = 0, best_part = 0;
   if (cache_path && *cache_path) {
     std::ifstream in(cache_path);
     std::string line;
     while (std::getline(in, line)) {
       const std::string k = "\"key\": \"" + key.str() + "\"";
       if (line.find(k) == std::string::npos) continue;
-      int cc = 0, gg = 0;
-      const size_t pc = line.find("\"cells\": "), pg = line.find("\"grid\": ");
-      if (pc != std::string::npos && pg != std::string::npos) {
+      int cc = 0, pp = -1;
+      const size_t pc = line.find("\"cells\": "), pe = line.find("\"euler_part\": ");
+      if (pc != std::string::npos && pe != std::string::npos) {
         cc = std::atoi(line.c_str() + pc + 9);
-        gg = std::atoi(line.c_str() + pg + 8);
+        pp = std::atoi(line.c_str() + pe + 14);
       }
-      if ((cc == 128 || cc == 256 || cc == 512) && gg > 0) {
+      if ((cc == 256 || cc == 512 || cc == 1024) && (pp == 0 || pp == 1024 || pp == 2048)) {
         best_cells = cc;
-        best_grid = gg;
+        best_part = pp;
       }
     }
   }
   if (!best_cells) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hofks_status st = HOFKS_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+      st = hip_fail(c, hipErrorOutOfMemory, "hipEventCreate");
+    // times one candidate: a warm-up step, then `steps` steps
+    auto time_cfg = [&](int cells, int part, float* ms) -> hofks_status {
+      hofks_status r = batch_configure(c, cells, part);
+      if (!r) r = batch_step(c, 1, false);
+      if (r) return r;
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+      r = batch_step(c, steps, false);
+      if (r) return r;
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      HIPCHK(c, hipEventSynchronize(e1));
+      HIPCHK(c, hipEventElapsedTime(ms, e0, e1));
+      return HOFKS_OK;
+    };
     // the state evolves while the candidates run, so every candidate is
     // timed in two rounds and keeps its better time
+    const int ccand[3] = {256, 512, 1024}, pcand[3] = {0, 1024, 2048};
+    float cms[3] = {1e30f, 1e30f, 1e30f}, pms[3] = {1e30f, 1e30f, 1e30f};
     float best_ms = 1e30f;
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
-    const int cand[6][2] = {{128, 1}, {128, 2}, {256, 1}, {256, 2}, {512, 1}, {512, 2}};
-    float cms[6] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
-    for (int round = 0; round < 2; ++round) {
-      for (int k = 0; k < 6; ++k) {
-        const int cells = cand[k][0], grid = B->ncu * cand[k][1];
-        hofks_status st = batch_configure(c, cells, grid);
-        if (st) return st;
-        st = batch_step(c, 1, false);  // warm-up
-        if (st) return st;
-        HIPCHK(c, hipEventRecord(e0, c->stream));
-        st = batch_step(c, steps, false);
-        if (st) return st;
-        HIPCHK(c, hipEventRecord(e1, c->stream));
-        HIPCHK(c, hipEventSynchronize(e1));
+    for (int round = 0; round < 2 && !st; ++round)
+      for (int k = 0; k < 3 && !st; ++k) {
         float ms = 0.0f;
-        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        st = time_cfg(ccand[k], best_part, &ms);
         cms[k] = std::min(cms[k], ms);
       }
-    }
-    for (int k = 0; k < 6; ++k)
+    for (int k = 0; k < 3; ++k)
       if (cms[k] < best_ms) {
         best_ms = cms[k];
-        best_cells = cand[k][0];
-        best_grid = B->ncu * cand[k][1];
+        best_cells = ccand[k];
       }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (int round = 0; round < 2 && !st; ++round)
+      for (int k = 0; k < 3 && !st; ++k) {
+        float ms = 0.0f;
+        st = time_cfg(best_cells, pcand[k], &ms);
+        pms[k] = std::min(pms[k], ms);
+      }
+    best_ms = 1e30f;
+    for (int k = 0; k < 3; ++k)
+      if (pms[k] < best_ms) {
+        best_ms = pms[k];
+        best_part = pcand[k];
+      }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) return st;
     if (cache_path && *cache_path) {
       std::ofstream o(cache_path, std::ios::app);
       o << "{\"key\": \"" << key.str() << "\", \"cells\": " << best_cells
-        << ", \"grid\": " << best_grid << ", \"ms_per_step\": " << best_ms / steps << "}\n";
+        << ", \"euler_part\": " << best_part << ", \"ms_per_step\": " << best_ms / steps
+        << "}\n";
     }
   }
-  hofks_status st = batch_configure(c, best_cells, best_grid);
+  hofks_status st = batch_configure(c, best_cells, best_part);
   if (st) return st;
   if (choice) {
     choice[0] = best_cells;
-    choice[1] = best_grid;
+    choice[1] = best_part;
     choice[2] = 0;
   }
   return batch_read_flag(c);

@@ -169,7 +169,7 @@ class Solver:
         """time the candidate launch configurations (advances the state: set
         it again afterwards); returns the chosen (wavefronts, loads ahead,
         Euler solve before the kinetic kernel) for a grid, (cells per item,
-        blocks, 0) for a batch"""
+        cells per Euler part, 0) for a batch"""
         ch = (ctypes.c_int * 3)()
         cp = cache_path.encode() if cache_path else None
         self._check(_lib.lib().hofks_autotune(self._h, int(steps), cp, ch), "autotune")
@@ -270,6 +270,12 @@ class Batch(Solver):
             out.append(f[o:o + nx * nv].reshape(nv, nx))
             o += nx * nv
         return out
+
+    def set_launch_config(self, cells, euler_part):
+        """a batch launch configuration without timing (see
+        hofks_batch_set_launch_config)"""
+        self._check(_lib.lib().hofks_batch_set_launch_config(self._h, int(cells), int(euler_part)),
+                    "batch_set_launch_config")
 
     def tube_flags(self):
         fl = (ctypes.c_int * len(self.tubes))()

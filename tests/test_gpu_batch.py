@@ -84,10 +84,10 @@ def test_autotuned_configuration_matches_oracle(tmp_path):
     fields = tube_fields(tubes)
     b.set_state_macro(*fields)
     cache = str(tmp_path / "tune.jsonl")
-    cells, grid, _ = b.autotune(steps=3, cache_path=cache)
-    assert cells in (128, 256, 512) and grid > 0
+    cells, part, _ = b.autotune(steps=3, cache_path=cache)
+    assert cells in (256, 512, 1024) and part in (0, 1024, 2048)
     # the cached choice is reused without timing
-    assert b.autotune(steps=3, cache_path=cache) == (cells, grid, 0)
+    assert b.autotune(steps=3, cache_path=cache) == (cells, part, 0)
     b.set_state_macro(*fields)
     b.step(10)
     for t, U in zip(tubes, b.read_moments()):
@@ -123,10 +123,10 @@ def test_full_batch_sampled_tubes():
 
 @gpu
 def test_long_tubes_match_oracle():
-    """long tubes: up to 4096 cells the Euler solve keeps four cells per
-    thread in registers (slabs of 1024 cells, ragged last slab), beyond it
-    runs by segments through memory; all of them, and a short tube beside
-    them, against the oracle after 12 single steps"""
+    """long tubes, each tube's Euler solve whole in one block: up to 4096
+    cells with every cell in registers (ceil(Nx / 1024) consecutive cells per
+    thread), beyond that by segments through memory; all of them, and a
+    short tube beside them, against the oracle after 12 single steps"""
     rng = np.random.default_rng(11)
     tubes = []
     for nx in (2049, 3001, 4096, 5000, 8192, 9000, 300):
@@ -139,6 +139,7 @@ def test_long_tubes_match_oracle():
     announce("long tubes", [t.nx for t in tubes])
     b = make_batch(tubes)
     b.set_state_macro(*tube_fields(tubes))
+    b.set_launch_config(512, 0)  # every tube whole in one block
     b.step(12)
     assert (b.tube_flags() == 0).all()
     for t, U in zip(tubes, b.read_moments()):
@@ -147,24 +148,27 @@ def test_long_tubes_match_oracle():
 
 
 @gpu
-def test_slab_edge_tubes_match_oracle():
-    """tube lengths at the edges of the 1024-cell slabs of the register form
-    of the Euler solve (one cell short of, exactly at and one cell past a
-    slab end): a slab's first face is carried over from the previous slab
-    and the split fluxes of the two cells on each side of a seam are reused,
-    so these lengths exercise every seam case"""
+def test_run_edge_tubes_match_oracle():
+    """tube lengths at the edges of the register form of the Euler solve,
+    which gives each thread ceil(Nx / 1024) consecutive cells: one cell
+    short of, exactly at and one cell past each change of the cells per
+    thread, a wavefront's end (64 cells at one cell per thread) and a tiny
+    tube, so that the last thread, the last wavefront and the stencil
+    entries taken from the neighbouring lanes and wavefronts meet every
+    ragged case"""
     rng = np.random.default_rng(23)
     tubes = []
-    for nx in (1023, 1024, 1025, 2047, 2048, 3072, 4095):
+    for nx in (5, 64, 65, 1023, 1024, 1025, 2047, 2048, 2049, 3071, 3072, 3073, 4095, 4096):
         nv = 32
         tau = float(10.0 ** rng.uniform(-3, -1))
         rl, pl, rr, pr = rng.uniform(0.5, 1.0, 4)
         th_max = max(pl / rl, pr / rr)
         dv = 2.0 ** np.ceil(np.log2(6.0 * np.sqrt(th_max) / (nv / 2)))
         tubes.append(W.Tube(nx, nv, float(dv), tau, (rl, 0.0, pl), (rr, 0.0, pr)))
-    announce("slab edge tubes", [t.nx for t in tubes])
+    announce("run edge tubes", [t.nx for t in tubes])
     b = make_batch(tubes)
     b.set_state_macro(*tube_fields(tubes))
+    b.set_launch_config(512, 0)  # every tube whole in one block
     b.step(12)
     assert (b.tube_flags() == 0).all()
     for t, U in zip(tubes, b.read_moments()):
@@ -227,3 +231,56 @@ def test_full_batch_flags_agree_with_oracle():
         print(f"tube {i}: gpu step {first[i]}, oracle step {oracle_first[i]}, nx {t.nx}, "
               f"nv {t.nv}, tau {t.tau:.2e}, dv/sqrt(theta_min) {res:.2f}", flush=True)
     assert len(diff) == 0
+
+
+def part_edge_tubes(seed):
+    """tube lengths at the edges of the 1024- and 2048-cell parts of the
+    split Euler solve: last parts of one, two and three cells (the right
+    halo folds onto the boundary cell), exact multiples, a single part one
+    cell short, and long tubes of five and nine parts"""
+    rng = np.random.default_rng(seed)
+    tubes = []
+    for nx in (1025, 1026, 1027, 2048, 2049, 2050, 3073, 4097, 6143, 9000, 700):
+        nv = 32
+        tau = float(10.0 ** rng.uniform(-3, -1))
+        rl, pl, rr, pr = rng.uniform(0.5, 1.0, 4)
+        th_max = max(pl / rl, pr / rr)
+        dv = 2.0 ** np.ceil(np.log2(6.0 * np.sqrt(th_max) / (nv / 2)))
+        tubes.append(W.Tube(nx, nv, float(dv), tau, (rl, 0.0, pl), (rr, 0.0, pr)))
+    return tubes
+
+
+@gpu
+def test_euler_parts_match_whole_tube_solve():
+    """the split Euler solve (parts of 1024 and 2048 cells meeting after
+    every sub-step) against the whole-tube forms on the same batch: the same
+    faces from the same values, so the moments agree bit for bit; and the
+    1024-cell split against the oracle"""
+    tubes = part_edge_tubes(31)
+    announce("euler parts", [t.nx for t in tubes])
+    fields = tube_fields(tubes)
+    res = {}
+    for part in (0, 2048, 1024):
+        b = make_batch(tubes)
+        b.set_state_macro(*fields)
+        b.set_launch_config(256, part)
+        b.step(20)
+        assert (b.tube_flags() == 0).all(), part
+        res[part] = b.read_moments()
+    for part in (2048, 1024):
+        for t, U0, U1 in zip(tubes, res[0], res[part]):
+            np.testing.assert_array_equal(U1, U0, err_msg=f"part {part}, nx {t.nx}")
+    for t, U in zip(tubes, res[1024]):
+        err = moment_errors(U, oracle_tube(t, 20).U, 1)
+        assert err.max() < TOL32, (t.nx, err)
+
+
+@gpu
+def test_batch_launch_config_rejects_unavailable_choices():
+    tubes = small_batch()[:2]
+    b = make_batch(tubes)
+    b.set_state_macro(*tube_fields(tubes))
+    from paper_1212_0204_amd.solver import HofksError
+    for args in ((100, 0), (256, 512), (256, 4096), (256, -1)):
+        with pytest.raises(HofksError):
+            b.set_launch_config(*args)

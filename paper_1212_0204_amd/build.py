@@ -6,7 +6,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "hofks_api.hip")
-HEADERS = [os.path.join(PKG, "csrc", h) for h in ("kernels.hpp", "batch.hpp", "closure.hpp", "mlp.hpp", "euler2d.hpp", "kinetic3d.hpp", "kinetic2w.hpp", "weno.hpp", "train.hpp", "probe.hpp")] + [
+HEADERS = [os.path.join(PKG, "csrc", h) for h in ("kernels.hpp", "batch.hpp", "closure.hpp", "mlp.hpp", "euler2d.hpp", "kinetic3d.hpp", "kinetic2w.hpp", "weno.hpp", "train.hpp", "probe.hpp", "slope.hpp")] + [
     os.path.join(ROOT, "include", "hofks.h")]
 LIB = os.path.join(PKG, "libhofks.so")
 

@@ -9,6 +9,7 @@
 // next records cell by cell.
 #pragma once
 #include "kernels.hpp"
+#include "slope.hpp"
 
 namespace hofks {
 
@@ -150,20 +151,6 @@ __device__ __forceinline__ void wsplit(const double* U, const double* F, double 
     w[r] = fma(alpha, U[r], F[r]);
     w[3 + r] = fma(-alpha, U[r], F[r]);
   }
-}
-
-// vl_slope without a branch: the same quotient, selected when ab > 0 (the
-// divergent branch of vl_slope keeps values live across it and serialises
-// the six slopes of a face)
-__device__ __forceinline__ double vl_slope_sel(double a, double b) {
-  const double ab = a * b;
-  const double den = a + b;
-  double r = __builtin_amdgcn_rcp(den);
-  r = fma(fma(-den, r, 1.0), r, r);
-  r = fma(fma(-den, r, 1.0), r, r);
-  const double q = 2.0 * ab * r;
-  const double v = fma(fma(-den, q, 2.0 * ab), r, q);
-  return ab > 0.0 ? v : 0.0;
 }
 
 // face flux between the cells of entries 1 and 2 of a four-entry window

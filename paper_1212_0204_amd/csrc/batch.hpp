@@ -33,7 +33,8 @@ struct BatchArgs {
   double* dar;            // moment arena
   const VelNode* vtar;    // velocity node arena
   const TubeDev* tubes;
-  const int4* eitems;     // Euler items (tube, part, parts, split), most work first
+  const int4* eitems;     // Euler items, most work first: (tube, 0, 0, 0) whole,
+                          // (tube, part, parts, 1) one part, (tube, tube or -1, CPT, 2) a pair
   const int2* items;      // kinetic items (tube, segment) dealt to the dies; tube -1: none
   int neuler, nitems;
   int part_cells;         // cells per part of a split Euler solve (1024 or 2048)
@@ -256,62 +257,79 @@ __device__ void batch_euler_seg(const BatchArgs& a, int t, double* L, double* re
   if (!phys) atomicOr(a.tflag + t, FLAG_NONPHYS);
 }
 
-// Euler solve of one tube of at most 1024 * CPT cells with every cell's
-// moments (and 1/rho) in registers for all s sub-steps: thread t owns the
-// CPT consecutive cells t CPT .. t CPT + CPT - 1, so the four-cell stencil of
-// a face reaches at most two cells into each neighbouring thread.  After
-// every sub-step a thread leaves U and 1/rho of its first two and last two
-// cells in its LDS slots, which the neighbouring lanes of its wavefront read
-// during the next sub-step (a wavefront's LDS operations complete in order,
-// so no barrier is needed between lanes of one wavefront); at the ends of a
-// wavefront the cells come from the edge set that each wavefront leaves for
-// its neighbours (one set per sub-step parity, so the one block barrier per
-// sub-step, which also publishes the wavefront speed maxima that make
-// alpha, orders them).  A thread forms the split fluxes of each stencil
-// entry as it enters a four-entry window, the left faces of its cells and
-// the right face of its last cell (which its right neighbour forms too,
-// from the same values with the same arithmetic), and updates its cells.
-// Outflow ends: entries before cell 0 repeat cell 0, those past cell
-// Nx - 1 repeat cell Nx - 1.
-constexpr int RUN_WAVES = 16;
-constexpr int RUN_TPB = 64 * RUN_WAVES;
+// Euler solve of one tube of at most NT * CPT cells with every cell's
+// moments (and 1/rho) in registers for all s sub-steps, by NT threads of
+// the block: thread t of the group owns the CPT consecutive cells
+// t CPT .. t CPT + CPT - 1, so a face stencil reaches at most two cells into
+// each neighbouring thread.  After every sub-step a thread leaves U and 1/rho
+// of its first two and last two cells in its LDS slots, which the
+// neighbouring lanes of its wavefront read during the next sub-step (a
+// wavefront's LDS operations complete in order, so lanes of one wavefront
+// need no barrier); at the ends of a wavefront the cells come from the edge
+// set that each wavefront leaves for its neighbours (one set per sub-step
+// parity, so one block barrier per sub-step suffices, which also publishes
+// the wavefront speed maxima that make alpha).  A thread forms the split
+// fluxes of each stencil entry as it enters a four-entry window, the left
+// faces of its cells and the right face of its last cell (which its right
+// neighbour forms too, from the same values with the same arithmetic), and
+// updates its cells.  Outflow ends: entries before cell 0 repeat cell 0,
+// those past cell Nx - 1 repeat cell Nx - 1.
+//
+// With NT = 512 the two halves of the block solve two tubes (t0, t1; t1 may
+// be -1) side by side: the solve is bound by the latency of its
+// per-sub-step dependency chain, so two tubes on one compute unit overlap
+// their chains.  Each half has its own LDS region and alpha; the block
+// barrier is shared, so the block runs max(s0, s1) sub-steps and a half
+// that is done only keeps meeting the barrier.
 constexpr int RUN_SLOT = 4;  // doubles per exchanged cell: U, 1/rho
-// LDS of the run form: per-thread slots [4 cells][RUN_SLOT][RUN_TPB], the
-// wavefront edge sets [2][RUN_WAVES][4 cells][RUN_SLOT] and the wavefront
-// speed maxima [2][RUN_WAVES]
-constexpr int RUN_SL = 4 * RUN_SLOT * RUN_TPB;
-constexpr int RUN_EX = 2 * RUN_WAVES * 4 * RUN_SLOT;
-constexpr size_t RUN_LDS = (size_t)(RUN_SL + RUN_EX + 2 * RUN_WAVES) * sizeof(double);
+// LDS of one group of NT threads: per-thread slots [4 cells][RUN_SLOT][NT],
+// the wavefront edge sets [2][NT/64][4 cells][RUN_SLOT] and the wavefront
+// speed maxima [2][NT/64]
+__host__ __device__ constexpr int run_lds_group(int nt) {
+  return 4 * RUN_SLOT * nt + 2 * (nt / 64) * 4 * RUN_SLOT + 2 * (nt / 64);
+}
+constexpr size_t RUN_LDS = (size_t)(2 * run_lds_group(512)) * sizeof(double);
+static_assert(run_lds_group(1024) <= 2 * run_lds_group(512), "one 1024-thread group fits");
 
-template <int CPT>
-__device__ void batch_euler_run(const BatchArgs& a, int t, double* L) {
+template <int CPT, int NT>
+__device__ void batch_euler_run(const BatchArgs& a, int t0, int t1, double* Lall) {
+  constexpr int WAVES = NT / 64;
+  __shared__ int s_grp[2];
+  const int grp = (int)threadIdx.x / NT;
+  const int tid = (int)threadIdx.x % NT, lane = tid & 63, wv = tid >> 6;
+  int t = grp == 0 ? t0 : t1;
   t = __builtin_amdgcn_readfirstlane(t);
-  const TubeDev T = a.tubes[t];
+  const TubeDev T = a.tubes[t < 0 ? t0 : t];
   const Geom G = tube_geom(T);
   const int p = a.parity;
-  double alpha = __hip_atomic_load(a.alpha + ((size_t)t * 2 + p) * ASTR, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-  bool over;
-  const int s = substeps<1>(&alpha, G, a.s_cap, &over);
-  if (threadIdx.x == 0) {
+  double alpha = t < 0 ? 0.0
+                       : __hip_atomic_load(a.alpha + ((size_t)t * 2 + p) * ASTR,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  bool over = false;
+  const int s_sub = t < 0 ? 0 : substeps<1>(&alpha, G, a.s_cap, &over);
+  if (tid == 0 && t >= 0) {
     // the update launch reduces the speeds of U^{n+1} into the other row
     a.alpha[((size_t)t * 2 + (p ^ 1)) * ASTR] = 0.0;
-    a.tube_s[t] = s;
+    a.tube_s[t] = s_sub;
     if (over) atomicOr(a.tflag + t, FLAG_SUBSTEP);
   }
-  if (G.mu == 0.0) return;
+  const int s = (t < 0 || G.mu == 0.0) ? 0 : s_sub;  // sub-steps this group runs
+  if (tid == 0) s_grp[grp] = s;
+  __syncthreads();
+  const int smax = NT == 1024 ? s : max(s_grp[0], s_grp[1]);
+  if (smax == 0) return;
   const int Nx = G.nc;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int c0 = tid * CPT;          // first cell of the thread
   const int wfirst = wv * 64 * CPT;  // first cell of the wavefront
-  double* SL = L;                    // [4][RUN_SLOT][RUN_TPB]
-  double* EX = L + RUN_SL;           // [2][RUN_WAVES][4][RUN_SLOT]
-  double* WM = L + RUN_SL + RUN_EX;  // [2][RUN_WAVES]
+  double* L = Lall + (size_t)grp * run_lds_group(NT);
+  double* SL = L;                          // [4][RUN_SLOT][NT]
+  double* EX = L + 4 * RUN_SLOT * NT;      // [2][WAVES][4][RUN_SLOT]
+  double* WM = EX + 2 * WAVES * 4 * RUN_SLOT;  // [2][WAVES]
   const double* U0 = a.dar + (p ? T.U[1] : T.U[0]);
   double U[CPT][3], ir[CPT];
 #pragma unroll
   for (int j = 0; j < CPT; ++j) {
-    const bool ok = c0 + j < Nx;  // idle cells hold a finite placeholder
+    const bool ok = s > 0 && c0 + j < Nx;  // idle cells hold a finite placeholder
 #pragma unroll
     for (int r = 0; r < 3; ++r) U[j][r] = ok ? U0[(size_t)r * Nx + c0 + j] : 1.0;
     ir[j] = rcp_nr(U[j][0]);
@@ -324,136 +342,140 @@ __device__ void batch_euler_run(const BatchArgs& a, int t, double* L) {
       const int j = k < 2 ? k : CPT - 4 + k;
       if (j < 0 || j >= CPT) continue;
 #pragma unroll
-      for (int r = 0; r < 3; ++r) SL[(k * RUN_SLOT + r) * RUN_TPB + tid] = U[j][r];
-      SL[(k * RUN_SLOT + 3) * RUN_TPB + tid] = ir[j];
+      for (int r = 0; r < 3; ++r) SL[(k * RUN_SLOT + r) * NT + tid] = U[j][r];
+      SL[(k * RUN_SLOT + 3) * NT + tid] = ir[j];
     }
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
       const int q = c0 + j - wfirst;
       const int slot = q < 2 ? q : (q >= 64 * CPT - 2 ? q - (64 * CPT - 4) : -1);
       if (slot >= 0) {
-        double* e = EX + ((b * RUN_WAVES + wv) * 4 + slot) * RUN_SLOT;
+        double* e = EX + ((b * WAVES + wv) * 4 + slot) * RUN_SLOT;
 #pragma unroll
         for (int r = 0; r < 3; ++r) e[r] = U[j][r];
         e[3] = ir[j];
       }
     }
   };
-  publish(0);
+  if (s > 0) publish(0);
   __syncthreads();
-  const double dts_dx = (G.dt / s) / G.dx;
+  const double dts_dx = s > 0 ? (G.dt / s) / G.dx : 0.0;
   bool phys = true;
-  for (int i = 0; i < s; ++i) {
+  for (int i = 0; i < smax; ++i) {
     const int b = i & 1;
-    if (i > 0) {
-      double m[RUN_WAVES];
+    if (i < s) {
+      if (i > 0) {
+        double m[WAVES];
 #pragma unroll
-      for (int q = 0; q < RUN_WAVES; ++q) m[q] = WM[b * RUN_WAVES + q];
+        for (int q = 0; q < WAVES; ++q) m[q] = WM[b * WAVES + q];
 #pragma unroll
-      for (int h = RUN_WAVES / 2; h >= 1; h /= 2)
+        for (int h = WAVES / 2; h >= 1; h /= 2)
 #pragma unroll
-        for (int q = 0; q < h; ++q) m[q] = fmax(m[q], m[q + h]);
-      alpha = m[0];
-    }
-    // split fluxes of an entry from U and 1/rho
-    auto entry = [&](const double* Uq, double irq, double* w) {
-      double F[3];
-      (void)flux1(Uq, irq, F);
-      wsplit(Uq, F, alpha, w);
-    };
-    auto own_entry = [&](int j, double* w) {
-      double F[3];
-      const bool ph = flux1(U[j], ir[j], F);
-      phys &= ph || c0 + j >= Nx;
-      wsplit(U[j], F, alpha, w);
-    };
-    // a neighbour's cell: from its slot k in the thread nb lanes away, or,
-    // past the wavefront's end, from edge slot es of wavefront ew
-    auto remote_entry = [&](int k, int nb, bool edge, int ew, int es, double* w) {
-      const double* src = edge ? EX + ((b * RUN_WAVES + ew) * 4 + es) * RUN_SLOT
-                               : SL + k * RUN_SLOT * RUN_TPB + (tid + nb);
-      const int stride = edge ? 1 : RUN_TPB;
-      const double Uq[3] = {src[0], src[stride], src[2 * stride]};
-      entry(Uq, src[3 * stride], w);
-    };
-    // stencil entries k = 0 .. CPT + 3 are the cells c0 - 2 + k: the left
-    // pair from lane - 1's slots 2, 3 (lanes - 2 and - 1 when CPT = 1), the
-    // right pair from lane + 1's slots 0, 1 (lanes + 1 and + 2)
-    auto left_entry = [&](int e, double* w) {
-      const int dl = CPT >= 2 ? 1 : 2 - e;
-      const bool edge = lane < dl;
-      remote_entry(CPT >= 2 ? 2 + e : 0, edge ? 0 : -dl, edge, max(wv - 1, 0),
-                   4 + (c0 - 2 + e - wfirst), w);
-    };
-    auto right_entry = [&](int e, double* w) {
-      const int dr = CPT >= 2 ? 1 : 1 + e;
-      const bool edge = lane >= 64 - dr;
-      remote_entry(CPT >= 2 ? e : 0, edge ? 0 : dr, edge, min(wv + 1, RUN_WAVES - 1),
-                   c0 + CPT + e - (wfirst + 64 * CPT), w);
-    };
-    // window of face 0: entries 0 .. 3
-    double W0[6], W1[6], W2[6], W3[6];
-    own_entry(0, W2);
-    left_entry(1, W1);
-    left_entry(0, W0);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      W1[q] = c0 - 1 < 0 ? W2[q] : W1[q];
-      W0[q] = c0 - 2 < 0 ? W1[q] : W0[q];
-    }
-    if (CPT >= 2)
-      own_entry(CPT >= 2 ? 1 : 0, W3);
-    else
-      right_entry(0, W3);
-    if (c0 + 1 >= Nx) {
-#pragma unroll
-      for (int q = 0; q < 6; ++q) W3[q] = W2[q];
-    }
-    double fprev[3];
-    face4(W0, W1, W2, W3, fprev);
-#pragma unroll
-    for (int j = 1; j <= CPT; ++j) {
-      // entry j + 3 (cell c0 + j + 1) enters the window
-      double Wn[6];
-      const int k = j + 3;
-      if (k - 2 < CPT)
-        own_entry(k - 2 < CPT ? k - 2 : 0, Wn);
-      else
-        right_entry(k - 2 - CPT, Wn);
-      const bool past = c0 + j + 1 >= Nx;
+          for (int q = 0; q < h; ++q) m[q] = fmax(m[q], m[q + h]);
+        alpha = m[0];
+      }
+      // split fluxes of an entry from U and 1/rho
+      auto entry = [&](const double* Uq, double irq, double* w) {
+        double F[3];
+        (void)flux1(Uq, irq, F);
+        wsplit(Uq, F, alpha, w);
+      };
+      auto own_entry = [&](int j, double* w) {
+        double F[3];
+        const bool ph = flux1(U[j], ir[j], F);
+        phys &= ph || c0 + j >= Nx;
+        wsplit(U[j], F, alpha, w);
+      };
+      // a neighbour's cell: from its slot k in the thread nb lanes away, or,
+      // past the wavefront's end, from edge slot es of wavefront ew
+      auto remote_entry = [&](int k, int nb, bool edge, int ew, int es, double* w) {
+        const double* src = edge ? EX + ((b * WAVES + ew) * 4 + es) * RUN_SLOT
+                                 : SL + k * RUN_SLOT * NT + (tid + nb);
+        const int stride = edge ? 1 : NT;
+        const double Uq[3] = {src[0], src[stride], src[2 * stride]};
+        entry(Uq, src[3 * stride], w);
+      };
+      // stencil entries k = 0 .. CPT + 3 are the cells c0 - 2 + k: the left
+      // pair from lane - 1's slots 2, 3 (lanes - 2 and - 1 when CPT = 1), the
+      // right pair from lane + 1's slots 0, 1 (lanes + 1 and + 2)
+      auto left_entry = [&](int e, double* w) {
+        const int dl = CPT >= 2 ? 1 : 2 - e;
+        const bool edge = lane < dl;
+        remote_entry(CPT >= 2 ? 2 + e : 0, edge ? 0 : -dl, edge, max(wv - 1, 0),
+                     4 + (c0 - 2 + e - wfirst), w);
+      };
+      auto right_entry = [&](int e, double* w) {
+        const int dr = CPT >= 2 ? 1 : 1 + e;
+        const bool edge = lane >= 64 - dr;
+        remote_entry(CPT >= 2 ? e : 0, edge ? 0 : dr, edge, min(wv + 1, WAVES - 1),
+                     c0 + CPT + e - (wfirst + 64 * CPT), w);
+      };
+      // window of face 0: entries 0 .. 3
+      double W0[6], W1[6], W2[6], W3[6];
+      own_entry(0, W2);
+      left_entry(1, W1);
+      left_entry(0, W0);
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
-        W0[q] = W1[q];
-        W1[q] = W2[q];
-        W2[q] = W3[q];
-        W3[q] = past ? W2[q] : Wn[q];
+        W1[q] = c0 - 1 < 0 ? W2[q] : W1[q];
+        W0[q] = c0 - 2 < 0 ? W1[q] : W0[q];
       }
-      double fc[3];
-      face4(W0, W1, W2, W3, fc);
+      if (CPT >= 2)
+        own_entry(CPT >= 2 ? 1 : 0, W3);
+      else
+        right_entry(0, W3);
+      if (c0 + 1 >= Nx) {
 #pragma unroll
-      for (int r = 0; r < 3; ++r) U[j - 1][r] = fma(-dts_dx, fc[r] - fprev[r], U[j - 1][r]);
+        for (int q = 0; q < 6; ++q) W3[q] = W2[q];
+      }
+      double fprev[3];
+      face4(W0, W1, W2, W3, fprev);
 #pragma unroll
-      for (int r = 0; r < 3; ++r) fprev[r] = fc[r];
-    }
-    if (i + 1 == s) break;
-    // 1/rho and the speeds of the new values; slots, edge cells and
-    // wavefront maxima out, then the block barrier
-    double mx = 0.0;
+      for (int j = 1; j <= CPT; ++j) {
+        // entry j + 3 (cell c0 + j + 1) enters the window
+        double Wn[6];
+        const int k = j + 3;
+        if (k - 2 < CPT)
+          own_entry(k - 2 < CPT ? k - 2 : 0, Wn);
+        else
+          right_entry(k - 2 - CPT, Wn);
+        const bool past = c0 + j + 1 >= Nx;
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-      ir[j] = rcp_nr(U[j][0]);
-      double sp;
-      const bool ps = speed1(U[j], ir[j], G.gam, &sp);
-      if (c0 + j < Nx) {
-        phys &= ps;
-        mx = fmax(mx, sp);
+        for (int q = 0; q < 6; ++q) {
+          W0[q] = W1[q];
+          W1[q] = W2[q];
+          W2[q] = W3[q];
+          W3[q] = past ? W2[q] : Wn[q];
+        }
+        double fc[3];
+        face4(W0, W1, W2, W3, fc);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) U[j - 1][r] = fma(-dts_dx, fc[r] - fprev[r], U[j - 1][r]);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) fprev[r] = fc[r];
+      }
+      if (i + 1 < s) {
+        // 1/rho and the speeds of the new values; slots, edge cells and
+        // wavefront maxima out before the block barrier
+        double mx = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+          ir[j] = rcp_nr(U[j][0]);
+          double sp;
+          const bool ps = speed1(U[j], ir[j], G.gam, &sp);
+          if (c0 + j < Nx) {
+            phys &= ps;
+            mx = fmax(mx, sp);
+          }
+        }
+        publish(b ^ 1);
+        const double wm = wave_max_dpp(mx);
+        if (lane == 0) WM[(b ^ 1) * WAVES + wv] = wm;
       }
     }
-    publish(b ^ 1);
-    const double wm = wave_max_dpp(mx);
-    if (lane == 0) WM[(b ^ 1) * RUN_WAVES + wv] = wm;
-    __syncthreads();
+    if (i + 1 < smax) __syncthreads();
   }
+  if (s == 0) return;
   double* out = a.dar + ((s & 1) ? T.UE[1] : T.UE[0]);
 #pragma unroll
   for (int j = 0; j < CPT; ++j) {
@@ -839,19 +861,30 @@ __global__ __launch_bounds__(1024) void k_batch_euler(BatchArgs a) {
   __shared__ double red[32];
   const int4 e = a.eitems[blockIdx.x];
   double* L = reinterpret_cast<double*>(lds_raw);
-  const int nx = a.tubes[e.x].Nx;
-  if (e.w)
+  if (e.w == 1) {
     batch_euler_part(a, e.x, e.y, e.z, L, red);
-  else if (nx <= 1024)
-    batch_euler_run<1>(a, e.x, L);
-  else if (nx <= 2048)
-    batch_euler_run<2>(a, e.x, L);
-  else if (nx <= 3072)
-    batch_euler_run<3>(a, e.x, L);
-  else if (nx <= 4096)
-    batch_euler_run<4>(a, e.x, L);
-  else
-    batch_euler_seg(a, e.x, L, red);
+  } else if (e.w == 2) {  // two tubes of at most 512 * e.z cells side by side
+    if (e.z == 1)
+      batch_euler_run<1, 512>(a, e.x, e.y, L);
+    else if (e.z == 2)
+      batch_euler_run<2, 512>(a, e.x, e.y, L);
+    else if (e.z == 3)
+      batch_euler_run<3, 512>(a, e.x, e.y, L);
+    else
+      batch_euler_run<4, 512>(a, e.x, e.y, L);
+  } else {
+    const int nx = a.tubes[e.x].Nx;
+    if (nx <= 1024)
+      batch_euler_run<1, 1024>(a, e.x, -1, L);
+    else if (nx <= 2048)
+      batch_euler_run<2, 1024>(a, e.x, -1, L);
+    else if (nx <= 3072)
+      batch_euler_run<3, 1024>(a, e.x, -1, L);
+    else if (nx <= 4096)
+      batch_euler_run<4, 1024>(a, e.x, -1, L);
+    else
+      batch_euler_seg(a, e.x, L, red);
+  }
 }
 
 // Kinetic launch: one 1024-thread block per kinetic item (relaxation, shift

@@ -1550,13 +1550,32 @@ hofks_status batch_order(hofks_ctx* c) {
   std::vector<int> order(B->n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
-  std::vector<int4> eitems;
+  // whole tubes of at most 2048 cells run two to a block (neighbours in the
+  // work order, so of similar work); the others one to a block or in parts
+  std::vector<std::pair<double, int4>> ew;
+  int pend = -1;
   for (int i : order) {
-    if (parts[i])
-      for (int k = 0; k < parts[i]; ++k) eitems.push_back(make_int4(i, k, parts[i], 1));
-    else
-      eitems.push_back(make_int4(i, 0, 1, 0));
+    if (parts[i]) {
+      for (int k = 0; k < parts[i]; ++k) ew.push_back({work[i], make_int4(i, k, parts[i], 1)});
+    } else if (B->tubes[i].Nx > 2 * 1024) {
+      ew.push_back({work[i], make_int4(i, 0, 0, 0)});
+    } else if (pend < 0) {
+      pend = i;
+    } else {
+      const int cpt = (std::max(B->tubes[pend].Nx, B->tubes[i].Nx) + 511) / 512;
+      ew.push_back({std::max(work[pend], work[i]), make_int4(pend, i, cpt, 2)});
+      pend = -1;
+    }
   }
+  if (pend >= 0) ew.push_back({work[pend], make_int4(pend, -1, (B->tubes[pend].Nx + 511) / 512, 2)});
+  std::stable_sort(ew.begin(), ew.end(),
+                   [](const std::pair<double, int4>& a, const std::pair<double, int4>& b) {
+                     return a.first > b.first;
+                   });
+  std::vector<int4> eitems;
+  for (const auto& w : ew) eitems.push_back(w.second);
+  if ((int)eitems.size() > B->eitems_max)
+    return fmt_err(c->err, "batch Euler item list exceeds its workspace"), HOFKS_EINVAL;
   // kinetic items: the tubes are dealt to the NXCD dies by kinetic work
   // (largest first, each to the least loaded die), a die's list holds its
   // tubes' segments in order, and block b of the kinetic launch takes entry

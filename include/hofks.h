@@ -171,9 +171,11 @@ void hofks_destroy(hofks_ctx *ctx);
 /* ------------------------------------------------------------- batches
  * Many independent 1D-1V tubes (dim 1, outflow, precision 1, scheme 0; n_vel
  * a multiple of 8), each with its own cells, dx, velocity grid, dt = dx/dv
- * and relaxation time, advanced together: one persistent launch per step
- * pulls per-tube Euler solves and per-segment kinetic work from a queue, and
- * hofks_step replays a captured graph of consecutive launches.  The same
+ * and relaxation time, advanced together: per step an Euler launch (one
+ * block per tube, two tubes of at most 2048 cells per block, or one block
+ * per part of a split tube) and a kinetic launch (one block per tube
+ * segment) run side by side on two streams, then a per-cell update launch;
+ * hofks_step replays a captured graph of consecutive steps.  The same
  * calls as above apply to a batch context with concatenated host arrays:
  *   hofks_set_state_macro  rho, u, theta of tube 0 cells, then tube 1, ...
  *   hofks_read_moments     per tube 3 x Nx_i (component-major), concatenated

@@ -207,8 +207,9 @@ class Solver:
 
 
 class Batch(Solver):
-    """Independent 1D-1V outflow tubes in FP32 pieces, advanced together (one
-    persistent launch per step, replayed from a captured graph).
+    """Independent 1D-1V outflow tubes in FP32 pieces, advanced together (an
+    Euler launch beside a kinetic launch, then an update launch, per step;
+    replayed from a captured graph).
 
     ``tubes``: sequence of (n_cells, dx, n_vel, dv, tau).  Host arrays are
     concatenated over tubes (see include/hofks.h)."""

@@ -1,4 +1,4 @@
-"""Batched persistent form on the GPU against the oracle, tube by tube.
+"""Batched form on the GPU against the oracle, tube by tube.
 
 Pieces are FP32 with FP64 compensated sums, so the bar is 1e-5 normwise on
 the moments of every tube.

@@ -106,6 +106,13 @@ def run_solver(wl, steps, warmup, precision, scheme=0, dt=None, strang=False):
         "kinetic_GBps": achieved,
         "kinetic_hbm_frac": achieved / HBM_PEAK_GBPS,
         "step_hbm_frac": bpcv * cv / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        # the kinetic launch of the step against the HBM roofline: one read
+        # and one write of every piece, over its average duration in the
+        # step (hipEvents around each launch on its stream)
+        "roofline": {"bound": "hbm", "kernel": "kinetic launch (relaxation, shift, moment sums)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "algorithmic_bytes_per_launch": bpcv * wl.cv},
         "tuned": {"wavefronts_per_block": tuned[0], "loads_ahead": tuned[1],
                   "euler_before_kinetic": bool(tuned[2])},
     }
@@ -156,6 +163,14 @@ def run_batch(steps, warmup):
            "steps": steps, "cv_per_s": cv_ok / (ms * 1e-3), "ms_per_step": ms / steps,
            "cv_per_s_incl_flagged_tubes": cv / (ms * 1e-3),
            "hbm_frac": 8 * cv_ok / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+           # the whole step (Euler and kinetic launches side by side, then the
+           # update) against the HBM roofline: the pieces' 8 B per
+           # cell-velocity over the step time, valid tubes only
+           "roofline": {"bound": "hbm", "kernel": "whole step (k_batch_euler beside k_batch_kinetic, "
+                                                  "then k_batch_update)",
+                        "achieved": 8 * cv_ok / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS,
+                        "unit": "GB/s", "frac": 8 * cv_ok / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                        "algorithmic_bytes_per_step": 8 * int((b.nx * b.nvs)[ok].sum())},
            "tuned": {"cells_per_item": tuned[0], "euler_part": tuned[1]},
            "flagged_tubes": flagged,
            # cold-side velocity resolution of each tube: dv / sqrt(theta_min)
@@ -490,6 +505,10 @@ def main():
         line["stream_probe"] = stream_probe(args.copy_probe_mb)
         line["roofline"]["frac_of_measured_copy"] = (
             prim["kinetic_GBps"] / line["stream_probe"]["copy_GBps"])
+        for f in forms.values():
+            if "roofline" in f:
+                f["roofline"]["frac_of_measured_copy"] = (
+                    f["roofline"]["achieved"] / line["stream_probe"]["copy_GBps"])
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)

@@ -155,13 +155,11 @@ def run_batch(steps, warmup):
     flags = b.tube_flags()
     flagged = int((flags != 0).sum())
     # throughput of the tubes whose results are valid: a tube that met a
-    # non-physical state keeps running but its work is not counted
+    # non-physical state is no longer advanced and none of its steps count
     ok = flags == 0
     cv_ok = int((b.nx * b.nvs)[ok].sum()) * steps
-    cv = b.ncv * steps
     out = {"workload": "batch512_tubes_seed4_fp32", "tubes": len(tubes), "cv_per_step": b.ncv,
            "steps": steps, "cv_per_s": cv_ok / (ms * 1e-3), "ms_per_step": ms / steps,
-           "cv_per_s_incl_flagged_tubes": cv / (ms * 1e-3),
            "hbm_frac": 8 * cv_ok / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
            # the whole step (Euler and kinetic launches side by side, then the
            # update) against the HBM roofline: the pieces' 8 B per

@@ -181,8 +181,10 @@ void hofks_destroy(hofks_ctx *ctx);
  *   hofks_read_moments     per tube 3 x Nx_i (component-major), concatenated
  *   hofks_read_f           per tube n_vel_i x Nx_i, concatenated
  * hofks_set_tau and hofks_set_state_f return HOFKS_EINVAL for a batch.  A
- * tube that meets a non-physical state is flagged and keeps running; its
- * flag is read with hofks_batch_tube_flags and the synchronising calls still
+ * tube that meets a non-physical state (or needs more Euler sub-steps than
+ * the cap) is flagged and from then on no longer advanced (its values are
+ * not meaningful; with split Euler solves its parts keep running); its flag
+ * is read with hofks_batch_tube_flags and the synchronising calls still
  * succeed, so the other tubes stay readable. */
 hofks_status hofks_batch_workspace_size(const hofks_grid_desc *descs, int n,
                                         size_t *bytes);

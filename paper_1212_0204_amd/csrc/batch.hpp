@@ -180,6 +180,7 @@ constexpr size_t EUL_LDS = (size_t)((EUL_TPB + 4) * 6 + (EUL_TPB + 1) * 3) * siz
 
 __device__ void batch_euler_seg(const BatchArgs& a, int t, double* L, double* red) {
   t = __builtin_amdgcn_readfirstlane(t);
+  if (a.tflag[t] != 0) return;  // a flagged tube is no longer advanced
   const TubeDev T = a.tubes[t];
   const Geom G = tube_geom(T);
   const int p = a.parity;
@@ -193,7 +194,7 @@ __device__ void batch_euler_seg(const BatchArgs& a, int t, double* L, double* re
     a.tube_s[t] = s;
     if (over) atomicOr(a.tflag + t, FLAG_SUBSTEP);
   }
-  if (G.mu == 0.0) return;
+  if (G.mu == 0.0 || over) return;  // over the cap: flagged, not solved
   const int Nx = G.nc;
   double* Wl = L;                           // [EUL_TPB + 4][6]: W+ (3), W- (3)
   double* Pl = L + (EUL_TPB + 4) * 6;       // [EUL_TPB + 1][3]: face fluxes
@@ -299,6 +300,7 @@ __device__ void batch_euler_run(const BatchArgs& a, int t0, int t1, double* Lall
   const int tid = (int)threadIdx.x % NT, lane = tid & 63, wv = tid >> 6;
   int t = grp == 0 ? t0 : t1;
   t = __builtin_amdgcn_readfirstlane(t);
+  if (t >= 0 && a.tflag[t] != 0) t = -1;  // a flagged tube is no longer advanced
   const TubeDev T = a.tubes[t < 0 ? t0 : t];
   const Geom G = tube_geom(T);
   const int p = a.parity;
@@ -313,7 +315,8 @@ __device__ void batch_euler_run(const BatchArgs& a, int t0, int t1, double* Lall
     a.tube_s[t] = s_sub;
     if (over) atomicOr(a.tflag + t, FLAG_SUBSTEP);
   }
-  const int s = (t < 0 || G.mu == 0.0) ? 0 : s_sub;  // sub-steps this group runs
+  // sub-steps this group runs (none over the cap: flagged, not solved)
+  const int s = (t < 0 || G.mu == 0.0 || over) ? 0 : s_sub;
   if (tid == 0) s_grp[grp] = s;
   __syncthreads();
   const int smax = NT == 1024 ? s : max(s_grp[0], s_grp[1]);
@@ -533,7 +536,7 @@ __device__ void batch_euler_part(const BatchArgs& a, int t, int part, int P, dou
     a.ebar[2 * t + (p ^ 1)] = 0u;  // the next step's barriers
     if (over) atomicOr(a.tflag + t, FLAG_SUBSTEP);
   }
-  if (G.mu == 0.0) return;
+  if (G.mu == 0.0 || over) return;  // every part sees the same alpha and s
   const int Nx = G.nc, PC = a.part_cells;
   const int c0 = part * PC, c1 = min(c0 + PC, Nx), n = c1 - c0;
   const int WS = PC + 4, FS = PC + 1;
@@ -699,6 +702,7 @@ __device__ void batch_kinetic_item(const BatchArgs& a, int it, unsigned char* ld
   const int2 item = a.items[it];
   const int t = __builtin_amdgcn_readfirstlane(item.x);
   if (t < 0) return;  // padding of a die's item list
+  if (a.tflag[t] != 0) return;  // a flagged tube is no longer advanced
   const TubeDev T = a.tubes[t];
   const Geom G = tube_geom(T);
   const int p = a.parity;
@@ -807,6 +811,7 @@ __device__ void batch_update_item(const BatchArgs& a, int it) {
   const int2 item = a.items[it];
   const int t = __builtin_amdgcn_readfirstlane(item.x);
   if (t < 0) return;  // padding of a die's item list
+  if (a.tflag[t] != 0) return;  // a flagged tube is no longer advanced
   const TubeDev T = a.tubes[t];
   const Geom G = tube_geom(T);
   const int p = a.parity;

@@ -2181,12 +2181,18 @@ hofks_status batch_read_f(hofks_ctx* c, double* f, size_t bytes) {
   return batch_read_flag(c);
 }
 
+// largest sub-step count of the last step over the tubes that are not flagged
 hofks_status batch_max_substeps(hofks_ctx* c, int* out) {
-  std::vector<int> ts(c->batch->n);
+  std::vector<int> ts(c->batch->n), tf(c->batch->n);
   HIPCHK(c, hipMemcpyAsync(ts.data(), c->batch->tube_s, sizeof(int) * ts.size(),
                            hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(tf.data(), c->batch->tflag, sizeof(int) * tf.size(),
+                           hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  *out = *std::max_element(ts.begin(), ts.end());
+  int m = 0;
+  for (size_t i = 0; i < ts.size(); ++i)
+    if (!tf[i]) m = std::max(m, ts[i]);
+  *out = m;
   return HOFKS_OK;
 }
 

@@ -42,6 +42,9 @@ class Solver:
     def __init__(self, dim, n_cells, dx, n_vel, dv, bc=None, precision=0, scheme=0,
                  tau=math.inf, stream=None, dt=None, strang=False):
         L = _lib.lib()
+        # held here so that close() still works while the interpreter tears
+        # down module globals
+        self._destroy = L.hofks_destroy
         if not torch.cuda.is_available():
             raise RuntimeError("the HOFKS library needs a ROCm GPU")
         n = (list(n_cells) + [1, 1, 1])[:3]
@@ -77,7 +80,7 @@ class Solver:
     def close(self):
         h = getattr(self, "_h", None)
         if h:
-            _lib.lib().hofks_destroy(h)
+            self._destroy(h)
             self._h = None
 
     def __del__(self):
@@ -216,6 +219,9 @@ class Batch(Solver):
 
     def __init__(self, tubes, stream=None):
         L = _lib.lib()
+        # held here so that close() still works while the interpreter tears
+        # down module globals
+        self._destroy = L.hofks_destroy
         if not torch.cuda.is_available():
             raise RuntimeError("the HOFKS library needs a ROCm GPU")
         n = len(tubes)

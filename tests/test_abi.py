@@ -84,3 +84,37 @@ def test_offlattice_needs_nvel_multiple_of_4_in_2d():
     d.dt = 0.5 * (1 / 16) / 0.5
     st, _ = ws(d)
     assert st == 0
+
+
+def batch_ws(descs):
+    from paper_1212_0204_amd import _lib
+    arr = (_lib.GridDesc * max(1, len(descs)))(*descs)
+    sz = ctypes.c_size_t(0)
+    st = _lib.lib().hofks_batch_workspace_size(arr, len(descs), ctypes.byref(sz))
+    return st, sz.value
+
+
+def tube_desc(nx=100, nv=32, dv=0.25, **kw):
+    d = dict(dim=1, n=(nx, 1, 1), dx=1.0 / nx, nv=nv, dv=dv, bc=(1, 0, 0), precision=1, scheme=0)
+    d.update(kw)
+    return desc(**d)
+
+
+def test_batch_workspace_of_the_512_tubes():
+    """two FP32 piece buffers of every tube, plus moments, records and lists"""
+    import workloads as W
+    tubes = W.batched_tubes()
+    st, b = batch_ws([tube_desc(t.nx, t.nv, t.dv) for t in tubes])
+    ncv = sum(t.nx * t.nv for t in tubes)
+    assert st == 0 and 2 * ncv * 4 <= b < 1.5 * 2 * ncv * 4
+
+
+@pytest.mark.parametrize("kw", [dict(dim=2, n=(16, 16, 1)), dict(precision=0), dict(bc=(0, 0, 0)),
+                                dict(scheme=1), dict(nv=12), dict(nv=4)])
+def test_bad_batch_tubes_are_rejected(kw):
+    """batches hold 1D outflow FP32 HOFKS tubes with n_vel a multiple of 8;
+    one bad tube rejects the batch"""
+    st, _ = batch_ws([tube_desc(), tube_desc(**kw)])
+    assert st == -1
+    st, _ = batch_ws([])
+    assert st == -1

@@ -22,7 +22,10 @@ __global__ __launch_bounds__(256) void k_euler_sub_tile(StepArgs<T> a, Geom G, i
   constexpr int NM = 4;
   double* S = a.set_r;
   const int Nx = G.n[0], Ny = G.n[1];
-  const int X0 = (int)(blockIdx.x % ntx) * ET, Y0 = (int)(blockIdx.x / ntx) * ET;
+  // contiguous ranges of tiles per die (blocks reach the dies round-robin),
+  // so that the halo of most tiles was written on the same die
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int X0 = (tile % ntx) * ET, Y0 = (tile / ntx) * ET;
   const int t = threadIdx.x;
   const double* in = (i == 0) ? a.U_in : ((i & 1) ? a.UE1 : a.UE0);
   double* out = ((i + 1) & 1) ? a.UE1 : a.UE0;
@@ -167,7 +170,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(64))) void k_eu
   constexpr int NM = 5;
   double* S = a.set_r;
   const int Nx = G.n[0], Ny = G.n[1], Nz = G.n[2];
-  const int tb = blockIdx.x;
+  const int tb = xcd_tile(blockIdx.x, gridDim.x);  // contiguous ranges of tiles per die
   const int X0 = (tb % ntx) * E3X, Y0 = ((tb / ntx) % nty) * E3Y, Z0 = (tb / ntx / nty) * E3Z;
   const int t = threadIdx.x;
   const double* in = (i == 0) ? a.U_in : ((i & 1) ? a.UE1 : a.UE0);

@@ -320,7 +320,9 @@ __global__ __launch_bounds__(256) void k_weno_stage_tile(StepArgs<T> a, Geom G, 
   constexpr int NM = 4;
   double* S = a.set_r;
   const int Nx = G.n[0], Ny = G.n[1];
-  const int X0 = (int)(blockIdx.x % ntx) * WT, Y0 = (int)(blockIdx.x / ntx) * WT;
+  // contiguous ranges of tiles per die, as the MUSCL tiles
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int X0 = (tile % ntx) * WT, Y0 = (tile / ntx) * WT;
   const int t = threadIdx.x;
   __shared__ double Vt[NM][WH * WH];        // stage input, tile + halo
   __shared__ double Hs[2][NM][WH * WT];     // split fluxes along one axis

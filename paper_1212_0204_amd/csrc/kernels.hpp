@@ -1172,11 +1172,14 @@ __global__ __launch_bounds__(64 * NG) void k_kinetic(StepArgs<T> a, Geom G, Mat 
 // (eqs. (UK), (mom), (minim_full)): delta = U_E - U_M, U^{n+1} = U_* + U_E,
 // cf = A delta, the next record and the speeds of U^{n+1}; in the closure
 // form also N^ for closure cells, the delta marks and the kinetic count.
+// The per-cell launches give each die a contiguous range of cells (blocks
+// reach the dies round-robin), as the kinetic and Euler tiles, so that most
+// of what a cell reads was written on its own die.
 template <int D, typename T, bool CLOS>
 __global__ __launch_bounds__(256) void k_cell_update(StepArgs<T> a, Geom G, Mat A) {
   constexpr int NM = D + 2;
   constexpr int RS = rec_stride<D, T>();
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
   const bool active = j < G.nc;
   const bool kin = !CLOS || (active && a.mode[j] != 0);
   bool phys = true;
@@ -1245,7 +1248,7 @@ __global__ __launch_bounds__(256) void k_cell_update(StepArgs<T> a, Geom G, Mat 
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_cell_update_u(StepArgs<T> a, Geom G, Mat A) {
   constexpr int NM = D + 2;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
   const bool active = j < G.nc;
   bool phys = true;
   double speed[3] = {0.0, 0.0, 0.0};
@@ -1299,7 +1302,7 @@ template <int D, typename T>
 __global__ __launch_bounds__(256) void k_cell_record(StepArgs<T> a, Geom G, Mat A) {
   constexpr int NM = D + 2;
   constexpr int RS = rec_stride<D, T>();
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
   if (j >= G.nc) return;
   double Un[NM], cfv[NM], speed[3];
 #pragma unroll

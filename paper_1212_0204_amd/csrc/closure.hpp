@@ -91,10 +91,10 @@ __global__ __launch_bounds__(64) void k_closure_center(const void* __restrict__ 
   const int lane = threadIdx.x & 63, q = lane >> 4;
   FwdW W;
   load_fwd(packed, W, lane);
-  s4 xf[3];
-#pragma unroll
-  for (int s = 0; s < 3; ++s)
-    xf[s] = pack4(f4{(s == 2 && q == 1) ? ftau : 0.0f, 0.0f, 0.0f, 0.0f});
+  // input 36 (element 4 of lane quarter 0 in the second K step) is the tau
+  // feature, the others zero
+  const s4 z = pack4(f4{0.0f, 0.0f, 0.0f, 0.0f});
+  const s8 xf[2] = {cat8(z, z), cat8(z, pack4(f4{q == 0 ? ftau : 0.0f, 0.0f, 0.0f, 0.0f}))};
   const f4 y = forward16<false>(W, biases(packed), xf, nullptr, lane);
   if (lane == 0) {
     y0[0] = y[0];
@@ -122,16 +122,23 @@ __global__ __launch_bounds__(256) void k_closure_mlp(ClosureArgs a, Geom G) {
     double pc[4];
     prim2(a.U, G.nc, jc, pc);
     const double cs = sqrt(G.gam * pc[3]);
-    s4 xf[3];
+    // K step s of lane quarter q: stencil cells 8 s + 2 q and 8 s + 2 q + 1
+    // (four inputs each; cell 9 is the tau feature, cells beyond are zero)
+    s8 xf[2];
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      const int c = 4 * s + q;  // stencil cell of this lane's four inputs
-      float v[4] = {0.f, 0.f, 0.f, 0.f};
-      if (c < 9)
-        stencil_inputs(a.U, G, x, y, c, pc, cs, v);
-      else if (c == 9)
-        v[0] = a.ftau;
-      xf[s] = pack4(f4{v[0], v[1], v[2], v[3]});
+    for (int s = 0; s < 2; ++s) {
+      s4 half[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = 8 * s + 2 * q + h;
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+        if (c < 9)
+          stencil_inputs(a.U, G, x, y, c, pc, cs, v);
+        else if (c == 9)
+          v[0] = a.ftau;
+        half[h] = pack4(f4{v[0], v[1], v[2], v[3]});
+      }
+      xf[s] = cat8(half[0], half[1]);
     }
     f4 yv = forward16<false>(W, bias, xf, nullptr, lane);
     if (lane < 16 && act) {

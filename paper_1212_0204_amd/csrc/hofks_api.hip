@@ -2290,7 +2290,7 @@ size_t hofks_mlp_packed_bytes(void) { return mlp::PACKED_BYTES; }
 
 hofks_status hofks_mlp_pack(const float* params, void* packed, void* stream) {
   if (!params || !packed || ((uintptr_t)packed & 15)) return HOFKS_EINVAL;
-  const int n = mlp::NFRAG * 64 * 4 + mlp::NBIAS;
+  const int n = mlp::PACK_VALUES + mlp::NBIAS;
   hipLaunchKernelGGL(mlp::k_mlp_pack, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, params,
                      packed);
   return hipGetLastError() == hipSuccess ? HOFKS_OK : HOFKS_EDEVICE;

@@ -1,23 +1,27 @@
 // Closure network on the matrix cores: a multilayer perceptron 37 -> 64 ->
 // 64 -> 64 -> 4 (tanh hidden layers, linear output) with BF16 weights and
-// activations and FP32 accumulation, evaluated with the CDNA
-// v_mfma_f32_16x16x16_bf16 instruction.  The network is not part of the
+// activations and FP32 accumulation, evaluated on the matrix cores: the
+// forward pass with gfx950's v_mfma_f32_16x16x32_bf16, the backward products
+// with v_mfma_f32_16x16x16_bf16.  The network is not part of the
 // paper; it is the learned closure of the near-equilibrium cells (the
 // non-equilibrium part of the moment update, eq. (UK)).
 //
 // One wavefront carries 16 samples through the whole network.  A layer is
 // out^T = W a^T: the rows of an MFMA tile are output neurons, its columns
 // samples, and the K dimension runs over input neurons.  The accumulator of
-// a tile (lane j + 16q holds rows 4q..4q+3 of column j) is exactly the B
-// operand of the next layer's K step, so activations never leave registers.
+// a tile (lane j + 16q holds rows 4q..4q+3 of column j) is half of the B
+// operand of the next layer's 32-deep K step: step s takes the accumulators
+// of tiles 2s and 2s+1 of the same lane (its K order is neuron
+// 16 (2s + e/4) + 4q + e%4 for element e of lane quarter q, and the weight
+// fragments are packed in that order), so activations never leave registers.
 //
 // Flat FP32 parameter layout (shared with the host and the trainer):
 //   W1[64][37] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[4][64] b4[4]
-// Packed BF16 layout (what the kernels read): 84 fragments of 64 lanes x 4
-// values -- forward fragments of W1 (4 x 3), W2 (4 x 4), W3 (4 x 4), W4 (1 x
-// 4), then transposed fragments of W2, W3 (4 x 4) and W4 (4 x 1) for the
-// backward pass -- followed by the biases in FP32 (b1, b2, b3, b4 padded
-// to 16).
+// Packed BF16 layout (what the kernels read): 26 forward fragments of 64
+// lanes x 8 values -- W1 (4 output tiles x 2 K steps of 32 inputs), W2 and
+// W3 (4 x 2), W4 (1 x 2) -- then 36 transposed fragments of 64 lanes x 4
+// values for the backward pass -- W2, W3 (4 x 4), W4 (4 x 1) -- followed by
+// the biases in FP32 (b1, b2, b3, b4 padded to 16).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -28,13 +32,17 @@ constexpr int NIN = 37, NH = 64, NOUT = 4;
 constexpr int OW1 = 0, OB1 = OW1 + NH * NIN, OW2 = OB1 + NH, OB2 = OW2 + NH * NH;
 constexpr int OW3 = OB2 + NH, OB3 = OW3 + NH * NH, OW4 = OB3 + NH, OB4 = OW4 + NOUT * NH;
 constexpr int NPARAM = OB4 + NOUT;  // 11012
-constexpr int F_L1 = 0, F_L2 = 12, F_L3 = 28, F_L4 = 44;    // forward fragments
-constexpr int F_T2 = 48, F_T3 = 64, F_T4 = 80, NFRAG = 84;  // transposed fragments
+constexpr int F_L1 = 0, F_L2 = 8, F_L3 = 16, F_L4 = 24, NFWD = 26;  // forward (K = 32)
+constexpr int F_T2 = 0, F_T3 = 16, F_T4 = 32, NTR = 36;            // transposed (K = 16)
 constexpr int NBIAS = 3 * NH + 16;
-constexpr size_t FRAG_BYTES = (size_t)NFRAG * 64 * 8;
+constexpr size_t FWD_BYTES = (size_t)NFWD * 64 * 16;
+constexpr size_t FRAG_BYTES = FWD_BYTES + (size_t)NTR * 64 * 8;
 constexpr size_t PACKED_BYTES = FRAG_BYTES + NBIAS * sizeof(float);
+constexpr int PACK_VALUES = NFWD * 64 * 8 + NTR * 64 * 4;  // BF16 values before the biases
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16, round to nearest even (inputs are finite here)
@@ -62,22 +70,42 @@ __device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// value of element e of lane L of packed fragment f, from the flat params
-__device__ inline float frag_value(const float* __restrict__ p, int f, int L, int e) {
+// 16 x 16 x 32: lane l holds A row l % 16 and B column l % 16, K elements
+// 8 (l / 16) .. + 7; the accumulator as in the 16-deep form
+__device__ __forceinline__ f4 mfma32(s8 a, s8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
+                                                  __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ s8 cat8(s4 lo, s4 hi) {
+  return s8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+}
+
+// element e (0..7) of lane L of forward fragment f, from the flat params:
+// rows are output neurons 16 t + L % 16, K element k = 8 (L / 16) + e of
+// step s is input 32 s + k of the first layer, and hidden neuron
+// 16 (2 s + e / 4) + 4 (L / 16) + e % 4 of the others
+__device__ inline float fwd_value(const float* __restrict__ p, int f, int L, int e) {
   const int i = L & 15, kq = L >> 4;
+  const int hid_in = 4 * kq + (e & 3);  // + 16 (2 s + e / 4)
   if (f < F_L2) {  // W1: tile t of outputs, K step s of inputs
-    const int t = f / 3, s = f % 3, o = 16 * t + i, in = 16 * s + 4 * kq + e;
+    const int t = f / 2, s = f % 2, o = 16 * t + i, in = 32 * s + 8 * kq + e;
     return in < NIN ? p[OW1 + o * NIN + in] : 0.0f;
   }
   if (f < F_L4) {  // W2, W3
     const int base = f < F_L3 ? OW2 : OW3, ff = f < F_L3 ? f - F_L2 : f - F_L3;
-    const int t = ff / 4, s = ff % 4, o = 16 * t + i, in = 16 * s + 4 * kq + e;
+    const int t = ff / 2, s = ff % 2, o = 16 * t + i, in = 16 * (2 * s + (e >> 2)) + hid_in;
     return p[base + o * NH + in];
   }
-  if (f < F_T2) {  // W4 (rows 4..15 of the tile are zero)
-    const int s = f - F_L4, o = i, in = 16 * s + 4 * kq + e;
+  {  // W4 (rows 4..15 of the tile are zero)
+    const int s = f - F_L4, o = i, in = 16 * (2 * s + (e >> 2)) + hid_in;
     return o < NOUT ? p[OW4 + o * NH + in] : 0.0f;
   }
+}
+
+// element e (0..3) of lane L of transposed fragment f (backward pass, K = 16)
+__device__ inline float tr_value(const float* __restrict__ p, int f, int L, int e) {
+  const int i = L & 15, kq = L >> 4;
   if (f < F_T4) {  // W2^T, W3^T: rows are inputs, K runs over outputs
     const int base = f < F_T3 ? OW2 : OW3, ff = f < F_T3 ? f - F_T2 : f - F_T3;
     const int t = ff / 4, s = ff % 4, in = 16 * t + i, o = 16 * s + 4 * kq + e;
@@ -92,12 +120,15 @@ __device__ inline float frag_value(const float* __restrict__ p, int f, int L, in
 // flat FP32 parameters -> packed BF16 fragments + FP32 biases
 __global__ void k_mlp_pack(const float* __restrict__ p, void* __restrict__ packed) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  constexpr int NV = NFRAG * 64 * 4;
-  if (idx < NV) {
-    const int e = idx & 3, L = (idx >> 2) & 63, f = idx >> 8;
-    reinterpret_cast<short*>(packed)[idx] = to_bf16(frag_value(p, f, L, e));
-  } else if (idx < NV + NBIAS) {
-    const int b = idx - NV;
+  constexpr int NF = NFWD * 64 * 8;
+  if (idx < NF) {
+    const int e = idx & 7, L = (idx >> 3) & 63, f = idx >> 9;
+    reinterpret_cast<short*>(packed)[idx] = to_bf16(fwd_value(p, f, L, e));
+  } else if (idx < PACK_VALUES) {
+    const int k = idx - NF, e = k & 3, L = (k >> 2) & 63, f = k >> 8;
+    reinterpret_cast<short*>(packed)[idx] = to_bf16(tr_value(p, f, L, e));
+  } else if (idx < PACK_VALUES + NBIAS) {
+    const int b = idx - PACK_VALUES;
     float v;
     if (b < NH) v = p[OB1 + b];
     else if (b < 2 * NH) v = p[OB2 + b - NH];
@@ -107,8 +138,11 @@ __global__ void k_mlp_pack(const float* __restrict__ p, void* __restrict__ packe
   }
 }
 
-__device__ __forceinline__ const s4* frags(const void* packed) {
-  return reinterpret_cast<const s4*>(packed);
+__device__ __forceinline__ const s8* fwd_frags(const void* packed) {
+  return reinterpret_cast<const s8*>(packed);
+}
+__device__ __forceinline__ const s4* tr_frags(const void* packed) {
+  return reinterpret_cast<const s4*>(reinterpret_cast<const char*>(packed) + FWD_BYTES);
 }
 __device__ __forceinline__ const float* biases(const void* packed) {
   return reinterpret_cast<const float*>(reinterpret_cast<const char*>(packed) + FRAG_BYTES);
@@ -121,13 +155,13 @@ __device__ __forceinline__ f4 bias_frag(const float* b, int t, int lane) {
 
 // forward fragments of one wavefront, kept in registers by the caller
 struct FwdW {
-  s4 w[F_T2];
+  s8 w[NFWD];
 };
 
 __device__ __forceinline__ void load_fwd(const void* packed, FwdW& W, int lane) {
-  const s4* F = frags(packed);
+  const s8* F = fwd_frags(packed);
 #pragma unroll
-  for (int f = 0; f < F_T2; ++f) W.w[f] = F[f * 64 + lane];
+  for (int f = 0; f < NFWD; ++f) W.w[f] = F[f * 64 + lane];
 }
 
 // Hidden activations of one 16-sample tile (post-tanh, FP32 and BF16).
@@ -136,19 +170,19 @@ struct Acts {
   s4 b[3][4];
 };
 
-// 16 samples through the network: x holds the three K fragments of the
-// inputs (features 16 s + 4 q .. + 3 of sample j in lane j + 16 q).  Returns
+// 16 samples through the network: x holds the two K fragments of the
+// inputs (features 32 s + 8 q .. + 7 of sample j in lane j + 16 q).  Returns
 // the output tile: lanes 0..15 hold outputs 0..3 of their sample.
 template <bool KEEP>
 __device__ __forceinline__ f4 forward16(const FwdW& W, const float* __restrict__ bias,
-                                        const s4 (&x)[3], Acts* acts, int lane) {
+                                        const s8 (&x)[2], Acts* acts, int lane) {
   s4 b[4];
   f4 h[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     h[t] = bias_frag(bias, t, lane);
 #pragma unroll
-    for (int s = 0; s < 3; ++s) h[t] = mfma(W.w[F_L1 + 3 * t + s], x[s], h[t]);
+    for (int s = 0; s < 2; ++s) h[t] = mfma32(W.w[F_L1 + 2 * t + s], x[s], h[t]);
   }
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
@@ -165,33 +199,35 @@ __device__ __forceinline__ f4 forward16(const FwdW& W, const float* __restrict__
     if (l == 2) break;
     const int base = l == 0 ? F_L2 : F_L3;
     const float* bl = bias + NH * (l + 1);
+    const s8 bk[2] = {cat8(b[0], b[1]), cat8(b[2], b[3])};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       h[t] = bias_frag(bl, t, lane);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) h[t] = mfma(W.w[base + 4 * t + s], b[s], h[t]);
+      for (int s = 0; s < 2; ++s) h[t] = mfma32(W.w[base + 2 * t + s], bk[s], h[t]);
     }
   }
   f4 y = bias_frag(bias + 3 * NH, 0, lane);
 #pragma unroll
-  for (int s = 0; s < 4; ++s) y = mfma(W.w[F_L4 + s], b[s], y);
+  for (int s = 0; s < 2; ++s) y = mfma32(W.w[F_L4 + s], cat8(b[2 * s], b[2 * s + 1]), y);
   return y;
 }
 
 // inputs of one 16-sample tile from row `row` of a row-major [.][37] FP32
 // array (zero where `ok` is false)
 __device__ __forceinline__ void load_x(const float* __restrict__ x, long row, bool ok, int lane,
-                                       s4 (&xf)[3]) {
+                                       s8 (&xf)[2]) {
   const int q = lane >> 4;
 #pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    f4 v;
+  for (int s = 0; s < 2; ++s) {
+    f4 lo, hi;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int in = 16 * s + 4 * q + e;
-      v[e] = (ok && in < NIN) ? x[row * NIN + in] : 0.0f;
+      const int in = 32 * s + 8 * q + e;
+      lo[e] = (ok && in < NIN) ? x[row * NIN + in] : 0.0f;
+      hi[e] = (ok && in + 4 < NIN) ? x[row * NIN + in + 4] : 0.0f;
     }
-    xf[s] = pack4(v);
+    xf[s] = cat8(pack4(lo), pack4(hi));
   }
 }
 
@@ -208,7 +244,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const void* __restrict__ pa
   const long nwave = (long)gridDim.x * (blockDim.x >> 6);
   for (long tile = wave; tile < ntile; tile += nwave) {
     const long j = tile * 16 + (lane & 15);
-    s4 xf[3];
+    s8 xf[2];
     load_x(x, j, j < n, lane, xf);
     const f4 out = forward16<false>(W, bias, xf, nullptr, lane);
     if (lane < 16 && j < n) *reinterpret_cast<f4*>(y + j * NOUT) = out;
@@ -239,6 +275,14 @@ __device__ __forceinline__ void tr_store(short* T, int t, s4 v, int lane) {
   const int j = lane & 15, q = lane >> 4;
 #pragma unroll
   for (int r = 0; r < 4; ++r) T[(16 * t + 4 * q + r) * TR_ROW + j] = v[r];
+}
+
+// an input fragment (features 32 s + 8 q + e of sample j) into rows
+// 32 s + 8 q + e of the transposed array
+__device__ __forceinline__ void tr_store8(short* T, int s, s8 v, int lane) {
+  const int j = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) T[(32 * s + 8 * q + e) * TR_ROW + j] = v[e];
 }
 
 // fragment with rows 16 t + i and K = samples 4 q .. 4 q + 3
@@ -320,7 +364,7 @@ __global__ __launch_bounds__(64 * GRAD_WAVES) void k_mlp_grad(const void* __rest
   FwdW W;
   load_fwd(packed, W, lane);
   const float* bias = biases(packed);
-  const s4* F = frags(packed);
+  const s4* F = tr_frags(packed);
   const float inv = 1.0f / (4.0f * (float)n);
   float lsum = 0.0f;
   const long ntile = (n + 15) / 16;
@@ -330,7 +374,7 @@ __global__ __launch_bounds__(64 * GRAD_WAVES) void k_mlp_grad(const void* __rest
   for (long tile = wave; tile < ntile; tile += nwave) {
     const long j = tile * 16 + (lane & 15);
     const long row = j < n ? (idx ? (long)idx[j] : j) : 0;
-    s4 xf[3];
+    s8 xf[2];
     load_x(x, row, j < n, lane, xf);
     Acts A;
     const f4 y = forward16<true>(W, bias, xf, &A, lane);
@@ -412,7 +456,7 @@ __global__ __launch_bounds__(64 * GRAD_WAVES) void k_mlp_grad(const void* __rest
       tr_store(TZ, u, pack4(d[u]), lane);
     }
 #pragma unroll
-    for (int s = 0; s < 3; ++s) tr_store(TA, s, xf[s], lane);
+    for (int s = 0; s < 2; ++s) tr_store8(TA, s, xf[s], lane);
     wave_sync_lds();
 #pragma unroll
     for (int T = 0; T < 4; ++T) {

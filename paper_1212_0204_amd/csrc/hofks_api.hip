@@ -1572,10 +1572,6 @@ hofks_status batch_order(hofks_ctx* c) {
                    [](const std::pair<double, int4>& a, const std::pair<double, int4>& b) {
                      return a.first > b.first;
                    });
-  std::vector<int4> eitems;
-  for (const auto& w : ew) eitems.push_back(w.second);
-  if ((int)eitems.size() > B->eitems_max)
-    return fmt_err(c->err, "batch Euler item list exceeds its workspace"), HOFKS_EINVAL;
   // kinetic items: the tubes are dealt to the NXCD dies by kinetic work
   // (largest first, each to the least loaded die), a die's list holds its
   // tubes' segments in order, and block b of the kinetic launch takes entry
@@ -1588,11 +1584,38 @@ hofks_status batch_order(hofks_ctx* c) {
   std::stable_sort(korder.begin(), korder.end(), [&](int a, int b) { return kwork(a) > kwork(b); });
   std::vector<std::vector<int2>> die(NXCD);
   std::vector<double> load(NXCD, 0.0);
+  std::vector<int> tdie(B->n, 0);
   for (int i : korder) {
     const int d = (int)(std::min_element(load.begin(), load.end()) - load.begin());
     for (int sg = 0; sg * B->cells < B->tubes[i].Nx; ++sg) die[d].push_back(make_int2(i, sg));
     load[d] += kwork(i);
+    tdie[i] = d;
   }
+  // Euler items on their tube's die (the die of its kinetic and update
+  // items, whose U^n it reads and which read its result): block p of the
+  // Euler launch takes the next item of die p mod NXCD, in work order, or
+  // the heaviest item left when that die has none; split solves keep the
+  // plain work order (their parts start together)
+  std::vector<int4> eitems;
+  if (B->part > 0) {
+    for (const auto& w : ew) eitems.push_back(w.second);
+  } else {
+    std::vector<std::vector<std::pair<double, int4>>> dq(NXCD);
+    for (const auto& w : ew) dq[tdie[w.second.x]].push_back(w);
+    std::vector<size_t> head(NXCD, 0);
+    for (size_t pos = 0; pos < ew.size(); ++pos) {
+      int d = (int)(pos % NXCD);
+      if (head[d] == dq[d].size()) {
+        d = -1;
+        for (int e = 0; e < (int)NXCD; ++e)
+          if (head[e] < dq[e].size() && (d < 0 || dq[e][head[e]].first > dq[d][head[d]].first))
+            d = e;
+      }
+      eitems.push_back(dq[d][head[d]++].second);
+    }
+  }
+  if ((int)eitems.size() > B->eitems_max)
+    return fmt_err(c->err, "batch Euler item list exceeds its workspace"), HOFKS_EINVAL;
   size_t len = 0;
   for (const auto& l : die) len = std::max(len, l.size());
   std::vector<int2> items;

@@ -13,6 +13,8 @@
 
 namespace hofks {
 
+constexpr int UPD_CELLS = 256;  // cells per update item (one thread each)
+
 struct TubeDev {
   long long g[2];    // piece offsets (floats); g[p] holds f^n when step % 2 == p
   long long rec[2];  // record offsets (floats)
@@ -36,6 +38,7 @@ struct BatchArgs {
   const int4* eitems;     // Euler items, most work first: (tube, 0, 0, 0) whole,
                           // (tube, part, parts, 1) one part, (tube, tube or -1, CPT, 2) a pair
   const int2* items;      // kinetic items (tube, segment) dealt to the dies; tube -1: none
+  const int2* uitems;     // update items (tube, UPD_CELLS-cell segment), the same dies
   int neuler, nitems;
   int part_cells;         // cells per part of a split Euler solve (1024 or 2048)
   unsigned* ebar;         // [tube][parity]: arrivals at the part barriers
@@ -808,7 +811,7 @@ __device__ void batch_kinetic_item(const BatchArgs& a, int it, unsigned char* ld
 __device__ void batch_update_item(const BatchArgs& a, int it) {
   constexpr int RS = rec_stride<1, float>();
   it = __builtin_amdgcn_readfirstlane(it);
-  const int2 item = a.items[it];
+  const int2 item = a.uitems[it];
   const int t = __builtin_amdgcn_readfirstlane(item.x);
   if (t < 0) return;  // padding of a die's item list
   if (a.tflag[t] != 0) return;  // a flagged tube is no longer advanced
@@ -901,7 +904,7 @@ __global__ __launch_bounds__(1024) void k_batch_kinetic(BatchArgs a) {
   batch_kinetic_item<CELLS, UNR>(a, blockIdx.x, lds_raw);
 }
 
-// Update launch: one block of CELLS threads per kinetic item.
+// Update launch: one block of UPD_CELLS threads per update item.
 __global__ __launch_bounds__(1024) void k_batch_update(BatchArgs a) {
   batch_update_item(a, blockIdx.x);
 }

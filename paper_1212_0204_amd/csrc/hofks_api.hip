@@ -1363,7 +1363,7 @@ struct Batch {
   int nvt = 0, items_max = 0, eitems_max = 0;
   long long total_cells = 0, total_cv = 0;
   size_t off_gar = 0, off_rar = 0, off_dar = 0, off_vt = 0, off_tubes = 0, off_eitems = 0,
-         off_items = 0, off_alpha = 0, off_s = 0, off_tflag = 0,
+         off_items = 0, off_uitems = 0, off_alpha = 0, off_s = 0, off_tflag = 0,
          off_flag = 0, off_ebar = 0, total = 0;
   // device pointers
   float *gar = nullptr, *rar = nullptr;
@@ -1374,9 +1374,10 @@ struct Batch {
   unsigned* ebar = nullptr;
   int4* eitems = nullptr;
   int2* items = nullptr;
+  int2* uitems = nullptr;  // update items: 256-cell segments on their tube's die
   // launch configuration; part = cells per part of a split Euler solve (0:
   // every tube whole in one block)
-  int cells = 256, unr = 8, nitems = 0, neuler = 0, ncu = 256, part = 0;
+  int cells = 256, unr = 8, nitems = 0, nuitems = 0, neuler = 0, ncu = 256, part = 0;
   size_t lds = 0;
   // graph of GRAPH_STEPS launches starting at parity 0
   hipStream_t cap = nullptr;
@@ -1475,6 +1476,7 @@ hofks_status batch_plan(const hofks_grid_desc* descs, const double* taus, int n,
   B->off_tubes = take(sizeof(TubeDev) * n);
   B->off_eitems = take(sizeof(int4) * eitems);
   B->off_items = take(sizeof(int2) * B->items_max);
+  B->off_uitems = take(sizeof(int2) * B->items_max);
   B->off_alpha = take(sizeof(double) * n * 2 * ASTR);
   B->off_s = take(sizeof(int) * n);
   B->off_tflag = take(sizeof(int) * n);
@@ -1624,11 +1626,26 @@ hofks_status batch_order(hofks_ctx* c) {
       items.push_back(q < die[d].size() ? die[d][q] : make_int2(-1, 0));
   if ((int)items.size() > B->items_max)
     return fmt_err(c->err, "batch item list exceeds its workspace"), HOFKS_EINVAL;
+  // update items: the same dies, in segments of UPD_CELLS cells
+  std::vector<std::vector<int2>> udie(NXCD);
+  for (int i : korder)
+    for (int sg = 0; sg * UPD_CELLS < B->tubes[i].Nx; ++sg) udie[tdie[i]].push_back(make_int2(i, sg));
+  size_t ulen = 0;
+  for (const auto& l : udie) ulen = std::max(ulen, l.size());
+  std::vector<int2> uitems;
+  for (size_t q = 0; q < ulen; ++q)
+    for (unsigned d = 0; d < NXCD; ++d)
+      uitems.push_back(q < udie[d].size() ? udie[d][q] : make_int2(-1, 0));
+  if ((int)uitems.size() > B->items_max)
+    return fmt_err(c->err, "batch update item list exceeds its workspace"), HOFKS_EINVAL;
+  B->nuitems = (int)uitems.size();
   B->nitems = (int)items.size();
   B->neuler = (int)eitems.size();
   HIPCHK(c, hipMemcpyAsync(B->eitems, eitems.data(), sizeof(int4) * eitems.size(),
                            hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(B->items, items.data(), sizeof(int2) * items.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(B->uitems, uitems.data(), sizeof(int2) * uitems.size(),
                            hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return HOFKS_OK;
@@ -1644,6 +1661,7 @@ BatchArgs batch_args(hofks_ctx* c, int parity) {
   a.tubes = B->tubes_d;
   a.eitems = B->eitems;
   a.items = B->items;
+  a.uitems = B->uitems;
   a.neuler = B->neuler;
   a.nitems = B->nitems;
   a.part_cells = B->part > 0 ? B->part : 1024;
@@ -1686,7 +1704,7 @@ hofks_status batch_launch(hofks_ctx* c, hipStream_t stream, int parity) {
 #undef BL
   HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
   HIPCHK(c, hipStreamWaitEvent(stream, c->ev_join, 0));
-  hipLaunchKernelGGL(k_batch_update, dim3(B->nitems), dim3(B->cells), 0, stream, a);
+  hipLaunchKernelGGL(k_batch_update, dim3(B->nuitems), dim3(UPD_CELLS), 0, stream, a);
   HIPCHK(c, hipGetLastError());
   return HOFKS_OK;
 }
@@ -1986,6 +2004,7 @@ hofks_status hofks_batch_create(const hofks_grid_desc* descs, const double* taus
   B->tubes_d = (TubeDev*)(c->ws + B->off_tubes);
   B->eitems = (int4*)(c->ws + B->off_eitems);
   B->items = (int2*)(c->ws + B->off_items);
+  B->uitems = (int2*)(c->ws + B->off_uitems);
   B->alpha = (double*)(c->ws + B->off_alpha);
   B->tube_s = (int*)(c->ws + B->off_s);
   B->tflag = (int*)(c->ws + B->off_tflag);

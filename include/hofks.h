@@ -109,7 +109,11 @@ hofks_status hofks_set_state_macro(hofks_ctx *ctx, const double *rho,
  * Nv*Nc values); U^0 = P(f^0), eq. (DM).  Synchronous. */
 hofks_status hofks_set_state_f(hofks_ctx *ctx, const double *f, size_t bytes);
 
-/* Advance n_steps >= 0 time steps; asynchronous on the context's stream. */
+/* Advance n_steps >= 0 time steps; asynchronous on the context's stream: it
+ * returns once the last step is queued.  In a call of more than 8 steps it
+ * reads back the Euler sub-step count of a step 8 behind the one it queues
+ * (waiting for that step when needed), so that the launches of the later
+ * steps follow a count that grows during the call. */
 hofks_status hofks_step(hofks_ctx *ctx, int n_steps);
 
 /* Wait for the stream and report the sticky device flag. */
@@ -148,8 +152,11 @@ hofks_status hofks_read_tail_substeps(hofks_ctx *ctx, long *n);
  * single-sub-step kernels followed by a persistent kernel that runs any
  * further sub-steps with an in-kernel barrier between them.  k = 0 (the
  * default) takes k = (sub-steps of the last step seen at a synchronising
- * call) + 1; k >= 1 fixes it, so that k = 1 runs every sub-step after the
- * first in the persistent kernel.  Results do not depend on k.  HOFKS_EINVAL
+ * call, or read back during a long hofks_step call) + 1; k >= 1 fixes it,
+ * so that k = 1 runs every sub-step after the first in the persistent
+ * kernel.  The two kernels form the same faces from the same values; their
+ * results agree to rounding (the compiler may contract their products
+ * differently).  HOFKS_EINVAL
  * for k < 0 or a batch. */
 hofks_status hofks_set_euler_launches(hofks_ctx *ctx, int k);
 

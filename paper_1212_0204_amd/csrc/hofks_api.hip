@@ -310,6 +310,14 @@ struct hofks_ctx {
   // caller's stream with two events, beside the kinetic kernel
   hipStream_t aux;
   hipEvent_t ev_fork, ev_join;
+  // the Euler sub-step count of a recent step, read back during long step
+  // calls: a third stream copies it to pinned host memory after the step
+  // (ev_s) and marks the copy (ev_peek); peek_at is the step it follows
+  hipStream_t peek_st;
+  hipEvent_t ev_s, ev_peek;
+  int* peek_h;
+  bool peek_pending;
+  long peek_at;
   // closure form (2D-2V): network (caller's device memory), scale of its
   // output, indicator threshold; per-cell arrays in the workspace
   const void* clos_w;
@@ -808,6 +816,41 @@ hofks_status launch_closure_step(hofks_ctx* c, StepArgs<T>& a, float* snap_x, fl
   return HOFKS_OK;
 }
 
+// Within a long step call the host reads back the Euler sub-step count of a
+// step some steps behind the one it queues, so that the per-sub-step Euler
+// launches of the later steps follow a count that grows during the call
+// (otherwise the persistent tail, slower per sub-step beside the kinetic
+// kernel, runs the growth).  It waits for that step only when it is
+// PEEK_LAG steps ahead of it, so the device keeps that many steps queued.
+constexpr long PEEK_LAG = 8;
+
+hofks_status peek_substeps(hofks_ctx* c) {
+  if (c->peek_pending) {
+    hipError_t q = hipEventQuery(c->ev_peek);
+    if (q == hipErrorNotReady) {
+      (void)hipGetLastError();  // clear the status the query leaves
+      if (c->steps - c->peek_at < PEEK_LAG) return HOFKS_OK;
+      q = hipEventSynchronize(c->ev_peek);
+    }
+    if (q != hipSuccess) return fmt_err(c->err, "step count read-back failed"), HOFKS_EDEVICE;
+    if (*c->peek_h > 0) c->s_known = *c->peek_h;
+    c->peek_pending = false;
+  }
+  return HOFKS_OK;
+}
+
+hofks_status peek_issue(hofks_ctx* c) {
+  if (c->peek_pending) return HOFKS_OK;
+  HIPCHK(c, hipEventRecord(c->ev_s, c->stream));
+  HIPCHK(c, hipStreamWaitEvent(c->peek_st, c->ev_s, 0));
+  HIPCHK(c, hipMemcpyAsync(c->peek_h, c->flag + 1, sizeof(int), hipMemcpyDeviceToHost,
+                           c->peek_st));
+  HIPCHK(c, hipEventRecord(c->ev_peek, c->peek_st));
+  c->peek_pending = true;
+  c->peek_at = c->steps;
+  return HOFKS_OK;
+}
+
 template <int D, typename T>
 hofks_status step_impl(hofks_ctx* c, int nsteps) {
   c->fork_pending = false;
@@ -815,11 +858,14 @@ hofks_status step_impl(hofks_ctx* c, int nsteps) {
   for (int it = 0; it < nsteps && !st; ++it) {
     c->fork_next = it + 1 < nsteps;
     if (c->strang) set_step_weights(c);
+    if (c->euler_k == 0) st = peek_substeps(c);
+    if (st) break;
     st = launch_step<D, T>(c);
     if (st) break;
     c->cur ^= 1;
     c->steps++;
     c->inv_prev = inv_tau(c->tau);
+    if (c->euler_k == 0 && nsteps > PEEK_LAG) st = peek_issue(c);
   }
   if (c->strang) set_step_weights(c);
   c->fork_next = c->fork_pending = false;
@@ -991,10 +1037,17 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
   constexpr unsigned evf = hipEventDisableTiming | hipEventDisableSystemFence;
   if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, evf) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, evf) != hipSuccess) {
-    delete c;
+      hipEventCreateWithFlags(&c->ev_join, evf) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->peek_st, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_s, evf) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_peek, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->peek_h), sizeof(int), hipHostMallocDefault) !=
+          hipSuccess) {
+    hofks_destroy(c);
     return HOFKS_EDEVICE;
   }
+  *c->peek_h = 0;
+  c->peek_pending = false;
   c->tau = INFINITY;
   c->s_cap = 1;
   c->s_known = 1;
@@ -2526,6 +2579,13 @@ hofks_status hofks_mlp_adam(float* params, const float* grad, float* m, float* v
 extern "C" void hofks_destroy(hofks_ctx* c) {
   if (!c) return;
   batch_free(c);
+  if (c->peek_st) {
+    (void)hipStreamSynchronize(c->peek_st);
+    (void)hipStreamDestroy(c->peek_st);
+  }
+  if (c->ev_s) (void)hipEventDestroy(c->ev_s);
+  if (c->ev_peek) (void)hipEventDestroy(c->ev_peek);
+  if (c->peek_h) (void)hipHostFree(c->peek_h);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);

@@ -110,10 +110,10 @@ hofks_status hofks_set_state_macro(hofks_ctx *ctx, const double *rho,
 hofks_status hofks_set_state_f(hofks_ctx *ctx, const double *f, size_t bytes);
 
 /* Advance n_steps >= 0 time steps; asynchronous on the context's stream: it
- * returns once the last step is queued.  In a call of more than 8 steps it
- * reads back the Euler sub-step count of a step 8 behind the one it queues
- * (waiting for that step when needed), so that the launches of the later
- * steps follow a count that grows during the call. */
+ * returns once the last step is queued.  In a call of more than 16 steps on
+ * a 2D or 3D grid it reads back the Euler sub-step count of earlier steps
+ * (waiting for a step once it is 16 behind the one being queued), so that the
+ * launches of the later steps follow a count that grows during the call. */
 hofks_status hofks_step(hofks_ctx *ctx, int n_steps);
 
 /* Wait for the stream and report the sticky device flag. */

@@ -285,6 +285,7 @@ struct hofks_ctx {
   double tau;
   int s_cap;
   int s_known;  // Euler sub-steps of the last step seen by the host
+  int s_margin;  // spare single-sub-step launches beyond s_known (0 or 1)
   int euler_k;  // > 0: per-sub-step Euler launches before the tail (0: s_known + 1)
   bool euler_seq;   // the Euler solve runs on the caller's stream before the kinetic kernel
   bool strang;      // Strang splitting: half relaxations around each transport
@@ -311,13 +312,15 @@ struct hofks_ctx {
   hipStream_t aux;
   hipEvent_t ev_fork, ev_join;
   // the Euler sub-step count of a recent step, read back during long step
-  // calls: a third stream copies it to pinned host memory after the step
-  // (ev_s) and marks the copy (ev_peek); peek_at is the step it follows
-  hipStream_t peek_st;
-  hipEvent_t ev_s, ev_peek;
+  // calls: the auxiliary stream copies it to pinned host memory after the
+  // step's Euler launches and marks the copy (ev_peek)
+  hipEvent_t ev_peek;
   int* peek_h;
+  bool peek_now;      // copy the count of the step being queued
   bool peek_pending;
-  long peek_at;
+  long peek_at;     // step after which the pending read was queued
+  long peek_next;   // first step at which the next read may be queued
+  int peek_every;   // steps between reads: 8 while the count moves, doubling to 64 while not
   // closure form (2D-2V): network (caller's device memory), scale of its
   // output, indicator threshold; per-cell arrays in the workspace
   const void* clos_w;
@@ -568,13 +571,32 @@ void launch_euler(hofks_ctx* c, const StepArgs<T>& a, hipStream_t st);
 
 // Euler launches of the step on the auxiliary stream, after everything
 // already queued on the caller's stream
+// the step's sub-step count to the host on the auxiliary stream, after its
+// Euler launches there (or, with the Euler solve on the caller's stream, after
+// an event that follows them), beside the update
+hofks_status queue_peek(hofks_ctx* c) {
+  c->peek_now = false;
+  if (c->euler_seq) {  // the auxiliary stream is idle in this form
+    HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->peek_h, c->flag + 1, sizeof(int), hipMemcpyDeviceToHost, c->aux));
+  HIPCHK(c, hipEventRecord(c->ev_peek, c->aux));
+  c->peek_pending = true;
+  c->peek_at = c->steps;
+  c->peek_next = c->steps + c->peek_every;
+  return HOFKS_OK;
+}
+
 template <int D, typename T>
 hofks_status fork_euler(hofks_ctx* c, const StepArgs<T>& a) {
   if (c->euler_seq) {  // before the kinetic kernel, on the caller's stream
-    Mark m0(c, 0, 1, c->stream);
-    launch_euler<D, T>(c, a, c->stream);
-    HIPCHK(c, hipGetLastError());
-    return HOFKS_OK;
+    {
+      Mark m0(c, 0, 1, c->stream);
+      launch_euler<D, T>(c, a, c->stream);
+      HIPCHK(c, hipGetLastError());
+    }
+    return c->peek_now ? queue_peek(c) : HOFKS_OK;
   }
   // within one hofks_step call the previous step recorded the fork point
   // right after U^{n+1} was formed, before its records
@@ -589,7 +611,7 @@ hofks_status fork_euler(hofks_ctx* c, const StepArgs<T>& a) {
     HIPCHK(c, hipGetLastError());
   }
   HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
-  return HOFKS_OK;
+  return c->peek_now ? queue_peek(c) : HOFKS_OK;
 }
 
 // join the Euler launches and run the per-cell update on the caller's stream
@@ -618,15 +640,18 @@ hofks_status join_update(hofks_ctx* c, const StepArgs<T>& a) {
 }
 
 // Euler solve of a step: one launch per sub-step for the first K = (last
-// known count + 1) sub-steps (the kernel boundary is the grid-wide barrier),
-// then a persistent tail that runs any further sub-steps with an in-kernel
-// barrier (it returns at once when K >= s).  One spare launch absorbs a count
-// that grows by one within a call; each launch with i >= s still costs a
-// kernel boundary on the solve's critical path, so there is only one.
+// known count + margin) sub-steps (the kernel boundary is the grid-wide
+// barrier), then a persistent tail that runs any further sub-steps with an
+// in-kernel barrier (it returns at once when K >= s).  The spare launch (margin
+// 1) absorbs a count that grows by one; each launch with i >= s still costs a
+// kernel boundary on the solve's critical path, so it is dropped while the
+// read-back sees a steady count, and a single sub-step left to the tail is
+// about as cheap.
 template <int D, typename T>
 void launch_euler(hofks_ctx* c, const StepArgs<T>& a, hipStream_t st) {
   const Plan& P = c->P;
-  const int K = std::max(1, std::min(c->s_cap, c->euler_k > 0 ? c->euler_k : c->s_known + 1));
+  const int K = std::max(
+      1, std::min(c->s_cap, c->euler_k > 0 ? c->euler_k : c->s_known + c->s_margin));
   if (c->desc.scheme == 3) {  // WENO: three Runge-Kutta stage launches per sub-step
     if constexpr (D == 2) {  // 16 x 16 LDS tiles
       const int ntx = (P.G.n[0] + WT - 1) / WT, nty = (P.G.n[1] + WT - 1) / WT;
@@ -816,13 +841,18 @@ hofks_status launch_closure_step(hofks_ctx* c, StepArgs<T>& a, float* snap_x, fl
   return HOFKS_OK;
 }
 
-// Within a long step call the host reads back the Euler sub-step count of a
-// step some steps behind the one it queues, so that the per-sub-step Euler
-// launches of the later steps follow a count that grows during the call
-// (otherwise the persistent tail, slower per sub-step beside the kinetic
-// kernel, runs the growth).  It waits for that step only when it is
-// PEEK_LAG steps ahead of it, so the device keeps that many steps queued.
-constexpr long PEEK_LAG = 8;
+// Within a long step call on a 2D or 3D grid the host reads back the Euler
+// sub-step count of a step some steps behind the one it queues, so that the
+// per-sub-step Euler launches of the later steps follow a count that grows
+// during the call (otherwise the persistent tail, slower per sub-step beside
+// the kinetic kernel, runs the growth).  Reads are 8 steps apart while the
+// count moves and up to 64 while it does not; while two reads agree the spare
+// Euler launch is dropped.  The host waits for the step a
+// read follows only when it is PEEK_LAG steps ahead of it, so the device
+// keeps that many steps queued; the wait polls (a blocking wait wakes up
+// late).  On 1D grids the tail is the faster form.
+constexpr long PEEK_LAG = 16;
+constexpr int PEEK_MIN = 8, PEEK_MAX = 64;
 
 hofks_status peek_substeps(hofks_ctx* c) {
   if (c->peek_pending) {
@@ -830,25 +860,24 @@ hofks_status peek_substeps(hofks_ctx* c) {
     if (q == hipErrorNotReady) {
       (void)hipGetLastError();  // clear the status the query leaves
       if (c->steps - c->peek_at < PEEK_LAG) return HOFKS_OK;
-      q = hipEventSynchronize(c->ev_peek);
+      do {
+        q = hipEventQuery(c->ev_peek);
+        if (q == hipErrorNotReady) (void)hipGetLastError();
+      } while (q == hipErrorNotReady);
     }
     if (q != hipSuccess) return fmt_err(c->err, "step count read-back failed"), HOFKS_EDEVICE;
-    if (*c->peek_h > 0) c->s_known = *c->peek_h;
+    const int sv = *c->peek_h;
+    c->peek_every = (sv > 0 && sv != c->s_known) ? PEEK_MIN : std::min(PEEK_MAX, 2 * c->peek_every);
+    if (sv > 0) c->s_known = sv;
     c->peek_pending = false;
   }
   return HOFKS_OK;
 }
 
-hofks_status peek_issue(hofks_ctx* c) {
-  if (c->peek_pending) return HOFKS_OK;
-  HIPCHK(c, hipEventRecord(c->ev_s, c->stream));
-  HIPCHK(c, hipStreamWaitEvent(c->peek_st, c->ev_s, 0));
-  HIPCHK(c, hipMemcpyAsync(c->peek_h, c->flag + 1, sizeof(int), hipMemcpyDeviceToHost,
-                           c->peek_st));
-  HIPCHK(c, hipEventRecord(c->ev_peek, c->peek_st));
-  c->peek_pending = true;
-  c->peek_at = c->steps;
-  return HOFKS_OK;
+// whether the step about to be queued copies its sub-step count back
+bool peek_due(const hofks_ctx* c) {
+  // (a step count set back by a new state leaves peek_next far ahead: read)
+  return !c->peek_pending && (c->steps >= c->peek_next || c->peek_next - c->steps > PEEK_MAX);
 }
 
 template <int D, typename T>
@@ -858,17 +887,20 @@ hofks_status step_impl(hofks_ctx* c, int nsteps) {
   for (int it = 0; it < nsteps && !st; ++it) {
     c->fork_next = it + 1 < nsteps;
     if (c->strang) set_step_weights(c);
-    if (c->euler_k == 0) st = peek_substeps(c);
+    const bool peek = c->euler_k == 0 && D >= 2 && nsteps > PEEK_LAG;
+    if (peek) st = peek_substeps(c);
     if (st) break;
+    c->peek_now = peek && peek_due(c);
+    c->s_margin = peek && c->peek_every > PEEK_MIN ? 0 : 1;  // two reads agreed
     st = launch_step<D, T>(c);
     if (st) break;
     c->cur ^= 1;
     c->steps++;
     c->inv_prev = inv_tau(c->tau);
-    if (c->euler_k == 0 && nsteps > PEEK_LAG) st = peek_issue(c);
   }
   if (c->strang) set_step_weights(c);
   c->fork_next = c->fork_pending = false;
+  c->s_margin = 1;
   return st;
 }
 
@@ -1038,8 +1070,6 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
   if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, evf) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_join, evf) != hipSuccess ||
-      hipStreamCreateWithFlags(&c->peek_st, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_s, evf) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_peek, hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->peek_h), sizeof(int), hipHostMallocDefault) !=
           hipSuccess) {
@@ -1048,9 +1078,12 @@ hofks_status hofks_create(const hofks_grid_desc* desc, void* dev_ws, size_t ws_b
   }
   *c->peek_h = 0;
   c->peek_pending = false;
+  c->peek_every = PEEK_MIN;
+  c->peek_next = 0;
   c->tau = INFINITY;
   c->s_cap = 1;
   c->s_known = 1;
+  c->s_margin = 1;
   // kinetic configuration before any tuning: wider unroll in 2D/3D, two
   // wavefronts per block for the FP64 2D grid
   c->kng = (P.d == 2 && !P.prec) ? 2 : 4;
@@ -2579,11 +2612,7 @@ hofks_status hofks_mlp_adam(float* params, const float* grad, float* m, float* v
 extern "C" void hofks_destroy(hofks_ctx* c) {
   if (!c) return;
   batch_free(c);
-  if (c->peek_st) {
-    (void)hipStreamSynchronize(c->peek_st);
-    (void)hipStreamDestroy(c->peek_st);
-  }
-  if (c->ev_s) (void)hipEventDestroy(c->ev_s);
+  if (c->aux) (void)hipStreamSynchronize(c->aux);  // a read-back may be in flight
   if (c->ev_peek) (void)hipEventDestroy(c->ev_peek);
   if (c->peek_h) (void)hipHostFree(c->peek_h);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);

@@ -462,6 +462,45 @@ def test_disk_substeps_grow_within_one_call():
     assert rel_inf(s.read_f(), o.f) < TOL64
 
 
+@gpu
+@pytest.mark.parametrize("before", [0, 1])
+def test_long_call_follows_a_moving_substep_count(before):
+    """the 40^2 periodic disk at tau = 0.02, whose sub-step count moves
+    between 12 and 18 over 70 steps: in one 70-step call the host reads the
+    count of earlier steps back and sizes the per-sub-step launches from it
+    (with the spare launch dropped while two reads agree); with the Euler
+    solve beside (0) or before (1) the kinetic kernel.  1e-12 against the
+    oracle and against the same run in single-step calls, and fewer tail
+    sub-steps than those calls, whose count stays at the initial one"""
+    n = (40, 40)
+    dx = 2.0 / 40
+    rho, u, th = W.disk_2d(40, 2.0, (1.0, 1.0), 0.3)
+    announce("disk 40^2 long call, euler before", before)
+    from paper_1212_0204_amd import Solver
+    o = Oracle(2, n, dx, 16, 0.5, bc=(0, 0), tau=0.02)
+    o.init_macro(rho, u, th)
+    o.step(70)
+    runs = []
+    for calls in (1, 70):
+        s = Solver(2, n, dx, 16, 0.5, bc=(0, 0), tau=0.02)
+        s.set_launch_config(4, 4, before)
+        s.set_state_macro(rho, u, th)
+        for _ in range(70 // calls):
+            s.step(calls)
+        s.sync()
+        runs.append((s.read_moments(), s.read_f(), s.tail_substeps(), s.counters()))
+        s.close()
+    (U1, f1, t1, c1), (U70, f70, t70, c70) = runs
+    print("tail sub-steps: single-step calls", t1, "one call", t70)
+    assert c1 == c70 == (o.substeps, 70), (c1, c70, o.substeps)
+    assert 0 < t70 < t1, (t70, t1)
+    for U, f in ((U1, f1), (U70, f70)):
+        err = moment_errors(U, o.U, 2)
+        assert err.max() < TOL64, err
+        assert rel_inf(f, o.f) < TOL64
+    assert moment_errors(U70, U1, 2).max() < TOL64
+
+
 # ------------------------------------------ WENO Euler solve (scheme 3)
 @gpu
 @pytest.mark.parametrize("d,n,nv,bc,tau,prec,launches", [

@@ -166,8 +166,10 @@ hofks_status hofks_set_euler_launches(hofks_ctx *ctx, int k);
  * sums), 2 = the per-cell update, 3 = the closure network and its indicator
  * (closure form only).  If ms/launches are non-null, synchronise and return
  * the summed elapsed milliseconds and the launch counts of each group since
- * the last call, then clear them; enable != 0 keeps recording for the
- * following steps. */
+ * the last call, then clear them.  enable is a bit mask of the groups to
+ * record for the following steps (bit g: group g; 15 all, 0 none); each
+ * recorded group adds two events per step to its stream.  HOFKS_EINVAL for
+ * a mask outside 0..15. */
 hofks_status hofks_kernel_timing(hofks_ctx *ctx, int enable, double ms[4],
                                  int launches[4]);
 

@@ -297,8 +297,9 @@ struct hofks_ctx {
   int kwide;      // 2D FP64 steps with an Euler solve: k_kinetic2w (two cells per lane)
   bool fork_next;     // the current step is followed by another in this call
   bool fork_pending;  // ev_fork already marks the next step's fork point
-  // optional per-kernel timing: hipEvents around each launch group
-  bool timing;
+  // optional per-kernel timing: hipEvents around the launch groups whose
+  // bits are set (bit g: group g)
+  unsigned timing;
   std::vector<hipEvent_t> ev_pool;
   struct MarkRec {
     int group, count;
@@ -417,13 +418,13 @@ struct Mark {
   hipEvent_t a = nullptr;
   Mark(hofks_ctx* c_, int g, int n = 1, hipStream_t s_ = nullptr)
       : c(c_), group(g), count(n), st(s_ ? s_ : c_->stream) {
-    if (c->timing) {
+    if (c->timing >> group & 1u) {
       a = next_event(c);
       if (a) (void)hipEventRecord(a, st);
     }
   }
   ~Mark() {
-    if (c->timing && a) {
+    if (a) {
       hipEvent_t b = next_event(c);
       if (b) {
         (void)hipEventRecord(b, st);
@@ -1385,6 +1386,7 @@ hofks_status hofks_read_counters(hofks_ctx* c, int* substeps, long* steps) {
 
 hofks_status hofks_kernel_timing(hofks_ctx* c, int enable, double* ms, int* launches) {
   if (!c) return HOFKS_EINVAL;
+  if (enable < 0 || enable > 15) return fmt_err(c->err, "timing group mask %d", enable), HOFKS_EINVAL;
   if (ms || launches) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1402,7 +1404,7 @@ hofks_status hofks_kernel_timing(hofks_ctx* c, int enable, double* ms, int* laun
   }
   c->ev_marks.clear();
   c->ev_next = 0;
-  c->timing = enable != 0;
+  c->timing = (unsigned)enable;
   return HOFKS_OK;
 }
 

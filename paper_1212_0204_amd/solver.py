@@ -149,13 +149,14 @@ class Solver:
         (0: automatic)"""
         self._check(_lib.lib().hofks_set_euler_launches(self._h, int(k)), "set_euler_launches")
 
-    def kernel_timing(self, enable=True):
+    def kernel_timing(self, enable=True, groups=(0, 1, 2, 3)):
         """(ms[4], launches[4]) of the Euler, kinetic, per-cell update and
         closure-network groups since the previous call; keeps recording
-        while ``enable``."""
+        the listed groups while ``enable``."""
+        mask = sum(1 << int(g) for g in set(groups)) if enable else 0
         ms = np.zeros(4)
         cnt = (ctypes.c_int * 4)()
-        self._check(_lib.lib().hofks_kernel_timing(self._h, int(enable), _dp(ms), cnt),
+        self._check(_lib.lib().hofks_kernel_timing(self._h, mask, _dp(ms), cnt),
                     "kernel_timing")
         return ms, list(cnt)
 

@@ -720,3 +720,32 @@ def test_euler_before_or_beside_the_kinetic_kernel(d, n, nv, prec, cfg):
     o.init_macro(*fields)
     o.step(7)
     assert moment_errors(runs[1][0], o.U, d).max() < (TOL64 if prec == 0 else TOL32)
+
+
+@gpu
+def test_kernel_timing_records_the_masked_groups_only():
+    """the timing mask: events around the kinetic launches only, then around
+    the Euler and update groups only; the launch counts follow the mask and
+    the results do not depend on it; a mask outside 0..15 is rejected"""
+    announce("kernel timing mask")
+    from paper_1212_0204_amd import Solver, _lib
+    n = (40, 36)
+    fields = _random_fields(2, 40 * 36, 91)
+    s = Solver(2, n, 1.0 / 40, 16, 0.5, bc=(0, 0), tau=1e-3)
+    s.set_state_macro(*fields)
+    s.kernel_timing(enable=True, groups=(1,))
+    s.step(5)
+    ms, cnt = s.kernel_timing(enable=True, groups=(0, 2))
+    assert cnt[1] == 5 and cnt[0] == cnt[2] == cnt[3] == 0 and ms[1] > 0, (ms, cnt)
+    s.step(5)
+    ms, cnt = s.kernel_timing(enable=False)
+    assert cnt[0] > 0 and cnt[2] > 0 and cnt[1] == cnt[3] == 0, (ms, cnt)
+    U = s.read_moments()
+    s.step(1)
+    assert s.kernel_timing(enable=False)[1] == [0, 0, 0, 0]
+    for bad in (16, -1):
+        assert _lib.lib().hofks_kernel_timing(s._h, bad, None, None) != 0
+    r = Solver(2, n, 1.0 / 40, 16, 0.5, bc=(0, 0), tau=1e-3)
+    r.set_state_macro(*fields)
+    r.step(10)
+    assert np.array_equal(r.read_moments(), U)

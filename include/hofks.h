@@ -152,9 +152,11 @@ hofks_status hofks_read_tail_substeps(hofks_ctx *ctx, long *n);
  * single-sub-step kernels followed by a persistent kernel that runs any
  * further sub-steps with an in-kernel barrier between them.  k = 0 (the
  * default) takes k = (sub-steps of the last step seen at a synchronising
- * call, or read back during a long hofks_step call) + 1; k >= 1 fixes it,
- * so that k = 1 runs every sub-step after the first in the persistent
- * kernel.  The two kernels form the same faces from the same values; their
+ * call, or read back during a long hofks_step call) + 1, dropping the + 1
+ * while that count is steady, and k = 1 on a 1D grid (scheme other than 3)
+ * that fits one persistent block, where the barrier is the block's own;
+ * k >= 1 fixes it, so that k = 1 runs every sub-step after the first in the
+ * persistent kernel.  The two kernels form the same faces from the same values; their
  * results agree to rounding (the compiler may contract their products
  * differently).  HOFKS_EINVAL
  * for k < 0 or a batch. */

@@ -651,8 +651,13 @@ hofks_status join_update(hofks_ctx* c, const StepArgs<T>& a) {
 template <int D, typename T>
 void launch_euler(hofks_ctx* c, const StepArgs<T>& a, hipStream_t st) {
   const Plan& P = c->P;
+  // a 1D grid within one tail block runs every sub-step after the first in
+  // the tail, whose barrier is then the block's own
+  const bool one_block = D == 1 && P.GE == 1 && c->desc.scheme != 3;
   const int K = std::max(
-      1, std::min(c->s_cap, c->euler_k > 0 ? c->euler_k : c->s_known + c->s_margin));
+      1, std::min(c->s_cap, c->euler_k > 0 ? c->euler_k
+                            : one_block    ? 1
+                                           : c->s_known + c->s_margin));
   if (c->desc.scheme == 3) {  // WENO: three Runge-Kutta stage launches per sub-step
     if constexpr (D == 2) {  // 16 x 16 LDS tiles
       const int ntx = (P.G.n[0] + WT - 1) / WT, nty = (P.G.n[1] + WT - 1) / WT;

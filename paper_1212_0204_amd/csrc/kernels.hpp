@@ -636,6 +636,22 @@ __global__ __launch_bounds__(TPB) void k_euler(StepArgs<T> a, Geom G, int K) {
         if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6][d2] = m;
       }
       __syncthreads();
+      if (a.GE == 1) {
+        // the whole grid is this block: its maxima are the sub-step's speeds
+        // and the block barrier orders the sub-steps (the same values as
+        // through the arrival counters)
+#pragma unroll
+        for (int d2 = 0; d2 < D; ++d2) {
+          double m = wmax[0][d2];
+          for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, wmax[w][d2]);
+          alpha[d2] = m;
+        }
+        if (threadIdx.x == 0)
+#pragma unroll
+          for (int d2 = 0; d2 < D; ++d2) speed_row(S, i + 1, 0)[d2] = alpha[d2];
+        __syncthreads();
+        continue;
+      }
       if (threadIdx.x < D) {
         double m = wmax[0][threadIdx.x];
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, wmax[w][threadIdx.x]);

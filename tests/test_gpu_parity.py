@@ -406,6 +406,9 @@ def test_gas3d_reduced_grid_fp32(lam):
 @gpu
 @pytest.mark.parametrize("d,n,nv,bc,tau", [
     (1, (130,), 24, (1,), 1e-2),
+    (1, (256,), 16, (0,), 1e-2),   # the largest 1D grid of one tail block
+    (1, (257,), 16, (1,), 1e-2),   # two blocks: arrival counters
+    (1, (700,), 24, (1,), 1e-2),
     (2, (70, 37), 16, (0, 0), 1e-3),
     (2, (48, 40), 16, (1, 1), 5e-3),
     (3, (23, 9, 11), 8, (0, 1, 0), 1e-2),

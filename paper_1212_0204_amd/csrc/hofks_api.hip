@@ -935,10 +935,22 @@ hofks_status zero_ints(hofks_ctx* c, int* p, int n) {
   return HOFKS_OK;
 }
 
+// a sub-step count read back for an earlier step, still in flight, would
+// later replace a newer one: wait for it and drop it
+hofks_status drop_peek(hofks_ctx* c) {
+  if (c->peek_pending) {
+    HIPCHK(c, hipEventSynchronize(c->ev_peek));
+    c->peek_pending = false;
+  }
+  return HOFKS_OK;
+}
+
 hofks_status read_flag(hofks_ctx* c) {
   int h[2] = {0, 0};
   HIPCHK(c, hipMemcpyAsync(h, c->flag, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  hofks_status st = drop_peek(c);
+  if (st) return st;
   if (h[1] > 0) c->s_known = h[1];
   if (h[0] & FLAG_SPIN) {
     fmt_err(c->err, "a bounded wait of the step kernel gave up; results are invalid");
@@ -965,7 +977,11 @@ hofks_status plan_substeps(hofks_ctx* c) {
   const double sv = std::ceil(c->P.G.sfac * c->P.G.dt * sum / c->P.G.dx);
   const int s0 = (sv >= 1.0 && sv < SMAX) ? (int)sv : (sv >= SMAX ? SMAX : 1);
   c->s_cap = std::min(SMAX, std::max(2 * s0, s0 + 8));
+  hofks_status st = drop_peek(c);  // the count of the previous state
+  if (st) return st;
   c->s_known = s0;
+  c->peek_every = PEEK_MIN;
+  c->peek_next = 0;
   return HOFKS_OK;
 }
 
